@@ -1,0 +1,196 @@
+"""FP64 CPU oracle for one-hidden-layer sigmoid MLP training (arxiv 1908.07847).
+
+TEST INFRASTRUCTURE ONLY.  Only `tests/`, `__graft_entry__.smoke()` and the
+CPU-baseline leg of `bench.py` may import this package.  It shares no code
+with the HIP library: the C sources here (`mlp_oracle.c`,
+`mlp_oracle_lowp.c`) are plain float64 loops written from the paper's
+section 2.2 and Equation 1, compiled with gcc into `liboracle.so`.
+
+Every array argument is converted to float64 here (an exact widening of
+float32 inputs), so the oracle sees exactly the values the GPU sees.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRCS = [os.path.join(_HERE, "mlp_oracle.c"), os.path.join(_HERE, "mlp_oracle_lowp.c")]
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (portable x86-64, no FMA contraction)."""
+    if not force and os.path.exists(_SO):
+        return _SO
+    tmp = _SO + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+           "-Wall", "-Wextra", "-o", tmp] + _SRCS + ["-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _SO)
+    return _SO
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_SO):
+        build()
+    lib = ctypes.CDLL(_SO)
+    P = ctypes.POINTER(ctypes.c_double)
+    i64, i32, dbl = ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    lib.ora_forward.argtypes = [i64, i32, i32, i32, P, P, P, P, P, P, P]
+    lib.ora_mse.argtypes = [i64, i32, P, P]
+    lib.ora_mse.restype = dbl
+    lib.ora_backward.argtypes = [i64, i32, i32, i32, P, P, P, P, P, P, P, P, P, P, P]
+    lib.ora_loss_grad.argtypes = [i64, i32, i32, i32, P, P, P, P, P, P, P, P, P, P]
+    lib.ora_loss_grad.restype = dbl
+    lib.ora_train.argtypes = [i64, i32, i32, i32, i64, P, P, P, P, P, P, dbl, i32, P]
+    lib.ora_train_many.argtypes = [i32, ctypes.c_void_p, ctypes.c_void_p, P, ctypes.c_void_p,
+                                   ctypes.c_void_p, i32, i32, P, P, P, i32, P, i32]
+    lib.ora_max_threads.restype = i32
+    lib.ora_round_format.argtypes = [dbl, i32, i32, dbl]
+    lib.ora_round_format.restype = dbl
+    lib.ora_round_bf16.argtypes = [dbl]
+    lib.ora_round_bf16.restype = dbl
+    lib.ora_round_e4m3.argtypes = [dbl]
+    lib.ora_round_e4m3.restype = dbl
+    lib.ora_e4m3_scale_exp.argtypes = [dbl]
+    lib.ora_e4m3_scale_exp.restype = i32
+    lib.ora_train_lowp.argtypes = [i64, i32, i32, i32, i64, P, P, P, P, P, P, dbl, i32, i32, P,
+                                   ctypes.c_void_p]
+    _lib = lib
+    return lib
+
+
+def _d(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Params:
+    """float64 parameters W1 [H][D], b1 [H], W2 [K][H], b2 [K]."""
+
+    def __init__(self, W1, b1, W2, b2):
+        self.W1, self.b1, self.W2, self.b2 = _d(W1).copy(), _d(b1).copy(), _d(W2).copy(), _d(b2).copy()
+
+    @classmethod
+    def of(cls, theta) -> "Params":
+        return cls(theta.W1, theta.b1, theta.W2, theta.b2)
+
+    def copy(self) -> "Params":
+        return Params(self.W1, self.b1, self.W2, self.b2)
+
+    def flat(self) -> np.ndarray:
+        return np.concatenate([self.W1.ravel(), self.b1, self.W2.ravel(), self.b2])
+
+    @property
+    def shape(self):
+        h, d = self.W1.shape
+        return d, h, self.W2.shape[0]
+
+
+def forward(X, p: Params):
+    """Returns (A [n][H], Y [n][K]) -- section 2.2 feed-forward, Equation 1."""
+    X = _d(X)
+    d, h, k = p.shape
+    n = X.shape[0]
+    A = np.zeros((n, h)); Y = np.zeros((n, k))
+    _load().ora_forward(n, d, h, k, _p(X), _p(p.W1), _p(p.b1), _p(p.W2), _p(p.b2), _p(A), _p(Y))
+    return A, Y
+
+
+def mse(Y, T) -> float:
+    Y, T = _d(Y), _d(T)
+    return float(_load().ora_mse(Y.shape[0], Y.shape[1], _p(Y), _p(T)))
+
+
+def backward(X, A, Y, dY, p: Params, want_dx: bool = False):
+    """Backpropagation from dL/dY; returns (gW1, gb1, gW2, gb2[, dX])."""
+    X, A, Y, dY = _d(X), _d(A), _d(Y), _d(dY)
+    d, h, k = p.shape
+    n = X.shape[0]
+    g = Params(np.zeros((h, d)), np.zeros(h), np.zeros((k, h)), np.zeros(k))
+    dX = np.zeros((n, d)) if want_dx else None
+    _load().ora_backward(n, d, h, k, _p(X), _p(A), _p(Y), _p(dY), _p(p.W1), _p(p.W2), _p(g.W1),
+                         _p(g.b1), _p(g.W2), _p(g.b2), _p(dX) if want_dx else None)
+    return (g, dX) if want_dx else g
+
+
+def loss_grad(X, T, p: Params):
+    """(L, gradient Params) of the mean-squared-error reading."""
+    X, T = _d(X), _d(T)
+    d, h, k = p.shape
+    g = Params(np.zeros((h, d)), np.zeros(h), np.zeros((k, h)), np.zeros(k))
+    L = _load().ora_loss_grad(X.shape[0], d, h, k, _p(X), _p(T), _p(p.W1), _p(p.b1), _p(p.W2),
+                              _p(p.b2), _p(g.W1), _p(g.b1), _p(g.W2), _p(g.b2))
+    return float(L), g
+
+
+def train(X, T, p: Params, lr: float, epochs: int, batch: int = 0):
+    """Gradient-descent training; returns (trained Params, loss_hist [epochs])."""
+    X, T = _d(X), _d(T)
+    d, h, k = p.shape
+    q = p.copy()
+    hist = np.zeros(max(epochs, 0))
+    _load().ora_train(X.shape[0], d, h, k, int(batch), _p(X), _p(T), _p(q.W1), _p(q.b1), _p(q.W2),
+                      _p(q.b2), float(lr), int(epochs), _p(hist))
+    return q, hist
+
+
+def train_many(items, X, T, theta_packed, d: int, k: int, epochs: int, threads: int = 0):
+    """Independent full-batch nets in the packed layout; returns (theta, loss_hist)."""
+    X, T = _d(X), _d(T)
+    th = _d(theta_packed).copy()
+    n = len(items)
+    nr = np.array([it["n_rows"] for it in items], dtype=np.int32)
+    nh = np.array([it["n_hidden"] for it in items], dtype=np.int32)
+    lr = np.array([float(it["lr"]) for it in items], dtype=np.float64)
+    xo = np.array([it["x_off"] for it in items], dtype=np.int64)
+    po = np.array([it["p_off"] for it in items], dtype=np.int64)
+    hist = np.zeros((n, max(epochs, 0)))
+    _load().ora_train_many(n, nr.ctypes.data, nh.ctypes.data, _p(lr), xo.ctypes.data, po.ctypes.data,
+                           d, k, _p(X), _p(T), _p(th), int(epochs), _p(hist), int(threads))
+    return th, hist
+
+
+def max_threads() -> int:
+    return int(_load().ora_max_threads())
+
+
+def round_bf16(v: float) -> float:
+    return float(_load().ora_round_bf16(float(v)))
+
+
+def round_e4m3(v: float) -> float:
+    return float(_load().ora_round_e4m3(float(v)))
+
+
+def e4m3_scale_exp(amax: float) -> int:
+    return int(_load().ora_e4m3_scale_exp(float(amax)))
+
+
+PREC = {"fp32": 0, "bf16": 1, "e4m3": 2}
+
+
+def train_lowp(X, T, p: Params, lr: float, epochs: int, batch: int, prec: str):
+    """Training with rounded contraction operands; returns (Params, loss_hist, scale_log)."""
+    X, T = _d(X), _d(T)
+    d, h, k = p.shape
+    q = p.copy()
+    n = X.shape[0]
+    b = n if batch <= 0 or batch > n else batch
+    steps = -(-n // b) * epochs
+    hist = np.zeros(max(epochs, 0))
+    slog = np.zeros((steps, 3), dtype=np.int32)
+    _load().ora_train_lowp(n, d, h, k, int(batch), _p(X), _p(T), _p(q.W1), _p(q.b1), _p(q.W2),
+                           _p(q.b2), float(lr), int(epochs), PREC[prec], _p(hist), slog.ctypes.data)
+    return q, hist, slog
