@@ -1,0 +1,168 @@
+/*
+ * mlp.h -- C ABI of libmlp: one-hidden-layer sigmoid MLP training on gfx950.
+ *
+ * The method (arxiv 1908.07847, section 2.2): a fully connected feed-forward
+ * network with one hidden layer, the logistic sigmoid of Equation 1 at both
+ * layers, trained by gradient descent through backpropagation with a fixed
+ * learning rate and no momentum.  Data and weights are flat float arrays;
+ * the input-to-hidden weights hold (hidden neurons x columns) entries.
+ *
+ *   forward:   A = sigma(X W1^T + b1),  Y = sigma(A W2^T + b2)
+ *   error:     L = sum (Y - T)^2 / (m K)     (mean over rows and outputs)
+ *   backward:  delta2 = dL/dY . Y(1-Y);  delta1 = (delta2 W2) . A(1-A)
+ *              gW2 = delta2^T A, gb2 = sum delta2, gW1 = delta1^T X,
+ *              gb1 = sum delta1  (delta1 uses the pre-update W2)
+ *   update:    theta <- theta - lr * g   (all four at once)
+ *
+ * Conventions for every function:
+ *   - Arrays are float32, row-major: X[n][D], T[n][K], A[n][H], Y[n][K],
+ *     W1[H][D], b1[H], W2[K][H], b2[K].  "Packed" parameters are
+ *     [W1 | b1 | W2 | b2] back to back (P = D*H + H + H*K + K floats).
+ *   - Every array argument is a DEVICE pointer unless marked "host".  The
+ *     caller allocates every device buffer (inputs, outputs, parameters,
+ *     compensation, workspace) and keeps it alive until the stream has run
+ *     the work; the library never allocates or frees device memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL: the null stream).
+ *     All device work is enqueued on it and is asynchronous: execution
+ *     errors surface at the caller's next synchronisation.
+ *   - Every function returns an mlp_status and never aborts.  Argument,
+ *     shape and alignment checks happen before any HIP call, so a rejected
+ *     call leaves no work on the stream.  mlp_last_error() gives a
+ *     thread-local message for the last failure.
+ *   - Device pointers must be 4-byte aligned; X, T, the workspace and the
+ *     batched item table must be 16-byte aligned.
+ *   - NaN/Inf in inputs propagate; nothing checks for them on the hot path.
+ */
+#ifndef MLP_H_
+#define MLP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MLP_OK = 0,
+  MLP_ERR_ARG = 1,         /* NULL pointer, non-positive size, bad flag */
+  MLP_ERR_SHAPE = 2,       /* sizes outside what the kernels support */
+  MLP_ERR_ALIGN = 3,       /* device pointer not 16-byte aligned */
+  MLP_ERR_WORKSPACE = 4,   /* workspace missing or too small */
+  MLP_ERR_UNSUPPORTED = 5, /* valid request no kernel here implements */
+  MLP_ERR_HIP = 6          /* the HIP runtime reported an error */
+} mlp_status;
+
+/* Operand precision of the two large contractions (X W1^T and delta1^T X).
+ * Master parameters, biases, sigmoid, the output layer, the loss and the
+ * update are float32 in every precision.  Reduced precisions are the
+ * build's own extension (the paper trains in float). */
+typedef enum { MLP_FP32 = 0, MLP_BF16 = 1, MLP_FP8_E4M3 = 2 } mlp_precision;
+
+/* Flags. */
+enum {
+  /* Compensated (Kahan) float32 parameter update, using the caller's
+   * compensation buffer.  Same update, computed more exactly. */
+  MLP_F_COMPENSATED = 1u
+};
+
+typedef struct {
+  int32_t n_in;     /* D, features per row                         */
+  int32_t n_hidden; /* H, hidden neurons                           */
+  int32_t n_out;    /* K, output neurons                           */
+  int32_t prec;     /* mlp_precision                               */
+  int64_t n_rows;   /* N, rows of the training set                 */
+  int64_t batch;    /* rows per gradient step; 0 or >= N: full batch */
+  float lr;         /* learning rate (section 2.2 uses 0.1)        */
+  uint32_t flags;   /* MLP_F_*                                     */
+} mlp_config;
+
+typedef struct {
+  float *W1, *b1, *W2, *b2; /* device, W1[H][D] b1[H] W2[K][H] b2[K] */
+} mlp_params;
+
+typedef struct mlp_net mlp_net; /* opaque host handle; owns no device memory */
+
+/* Bytes of device workspace that mlp_init must be given for this
+ * configuration (host out).  Pure host computation. */
+mlp_status mlp_workspace_size(const mlp_config *cfg /*host*/, size_t *bytes /*host out*/);
+
+/* Create a handle bound to caller-owned parameters (updated in place by
+ * mlp_step / mlp_train), an optional compensation buffer comp[P] (packed
+ * order; required when MLP_F_COMPENSATED is set; zero it before the first
+ * training call) and a workspace of at least mlp_workspace_size bytes.
+ * Queries the current device once.  One handle per stream; not
+ * thread-safe. */
+mlp_status mlp_init(mlp_net **out /*host out*/, const mlp_config *cfg /*host*/, mlp_params theta,
+                    float *comp, void *workspace, size_t ws_bytes);
+
+/* Release the handle (host memory only). */
+mlp_status mlp_destroy(mlp_net *net);
+
+/* Feed-forward pass over n rows (section 2.2, Equation 1):
+ * A[n][H] (may be NULL) and Y[n][K] are overwritten.  Any n >= 1. */
+mlp_status mlp_forward(mlp_net *net, const float *X, int64_t n, float *A, float *Y, void *stream);
+
+/* Backpropagation over n rows, from the A and Y of mlp_forward at the
+ * current parameters.  dY[n][K] is the upstream gradient dL/dY; when dY is
+ * NULL the mean-squared-error reading is used against T[n][K]
+ * (dL/dY = 2 (Y - T) / (n K)) and, if loss is non-NULL, loss[0] receives
+ * L.  grads (device, same shapes as the parameters) are overwritten with
+ * the parameter gradients; dX[n][D] (may be NULL) receives delta1 W1.
+ * Row sums are reduced in a fixed order: repeated calls are bitwise equal. */
+mlp_status mlp_backward(mlp_net *net, const float *X, const float *A, const float *Y,
+                        const float *dY, const float *T, int64_t n, mlp_params grads, float *dX,
+                        float *loss, void *stream);
+
+/* theta <- theta - lr * grads (section 2.2: fixed rate, no momentum),
+ * compensated when the handle was created with MLP_F_COMPENSATED. */
+mlp_status mlp_step(mlp_net *net, mlp_params grads, float lr, void *stream);
+
+/* Train for `epochs` epochs on X[N][D], T[N][K]: per epoch, ceil(N/batch)
+ * contiguous minibatches in stored order, each a forward pass, the MSE
+ * error, backpropagation and an update.  loss_hist[epochs] (may be NULL)
+ * receives, per epoch, the mean over its minibatches of the minibatch loss
+ * at the pre-update parameters.  With the compensation buffer, training a
+ * then b epochs is bitwise equal to training a+b epochs. */
+mlp_status mlp_train(mlp_net *net, const float *X, const float *T, int32_t epochs,
+                     float *loss_hist, void *stream);
+
+/* ---- many independent small networks in one launch ---------------------- */
+
+typedef struct {
+  int32_t n_rows;   /* N_i: rows of net i (full batch)                     */
+  int32_t n_hidden; /* H_i                                                  */
+  float lr;         /* lr_i                                                 */
+  int32_t reserved; /* must be 0                                            */
+  int64_t x_off;    /* first row of net i in X_packed and T_packed          */
+  int64_t p_off;    /* first float of net i's [W1|b1|W2|b2] in theta_packed */
+} mlp_batch_item;   /* 32 bytes */
+
+/* Limits of the batched (and small full-batch) trainer. */
+#define MLP_SMALL_MAX_ROWS 128
+#define MLP_SMALL_MAX_HIDDEN 64
+#define MLP_SMALL_MAX_IN 48
+#define MLP_SMALL_MAX_OUT 4
+
+/* Train n_nets independent networks, each full batch on its own rows, for
+ * `epochs` epochs, in one kernel launch (capturable in a hipGraph).  The
+ * item table is given twice with identical contents: items_host (host) is
+ * validated and drives the launch, items_dev (device) is read by the
+ * kernel.  Nets are started in table order, so listing them by decreasing
+ * N_i*H_i gives a longest-first schedule.  theta_packed and comp_packed
+ * (may be NULL: plain update) are updated in place; loss_hist
+ * [n_nets][epochs] (may be NULL) is indexed by table position.  Every net's
+ * result is independent of the others and of the table order. */
+mlp_status mlp_train_batched(const mlp_batch_item *items_host, const mlp_batch_item *items_dev,
+                             int32_t n_nets, int32_t n_in, int32_t n_out, const float *X_packed,
+                             const float *T_packed, int64_t total_rows, float *theta_packed,
+                             float *comp_packed, int64_t total_params, int32_t epochs,
+                             float *loss_hist, void *stream);
+
+const char *mlp_status_string(mlp_status s);
+const char *mlp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MLP_H_ */

@@ -1,0 +1,160 @@
+// Separate forward / backward / update kernels (arxiv 1908.07847,
+// section 2.2), for callers that drive the steps themselves -- e.g. a
+// torch.autograd.Function whose backward is this hand-written adjoint.
+//
+//  k_forward       one thread per row: z1 = X W1^T + b1, A = sigma(z1),
+//                  Y = sigma(A W2^T + b2).  W1/W2 reads are uniform across
+//                  the wave (broadcast); each thread streams its own row.
+//  k_backward_rows one thread per row: delta2 = dY . Y (1 - Y) (dY from the
+//                  caller, or the MSE reading 2 (Y - T) / (n K)),
+//                  delta1 = (delta2 W2) . A (1 - A); optional dX = delta1 W1;
+//                  writes delta1, delta2 and the row's squared error.
+//  k_backward_sum  one thread per parameter (plus one for the loss): sums
+//                  its gradient over all rows in row order, so the result
+//                  is bitwise repeatable.
+//  k_step          theta <- theta - lr g, optionally Kahan-compensated.
+#include "mlp_device.hpp"
+
+namespace mlpk {
+
+__global__ __launch_bounds__(256) void k_forward(int64_t n, int D, int H, int K,
+                                                 const float *__restrict__ X, mlp_params p,
+                                                 float *__restrict__ A, float *__restrict__ Y) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const float *x = X + r * D;
+  float z2[kLayerMaxOut];
+  for (int k = 0; k < K && k < kLayerMaxOut; ++k) z2[k] = p.b2[k];
+  for (int h = 0; h < H; ++h) {
+    const float *w = p.W1 + (int64_t)h * D;
+    float z = p.b1[h];
+    for (int d = 0; d < D; ++d) z += x[d] * w[d];
+    float a = sigmoid(z);
+    if (A) A[r * H + h] = a;
+    for (int k = 0; k < K && k < kLayerMaxOut; ++k) z2[k] += a * p.W2[(int64_t)k * H + h];
+  }
+  for (int k = 0; k < K && k < kLayerMaxOut; ++k) Y[r * K + k] = sigmoid(z2[k]);
+}
+
+__global__ __launch_bounds__(256) void k_backward_rows(
+    int64_t n, int D, int H, int K, const float *__restrict__ A, const float *__restrict__ Y,
+    const float *__restrict__ dY, const float *__restrict__ T, mlp_params p,
+    float *__restrict__ dX, float *__restrict__ d1_out, float *__restrict__ d2_out,
+    float *__restrict__ sq_out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const float mse_scale = 2.0f / ((float)n * (float)K);
+  float sq = 0.0f;
+  for (int k = 0; k < K; ++k) {
+    float y = Y[r * K + k];
+    float g;
+    if (dY) {
+      g = dY[r * K + k];
+    } else {
+      float err = y - T[r * K + k];
+      sq += err * err;
+      g = mse_scale * err;
+    }
+    d2_out[r * K + k] = g * y * (1.0f - y);
+  }
+  sq_out[r] = sq;
+  for (int h = 0; h < H; ++h) {
+    float s = 0.0f;
+    for (int k = 0; k < K; ++k) s += d2_out[r * K + k] * p.W2[(int64_t)k * H + h];
+    float a = A[r * H + h];
+    d1_out[r * H + h] = s * a * (1.0f - a);
+  }
+  if (dX) {
+    for (int d = 0; d < D; ++d) {
+      float s = 0.0f;
+      for (int h = 0; h < H; ++h) s += d1_out[r * H + h] * p.W1[(int64_t)h * D + d];
+      dX[r * D + d] = s;
+    }
+  }
+}
+
+// Parameter index q in packed order [W1 | b1 | W2 | b2], plus q == P for the loss.
+__global__ __launch_bounds__(256) void k_backward_sum(
+    int64_t n, int D, int H, int K, const float *__restrict__ X, const float *__restrict__ A,
+    const float *__restrict__ d1, const float *__restrict__ d2, const float *__restrict__ sq,
+    mlp_params g, float *__restrict__ loss) {
+  const int64_t P = (int64_t)D * H + H + (int64_t)H * K + K;
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q > P) return;
+  float s = 0.0f;
+  if (q < (int64_t)D * H) {
+    const int h = (int)(q / D), d = (int)(q - (int64_t)h * D);
+    for (int64_t r = 0; r < n; ++r) s += d1[r * H + h] * X[r * D + d];
+    g.W1[q] = s;
+  } else if (q < (int64_t)D * H + H) {
+    const int h = (int)(q - (int64_t)D * H);
+    for (int64_t r = 0; r < n; ++r) s += d1[r * H + h];
+    g.b1[h] = s;
+  } else if (q < (int64_t)D * H + H + (int64_t)H * K) {
+    const int64_t o = q - ((int64_t)D * H + H);
+    const int k = (int)(o / H), h = (int)(o - (int64_t)k * H);
+    for (int64_t r = 0; r < n; ++r) s += d2[r * K + k] * A[r * H + h];
+    g.W2[o] = s;
+  } else if (q < P) {
+    const int k = (int)(q - ((int64_t)D * H + H + (int64_t)H * K));
+    for (int64_t r = 0; r < n; ++r) s += d2[r * K + k];
+    g.b2[k] = s;
+  } else if (loss) {
+    for (int64_t r = 0; r < n; ++r) s += sq[r];
+    loss[0] = s / ((float)n * (float)K);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_step(int D, int H, int K, mlp_params p, mlp_params g,
+                                              float *__restrict__ comp, float lr) {
+  const int64_t P = (int64_t)D * H + H + (int64_t)H * K + K;
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= P) return;
+  float *w;
+  const float *gr;
+  const int64_t oB1 = (int64_t)D * H, oW2 = oB1 + H, oB2 = oW2 + (int64_t)H * K;
+  if (q < oB1) { w = p.W1 + q; gr = g.W1 + q; }
+  else if (q < oW2) { w = p.b1 + (q - oB1); gr = g.b1 + (q - oB1); }
+  else if (q < oB2) { w = p.W2 + (q - oW2); gr = g.W2 + (q - oW2); }
+  else { w = p.b2 + (q - oB2); gr = g.b2 + (q - oB2); }
+  float wv = *w, c = comp ? comp[q] : 0.0f;
+  gd_update(wv, c, lr, *gr, comp != nullptr);
+  *w = wv;
+  if (comp) comp[q] = c;
+}
+
+}  // namespace mlpk
+
+namespace mlph {
+
+static dim3 grid_for(int64_t n, int b) { return dim3((unsigned)((n + b - 1) / b)); }
+
+hipError_t launch_forward(int64_t n, int D, int H, int K, const float *X, mlp_params p, float *A,
+                          float *Y, hipStream_t s) {
+  hipLaunchKernelGGL(mlpk::k_forward, grid_for(n, 256), dim3(256), 0, s, n, D, H, K, X, p, A, Y);
+  return hipGetLastError();
+}
+
+// ws layout (floats): delta1 [n][H] | delta2 [n][K] | sq [n]
+hipError_t launch_backward(int64_t n, int D, int H, int K, const float *X, const float *A,
+                           const float *Y, const float *dY, const float *T, mlp_params p,
+                           mlp_params g, float *dX, float *loss, float *ws, hipStream_t s) {
+  float *d1 = ws, *d2 = ws + n * H, *sq = d2 + n * K;
+  hipLaunchKernelGGL(mlpk::k_backward_rows, grid_for(n, 256), dim3(256), 0, s, n, D, H, K, A, Y,
+                     dY, T, p, dX, d1, d2, sq);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t P = (int64_t)D * H + H + (int64_t)H * K + K;
+  hipLaunchKernelGGL(mlpk::k_backward_sum, grid_for(P + 1, 256), dim3(256), 0, s, n, D, H, K, X,
+                     A, d1, d2, sq, g, dY ? nullptr : loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_step(int D, int H, int K, mlp_params p, mlp_params g, float *comp, float lr,
+                       hipStream_t s) {
+  const int64_t P = (int64_t)D * H + H + (int64_t)H * K + K;
+  hipLaunchKernelGGL(mlpk::k_step, grid_for(P, 256), dim3(256), 0, s, D, H, K, p, g, comp, lr);
+  return hipGetLastError();
+}
+
+}  // namespace mlph

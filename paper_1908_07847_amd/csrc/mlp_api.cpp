@@ -1,0 +1,283 @@
+// Host side of libmlp: argument validation, workspace sizing and dispatch
+// to the HIP kernels.  Validation never calls HIP, so a rejected call
+// leaves nothing on the stream and can be tested without a GPU.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "mlp.h"
+#include "mlp_device.hpp"
+#include "mlp_large.hpp"
+
+struct mlp_net {
+  mlp_config cfg;
+  mlp_params theta;
+  float *comp;
+  void *ws;
+  size_t ws_bytes;
+  int device;
+  int n_cu;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+mlp_status fail(mlp_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+mlp_status hip_fail(hipError_t e, const char *where) {
+  return fail(MLP_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+bool aligned4(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
+
+int64_t n_params(int64_t D, int64_t H, int64_t K) { return D * H + H + H * K + K; }
+
+mlp_status check_config(const mlp_config *c) {
+  if (!c) return fail(MLP_ERR_ARG, "config is NULL");
+  if (c->n_in <= 0 || c->n_hidden <= 0 || c->n_out <= 0 || c->n_rows <= 0)
+    return fail(MLP_ERR_SHAPE, "n_in, n_hidden, n_out and n_rows must be positive (got %d, %d, %d, %lld)",
+                c->n_in, c->n_hidden, c->n_out, (long long)c->n_rows);
+  if (c->batch < 0) return fail(MLP_ERR_SHAPE, "batch must be >= 0");
+  if (c->n_out > mlpk::kLayerMaxOut)
+    return fail(MLP_ERR_SHAPE, "n_out %d above the supported %d", c->n_out, mlpk::kLayerMaxOut);
+  if (c->n_in > (1 << 20) || c->n_hidden > (1 << 20))
+    return fail(MLP_ERR_SHAPE, "n_in / n_hidden above 2^20");
+  if (c->prec != MLP_FP32 && c->prec != MLP_BF16 && c->prec != MLP_FP8_E4M3)
+    return fail(MLP_ERR_ARG, "unknown precision %d", c->prec);
+  if (c->flags & ~(uint32_t)MLP_F_COMPENSATED) return fail(MLP_ERR_ARG, "unknown flag bits 0x%x", c->flags);
+  if (!(c->lr >= 0.0f) || c->lr > 1e6f) return fail(MLP_ERR_ARG, "lr must be finite and >= 0");
+  return MLP_OK;
+}
+
+mlp_status check_params(mlp_params p, const char *what) {
+  if (!p.W1 || !p.b1 || !p.W2 || !p.b2) return fail(MLP_ERR_ARG, "%s: a parameter pointer is NULL", what);
+  if (!aligned4(p.W1) || !aligned4(p.b1) || !aligned4(p.W2) || !aligned4(p.b2))
+    return fail(MLP_ERR_ALIGN, "%s: parameter pointers must be 4-byte aligned", what);
+  return MLP_OK;
+}
+
+int64_t eff_batch(const mlp_config &c) { return (c.batch <= 0 || c.batch >= c.n_rows) ? c.n_rows : c.batch; }
+
+bool small_path(const mlp_config &c) {
+  return c.prec == MLP_FP32 && eff_batch(c) == c.n_rows && c.n_rows <= MLP_SMALL_MAX_ROWS &&
+         c.n_hidden <= MLP_SMALL_MAX_HIDDEN && c.n_in <= MLP_SMALL_MAX_IN &&
+         c.n_out <= MLP_SMALL_MAX_OUT;
+}
+
+size_t backward_ws_bytes(const mlp_config &c) {
+  return sizeof(float) * (size_t)c.n_rows * (size_t)(c.n_hidden + c.n_out + 1);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mlp_status_string(mlp_status s) {
+  switch (s) {
+    case MLP_OK: return "ok";
+    case MLP_ERR_ARG: return "invalid argument";
+    case MLP_ERR_SHAPE: return "unsupported or inconsistent shape";
+    case MLP_ERR_ALIGN: return "misaligned device pointer";
+    case MLP_ERR_WORKSPACE: return "workspace missing or too small";
+    case MLP_ERR_UNSUPPORTED: return "unsupported request";
+    case MLP_ERR_HIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+const char *mlp_last_error(void) { return g_last_error.c_str(); }
+
+mlp_status mlp_workspace_size(const mlp_config *cfg, size_t *bytes) {
+  mlp_status s = check_config(cfg);
+  if (s != MLP_OK) return s;
+  if (!bytes) return fail(MLP_ERR_ARG, "bytes is NULL");
+  size_t need = backward_ws_bytes(*cfg);
+  if (!small_path(*cfg)) {
+    size_t lw = 0;
+    s = mlph::large_workspace_bytes(*cfg, &lw);
+    if (s != MLP_OK && s != MLP_ERR_UNSUPPORTED) return s;
+    if (s == MLP_OK) need = std::max(need, lw);
+  }
+  *bytes = (need + 255) / 256 * 256;
+  return MLP_OK;
+}
+
+mlp_status mlp_init(mlp_net **out, const mlp_config *cfg, mlp_params theta, float *comp,
+                    void *workspace, size_t ws_bytes) {
+  if (!out) return fail(MLP_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  mlp_status s = check_config(cfg);
+  if (s != MLP_OK) return s;
+  if ((s = check_params(theta, "theta")) != MLP_OK) return s;
+  if ((cfg->flags & MLP_F_COMPENSATED) && !comp)
+    return fail(MLP_ERR_ARG, "MLP_F_COMPENSATED needs a compensation buffer");
+  if (comp && !aligned4(comp)) return fail(MLP_ERR_ALIGN, "comp must be 4-byte aligned");
+  size_t need = 0;
+  mlp_workspace_size(cfg, &need);
+  if (ws_bytes < need || (need > 0 && !workspace))
+    return fail(MLP_ERR_WORKSPACE, "workspace of %zu bytes given, %zu needed", ws_bytes, need);
+  if (workspace && !aligned16(workspace)) return fail(MLP_ERR_ALIGN, "workspace must be 16-byte aligned");
+  int dev = 0, ncu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+  mlp_net *n = new (std::nothrow) mlp_net;
+  if (!n) return fail(MLP_ERR_ARG, "out of host memory");
+  n->cfg = *cfg;
+  n->theta = theta;
+  n->comp = (cfg->flags & MLP_F_COMPENSATED) ? comp : nullptr;
+  n->ws = workspace;
+  n->ws_bytes = ws_bytes;
+  n->device = dev;
+  n->n_cu = ncu;
+  *out = n;
+  return MLP_OK;
+}
+
+mlp_status mlp_destroy(mlp_net *net) {
+  if (!net) return fail(MLP_ERR_ARG, "net is NULL");
+  delete net;
+  return MLP_OK;
+}
+
+mlp_status mlp_forward(mlp_net *net, const float *X, int64_t n, float *A, float *Y, void *stream) {
+  if (!net) return fail(MLP_ERR_ARG, "net is NULL");
+  if (!X || !Y) return fail(MLP_ERR_ARG, "X and Y must not be NULL");
+  if (n <= 0) return fail(MLP_ERR_SHAPE, "n must be positive");
+  if (!aligned16(X) || !aligned4(Y) || (A && !aligned4(A)))
+    return fail(MLP_ERR_ALIGN, "X must be 16-byte and A, Y 4-byte aligned");
+  const mlp_config &c = net->cfg;
+  hipError_t e = mlph::launch_forward(n, c.n_in, c.n_hidden, c.n_out, X, net->theta, A, Y,
+                                      (hipStream_t)stream);
+  return e == hipSuccess ? MLP_OK : hip_fail(e, "mlp_forward launch");
+}
+
+mlp_status mlp_backward(mlp_net *net, const float *X, const float *A, const float *Y,
+                        const float *dY, const float *T, int64_t n, mlp_params grads, float *dX,
+                        float *loss, void *stream) {
+  if (!net) return fail(MLP_ERR_ARG, "net is NULL");
+  if (!X || !A || !Y) return fail(MLP_ERR_ARG, "X, A and Y must not be NULL");
+  if (!dY && !T) return fail(MLP_ERR_ARG, "either dY or T must be given");
+  if (n <= 0) return fail(MLP_ERR_SHAPE, "n must be positive");
+  const mlp_config &c = net->cfg;
+  if (n > c.n_rows)
+    return fail(MLP_ERR_SHAPE, "n = %lld rows exceeds the n_rows = %lld the workspace was sized for",
+                (long long)n, (long long)c.n_rows);
+  mlp_status s = check_params(grads, "grads");
+  if (s != MLP_OK) return s;
+  const void *ptrs[] = {A, Y, dY, T, dX, loss};
+  for (const void *p : ptrs)
+    if (p && !aligned4(p)) return fail(MLP_ERR_ALIGN, "device pointers must be 4-byte aligned");
+  if (!aligned16(X)) return fail(MLP_ERR_ALIGN, "X must be 16-byte aligned");
+  if (!net->ws || net->ws_bytes < backward_ws_bytes(c))
+    return fail(MLP_ERR_WORKSPACE, "backward needs %zu workspace bytes", backward_ws_bytes(c));
+  hipError_t e = mlph::launch_backward(n, c.n_in, c.n_hidden, c.n_out, X, A, Y, dY, T, net->theta,
+                                       grads, dX, loss, (float *)net->ws, (hipStream_t)stream);
+  return e == hipSuccess ? MLP_OK : hip_fail(e, "mlp_backward launch");
+}
+
+mlp_status mlp_step(mlp_net *net, mlp_params grads, float lr, void *stream) {
+  if (!net) return fail(MLP_ERR_ARG, "net is NULL");
+  mlp_status s = check_params(grads, "grads");
+  if (s != MLP_OK) return s;
+  if (!(lr >= 0.0f) || lr > 1e6f) return fail(MLP_ERR_ARG, "lr must be finite and >= 0");
+  const mlp_config &c = net->cfg;
+  hipError_t e = mlph::launch_step(c.n_in, c.n_hidden, c.n_out, net->theta, grads, net->comp, lr,
+                                   (hipStream_t)stream);
+  return e == hipSuccess ? MLP_OK : hip_fail(e, "mlp_step launch");
+}
+
+mlp_status mlp_train(mlp_net *net, const float *X, const float *T, int32_t epochs,
+                     float *loss_hist, void *stream) {
+  if (!net) return fail(MLP_ERR_ARG, "net is NULL");
+  if (!X || !T) return fail(MLP_ERR_ARG, "X and T must not be NULL");
+  if (epochs < 0) return fail(MLP_ERR_ARG, "epochs must be >= 0");
+  if (!aligned16(X) || !aligned16(T) || (loss_hist && !aligned4(loss_hist)))
+    return fail(MLP_ERR_ALIGN, "X and T must be 16-byte and loss_hist 4-byte aligned");
+  if (epochs == 0) return MLP_OK;
+  const mlp_config &c = net->cfg;
+  const mlp_params &p = net->theta;
+  if (small_path(c)) {
+    // The small trainer reads the parameters packed; a single net whose
+    // four arrays are laid out back to back is trained in place, any other
+    // layout is rejected rather than silently copied.
+    const int64_t D = c.n_in, H = c.n_hidden, K = c.n_out;
+    if (p.b1 != p.W1 + D * H || p.W2 != p.b1 + H || p.b2 != p.W2 + H * K)
+      return fail(MLP_ERR_UNSUPPORTED,
+                  "full-batch small training needs W1, b1, W2, b2 contiguous in packed order");
+    mlp_batch_item one{};
+    one.n_rows = (int32_t)c.n_rows;
+    one.n_hidden = (int32_t)H;
+    one.lr = c.lr;
+    one.x_off = 0;
+    one.p_off = 0;
+    hipError_t e = mlph::launch_small_train(nullptr, one, 1, (int)D, (int)K, (int)c.n_rows, (int)H,
+                                            X, T, p.W1, net->comp, epochs, loss_hist,
+                                            (hipStream_t)stream);
+    return e == hipSuccess ? MLP_OK : hip_fail(e, "mlp_train (small) launch");
+  }
+  return mlph::large_train(net->cfg, net->theta, net->comp, net->ws, net->ws_bytes, net->n_cu, X, T,
+                           epochs, loss_hist, (hipStream_t)stream, &g_last_error);
+}
+
+mlp_status mlp_train_batched(const mlp_batch_item *items_host, const mlp_batch_item *items_dev,
+                             int32_t n_nets, int32_t n_in, int32_t n_out, const float *X_packed,
+                             const float *T_packed, int64_t total_rows, float *theta_packed,
+                             float *comp_packed, int64_t total_params, int32_t epochs,
+                             float *loss_hist, void *stream) {
+  if (!items_host || !items_dev) return fail(MLP_ERR_ARG, "item tables must not be NULL");
+  if (n_nets <= 0) return fail(MLP_ERR_SHAPE, "n_nets must be positive");
+  if (n_in <= 0 || n_in > MLP_SMALL_MAX_IN || n_out <= 0 || n_out > MLP_SMALL_MAX_OUT)
+    return fail(MLP_ERR_SHAPE, "n_in must be in [1,%d] and n_out in [1,%d]", MLP_SMALL_MAX_IN,
+                MLP_SMALL_MAX_OUT);
+  if (!X_packed || !T_packed || !theta_packed) return fail(MLP_ERR_ARG, "X, T, theta must not be NULL");
+  if (epochs < 0) return fail(MLP_ERR_ARG, "epochs must be >= 0");
+  const void *ptrs[] = {items_dev, X_packed, T_packed};
+  for (const void *p : ptrs)
+    if (p && !aligned16(p)) return fail(MLP_ERR_ALIGN, "items, X and T must be 16-byte aligned");
+  const void *ptrs4[] = {theta_packed, comp_packed, loss_hist};
+  for (const void *p : ptrs4)
+    if (p && !aligned4(p)) return fail(MLP_ERR_ALIGN, "theta, comp, loss_hist must be 4-byte aligned");
+  int max_rows = 0, max_h = 0;
+  for (int32_t i = 0; i < n_nets; ++i) {
+    const mlp_batch_item &it = items_host[i];
+    if (it.n_rows <= 0 || it.n_rows > MLP_SMALL_MAX_ROWS || it.n_hidden <= 0 ||
+        it.n_hidden > MLP_SMALL_MAX_HIDDEN)
+      return fail(MLP_ERR_SHAPE, "net %d: n_rows %d / n_hidden %d outside [1,%d] / [1,%d]", i,
+                  it.n_rows, it.n_hidden, MLP_SMALL_MAX_ROWS, MLP_SMALL_MAX_HIDDEN);
+    if (it.reserved != 0) return fail(MLP_ERR_ARG, "net %d: reserved field must be 0", i);
+    if (!(it.lr >= 0.0f) || it.lr > 1e6f) return fail(MLP_ERR_ARG, "net %d: bad lr", i);
+    if (it.x_off < 0 || it.x_off + it.n_rows > total_rows)
+      return fail(MLP_ERR_SHAPE, "net %d: rows [%lld, %lld) outside the %lld packed rows", i,
+                  (long long)it.x_off, (long long)(it.x_off + it.n_rows), (long long)total_rows);
+    if (it.p_off < 0 || it.p_off + n_params(n_in, it.n_hidden, n_out) > total_params)
+      return fail(MLP_ERR_SHAPE, "net %d: parameters outside the %lld packed floats", i,
+                  (long long)total_params);
+    max_rows = std::max(max_rows, it.n_rows);
+    max_h = std::max(max_h, it.n_hidden);
+  }
+  if (epochs == 0) return MLP_OK;
+  mlp_batch_item none{};
+  hipError_t e = mlph::launch_small_train(items_dev, none, n_nets, n_in, n_out, max_rows, max_h,
+                                          X_packed, T_packed, theta_packed, comp_packed, epochs,
+                                          loss_hist, (hipStream_t)stream);
+  return e == hipSuccess ? MLP_OK : hip_fail(e, "mlp_train_batched launch");
+}
+
+}  // extern "C"

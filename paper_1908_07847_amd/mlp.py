@@ -1,0 +1,211 @@
+"""PyTorch-facing wrapper of libmlp.
+
+PyTorch provides device memory and the stream; the arithmetic of every
+step -- forward, error, backpropagation, update -- runs in libmlp's HIP
+kernels (arxiv 1908.07847, section 2.2).  Nothing here computes on the
+host beyond argument marshalling.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import BatchItem, Config, Params, check, lib
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def n_params(d: int, h: int, k: int) -> int:
+    return d * h + h + h * k + k
+
+
+def split_packed(flat: torch.Tensor, d: int, h: int, k: int):
+    """Views W1 [H][D], b1 [H], W2 [K][H], b2 [K] of a packed [P] tensor."""
+    o = 0
+    W1 = flat[o:o + h * d].view(h, d); o += h * d
+    b1 = flat[o:o + h]; o += h
+    W2 = flat[o:o + k * h].view(k, h); o += k * h
+    b2 = flat[o:o + k]
+    return W1, b1, W2, b2
+
+
+def _aligned_empty(n: int, device) -> torch.Tensor:
+    # torch's caching allocator returns 256-byte aligned blocks; keep sizes >= 1
+    return torch.empty(max(n, 4), dtype=torch.float32, device=device)[:n]
+
+
+@dataclass
+class Grads:
+    W1: torch.Tensor
+    b1: torch.Tensor
+    W2: torch.Tensor
+    b2: torch.Tensor
+    flat: torch.Tensor
+
+    def c(self) -> Params:
+        return Params(self.W1.data_ptr(), self.b1.data_ptr(), self.W2.data_ptr(), self.b2.data_ptr())
+
+
+class Net:
+    """One network bound to device parameters, a compensation buffer and a workspace.
+
+    The four parameter tensors are views of one packed float32 buffer
+    (`self.flat`, order [W1 | b1 | W2 | b2]).
+    """
+
+    def __init__(self, n_in: int, n_hidden: int, n_out: int, n_rows: int, *, batch: int = 0,
+                 lr: float = 0.1, prec: str = "fp32", compensated: bool = True, theta=None,
+                 device="cuda"):
+        self.D, self.H, self.K = int(n_in), int(n_hidden), int(n_out)
+        self.n_rows, self.batch, self.lr, self.prec = int(n_rows), int(batch), float(lr), prec
+        self.device = torch.device(device)
+        P = n_params(self.D, self.H, self.K)
+        self.flat = _aligned_empty(P, self.device)
+        if theta is not None:
+            self.flat.copy_(torch.as_tensor(np.asarray(theta_packed(theta), dtype=np.float32)))
+        else:
+            self.flat.zero_()
+        self.W1, self.b1, self.W2, self.b2 = split_packed(self.flat, self.D, self.H, self.K)
+        self.comp = torch.zeros(max(P, 4), dtype=torch.float32, device=self.device)[:P] if compensated else None
+        self.cfg = Config(self.D, self.H, self.K, _lib.PREC[prec], self.n_rows, self.batch, self.lr,
+                          _lib.MLP_F_COMPENSATED if compensated else 0)
+        nbytes = ctypes.c_size_t(0)
+        check(lib.mlp_workspace_size(ctypes.byref(self.cfg), ctypes.byref(nbytes)))
+        self.ws_bytes = int(nbytes.value)
+        self.ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        check(lib.mlp_init(ctypes.byref(h), ctypes.byref(self.cfg), self.params_c(), _ptr(self.comp),
+                           _ptr(self.ws), self.ws_bytes))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib.mlp_destroy(h)
+            self._h = None
+
+    def params_c(self) -> Params:
+        return Params(self.W1.data_ptr(), self.b1.data_ptr(), self.W2.data_ptr(), self.b2.data_ptr())
+
+    def set_theta(self, theta) -> None:
+        self.flat.copy_(torch.as_tensor(np.asarray(theta_packed(theta), dtype=np.float32)))
+        if self.comp is not None:
+            self.comp.zero_()
+
+    def new_grads(self) -> Grads:
+        flat = _aligned_empty(self.flat.numel(), self.device)
+        W1, b1, W2, b2 = split_packed(flat, self.D, self.H, self.K)
+        return Grads(W1, b1, W2, b2, flat)
+
+    # ---------------------------------------------------------------- steps
+    def forward(self, X: torch.Tensor, want_hidden: bool = True, stream=None):
+        n = X.shape[0]
+        A = torch.empty((n, self.H), dtype=torch.float32, device=self.device) if want_hidden else None
+        Y = torch.empty((n, self.K), dtype=torch.float32, device=self.device)
+        check(lib.mlp_forward(self._h, _ptr(X), n, _ptr(A), _ptr(Y), _stream(stream)))
+        return A, Y
+
+    def backward(self, X, A, Y, dY=None, T=None, want_dx=False, grads: Grads | None = None, stream=None):
+        n = X.shape[0]
+        g = grads if grads is not None else self.new_grads()
+        dX = torch.empty((n, self.D), dtype=torch.float32, device=self.device) if want_dx else None
+        loss = torch.empty(4, dtype=torch.float32, device=self.device)[:1] if dY is None else None
+        check(lib.mlp_backward(self._h, _ptr(X), _ptr(A), _ptr(Y), _ptr(dY), _ptr(T), n, g.c(), _ptr(dX),
+                               _ptr(loss), _stream(stream)))
+        return g, dX, loss
+
+    def step(self, grads: Grads, lr: float | None = None, stream=None) -> None:
+        check(lib.mlp_step(self._h, grads.c(), float(self.lr if lr is None else lr), _stream(stream)))
+
+    def train(self, X: torch.Tensor, T: torch.Tensor, epochs: int, record_loss: bool = True,
+              loss_hist: torch.Tensor | None = None, stream=None):
+        if record_loss and loss_hist is None:
+            loss_hist = torch.empty(max(epochs, 4), dtype=torch.float32, device=self.device)[:epochs]
+        check(lib.mlp_train(self._h, _ptr(X), _ptr(T), int(epochs), _ptr(loss_hist) if record_loss else None,
+                            _stream(stream)))
+        return loss_hist
+
+
+def theta_packed(theta) -> np.ndarray:
+    if hasattr(theta, "packed"):
+        return theta.packed()
+    return np.asarray(theta, dtype=np.float32)
+
+
+# ---------------------------------------------------------------- batched
+class BatchPlan:
+    """Host and device copies of the item table for mlp_train_batched.
+
+    `order` lists the nets in launch order: longest first (by N_i * H_i), a
+    greedy longest-processing-time schedule over the hardware's workgroup
+    dispatcher.  Results are indexed by the caller's net index regardless of
+    the order.
+    """
+
+    def __init__(self, items, device="cuda", order: str = "lpt"):
+        n = len(items)
+        cost = np.array([it["n_rows"] * it["n_hidden"] for it in items], dtype=np.int64)
+        if isinstance(order, str) and order == "lpt":
+            self.order = np.argsort(-cost, kind="stable")
+        elif isinstance(order, str) and order == "given":
+            self.order = np.arange(n)
+        else:
+            self.order = np.asarray(order)
+        arr = (BatchItem * n)()
+        for pos, i in enumerate(self.order):
+            it = items[int(i)]
+            arr[pos] = BatchItem(int(it["n_rows"]), int(it["n_hidden"]), float(it["lr"]), 0, int(it["x_off"]),
+                                 int(it["p_off"]))
+        self.host = arr
+        self.n = n
+        raw = np.frombuffer(bytes(arr), dtype=np.uint8).copy()
+        self.dev = torch.from_numpy(raw).to(device)
+        self.max_rows = int(max(it["n_rows"] for it in items))
+        self.max_hidden = int(max(it["n_hidden"] for it in items))
+
+
+def train_batched(plan: BatchPlan, X: torch.Tensor, T: torch.Tensor, theta: torch.Tensor,
+                  comp: torch.Tensor | None, epochs: int, n_in: int, n_out: int,
+                  loss_hist: torch.Tensor | None = None, stream=None):
+    """Train every net of the plan in one launch; loss_hist rows follow the plan order."""
+    check(lib.mlp_train_batched(plan.host, _ptr(plan.dev), plan.n, n_in, n_out, _ptr(X), _ptr(T),
+                                X.shape[0], _ptr(theta), _ptr(comp), theta.numel(), int(epochs),
+                                _ptr(loss_hist), _stream(stream)))
+    return loss_hist
+
+
+# ---------------------------------------------------------------- autograd
+class MLPFunction(torch.autograd.Function):
+    """Y = sigma(sigma(X W1^T + b1) W2^T + b2) with the hand-written adjoint.
+
+    Usage:  Y = MLPFunction.apply(net, X, net.W1, net.b1, net.W2, net.b2)
+    The parameters must be the net's own tensors (the kernels read them from
+    the handle); they are passed so autograd can route their gradients.
+    """
+
+    @staticmethod
+    def forward(ctx, net: Net, X, W1, b1, W2, b2):
+        A, Y = net.forward(X)
+        ctx.net = net
+        ctx.save_for_backward(X, A, Y)
+        return Y
+
+    @staticmethod
+    def backward(ctx, gY):
+        X, A, Y = ctx.saved_tensors
+        net: Net = ctx.net
+        g, dX, _ = net.backward(X, A, Y, dY=gY.contiguous(), want_dx=ctx.needs_input_grad[1])
+        return None, dX, g.W1, g.b1, g.W2, g.b2

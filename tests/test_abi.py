@@ -1,0 +1,122 @@
+"""The C ABI of libmlp on the host: the library loads, exports every symbol
+that include/mlp.h declares, and rejects bad arguments before any HIP call
+(so these run without a GPU; no compute call is made)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_1908_07847_amd import _lib
+    return _lib
+
+
+def test_header_declarations_are_all_exported():
+    L = _lib()
+    hdr = open(os.path.join(ROOT, "include", "mlp.h")).read()
+    declared = set(re.findall(r"\b(mlp_[a-z_]+)\s*\(", hdr))
+    assert declared == set(L.SYMBOLS)
+    for name in declared:
+        assert hasattr(L.lib, name), name
+
+
+def test_struct_sizes_match_header():
+    L = _lib()
+    assert ctypes.sizeof(L.BatchItem) == 32
+    assert ctypes.sizeof(L.Config) == 40
+
+
+def test_status_strings():
+    L = _lib()
+    for s in range(7):
+        assert L.lib.mlp_status_string(s)
+    assert L.lib.mlp_status_string(99) == b"unknown status"
+
+
+def _ws(cfg):
+    L = _lib()
+    n = ctypes.c_size_t(0)
+    st = L.lib.mlp_workspace_size(ctypes.byref(cfg), ctypes.byref(n))
+    return st, n.value
+
+
+def test_workspace_size_and_config_validation():
+    L = _lib()
+    good = L.Config(33, 16, 3, 0, 120, 0, 0.1, 1)
+    st, n = _ws(good)
+    assert st == L.MLP_OK and n >= 120 * (16 + 3 + 1) * 4 and n % 256 == 0
+    bad = [L.Config(0, 16, 3, 0, 120, 0, 0.1, 1), L.Config(33, 0, 3, 0, 120, 0, 0.1, 1),
+           L.Config(33, 16, 0, 0, 120, 0, 0.1, 1), L.Config(33, 16, 3, 0, 0, 0, 0.1, 1),
+           L.Config(33, 16, 3, 0, 120, -1, 0.1, 1), L.Config(33, 16, 17, 0, 120, 0, 0.1, 1)]
+    for c in bad:
+        assert _ws(c)[0] == L.MLP_ERR_SHAPE
+    assert _ws(L.Config(33, 16, 3, 7, 120, 0, 0.1, 1))[0] == L.MLP_ERR_ARG        # precision
+    assert _ws(L.Config(33, 16, 3, 0, 120, 0, 0.1, 8))[0] == L.MLP_ERR_ARG        # flags
+    assert _ws(L.Config(33, 16, 3, 0, 120, 0, float("nan"), 1))[0] == L.MLP_ERR_ARG
+    assert L.lib.mlp_workspace_size(None, None) == L.MLP_ERR_ARG
+    assert b"NULL" in L.lib.mlp_last_error()
+
+
+def test_init_rejects_before_touching_the_device():
+    L = _lib()
+    h = ctypes.c_void_p()
+    cfg = L.Config(33, 16, 3, 0, 120, 0, 0.1, 1)
+    p = L.Params(0x1000, 0x2000, 0x3000, 0x4000)
+    # compensated without a buffer
+    assert L.lib.mlp_init(ctypes.byref(h), ctypes.byref(cfg), p, None, 0x5000, 1 << 20) == L.MLP_ERR_ARG
+    # workspace too small
+    assert L.lib.mlp_init(ctypes.byref(h), ctypes.byref(cfg), p, 0x6000, 0x5000, 16) == L.MLP_ERR_WORKSPACE
+    # misaligned parameter pointer
+    p2 = L.Params(0x1002, 0x2000, 0x3000, 0x4000)
+    assert L.lib.mlp_init(ctypes.byref(h), ctypes.byref(cfg), p2, 0x6000, 0x5000, 1 << 20) == L.MLP_ERR_ALIGN
+    # NULL parameter
+    p3 = L.Params(0x1000, None, 0x3000, 0x4000)
+    assert L.lib.mlp_init(ctypes.byref(h), ctypes.byref(cfg), p3, 0x6000, 0x5000, 1 << 20) == L.MLP_ERR_ARG
+    assert h.value is None
+
+
+def test_calls_on_a_null_handle_fail_cleanly():
+    L = _lib()
+    p = L.Params(0x1000, 0x2000, 0x3000, 0x4000)
+    assert L.lib.mlp_forward(None, 0x1000, 4, None, 0x2000, None) == L.MLP_ERR_ARG
+    assert L.lib.mlp_backward(None, 0x1000, 0x2000, 0x3000, None, 0x4000, 4, p, None, None, None) == L.MLP_ERR_ARG
+    assert L.lib.mlp_step(None, p, 0.1, None) == L.MLP_ERR_ARG
+    assert L.lib.mlp_train(None, 0x1000, 0x2000, 5, None, None) == L.MLP_ERR_ARG
+    assert L.lib.mlp_destroy(None) == L.MLP_ERR_ARG
+
+
+def _items(**kw):
+    L = _lib()
+    base = dict(n_rows=50, n_hidden=8, lr=0.1, reserved=0, x_off=0, p_off=0)
+    base.update(kw)
+    arr = (L.BatchItem * 1)()
+    arr[0] = L.BatchItem(base["n_rows"], base["n_hidden"], base["lr"], base["reserved"], base["x_off"],
+                         base["p_off"])
+    return arr
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(n_rows=0), 2), (dict(n_rows=129), 2), (dict(n_hidden=65), 2), (dict(n_hidden=0), 2),
+    (dict(x_off=60), 2), (dict(p_off=10**6), 2), (dict(reserved=1), 1), (dict(lr=-1.0), 1)])
+def test_batched_item_validation(kw, status):
+    L = _lib()
+    st = L.lib.mlp_train_batched(_items(**kw), 0x1000, 1, 33, 3, 0x2000, 0x3000, 100, 0x4000, None,
+                                 100000, 10, None, None)
+    assert st == status
+
+
+def test_batched_shape_and_pointer_validation():
+    L = _lib()
+    it = _items()
+    assert L.lib.mlp_train_batched(it, 0x1000, 0, 33, 3, 0x2000, 0x3000, 100, 0x4000, None, 10**5, 1, None,
+                                   None) == L.MLP_ERR_SHAPE
+    assert L.lib.mlp_train_batched(it, 0x1000, 1, 49, 3, 0x2000, 0x3000, 100, 0x4000, None, 10**5, 1, None,
+                                   None) == L.MLP_ERR_SHAPE
+    assert L.lib.mlp_train_batched(it, 0x1008, 1, 33, 3, 0x2000, 0x3000, 100, 0x4000, None, 10**5, 1, None,
+                                   None) == L.MLP_ERR_ALIGN
+    assert L.lib.mlp_train_batched(it, None, 1, 33, 3, 0x2000, 0x3000, 100, 0x4000, None, 10**5, 1, None,
+                                   None) == L.MLP_ERR_ARG
