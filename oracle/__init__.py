@@ -63,7 +63,8 @@ def _load():
     lib.ora_e4m3_scale_exp.argtypes = [dbl]
     lib.ora_e4m3_scale_exp.restype = i32
     lib.ora_train_lowp.argtypes = [i64, i32, i32, i32, i64, P, P, P, P, P, P, dbl, i32, i32, P,
-                                   ctypes.c_void_p]
+                                   ctypes.c_void_p, P, P]
+    lib.ora_round_array.argtypes = [i32, i32, P, P, i64]
     _lib = lib
     return lib
 
@@ -181,8 +182,9 @@ def e4m3_scale_exp(amax: float) -> int:
 PREC = {"fp32": 0, "bf16": 1, "e4m3": 2}
 
 
-def train_lowp(X, T, p: Params, lr: float, epochs: int, batch: int, prec: str):
-    """Training with rounded contraction operands; returns (Params, loss_hist, scale_log)."""
+def train_lowp(X, T, p: Params, lr: float, epochs: int, batch: int, prec: str, first_step_detail=False):
+    """Training with rounded contraction operands; returns (Params, loss_hist, scale_log)
+    and, with first_step_detail, also (delta1, delta2 W2) of the first step."""
     X, T = _d(X), _d(T)
     d, h, k = p.shape
     q = p.copy()
@@ -191,6 +193,19 @@ def train_lowp(X, T, p: Params, lr: float, epochs: int, batch: int, prec: str):
     steps = -(-n // b) * epochs
     hist = np.zeros(max(epochs, 0))
     slog = np.zeros((steps, 3), dtype=np.int32)
+    d1 = np.zeros((b, h)) if first_step_detail else None
+    bp = np.zeros((b, h)) if first_step_detail else None
     _load().ora_train_lowp(n, d, h, k, int(batch), _p(X), _p(T), _p(q.W1), _p(q.b1), _p(q.W2),
-                           _p(q.b2), float(lr), int(epochs), PREC[prec], _p(hist), slog.ctypes.data)
+                           _p(q.b2), float(lr), int(epochs), PREC[prec], _p(hist), slog.ctypes.data,
+                           _p(d1) if first_step_detail else None, _p(bp) if first_step_detail else None)
+    if first_step_detail:
+        return q, hist, slog, d1, bp
     return q, hist, slog
+
+
+def round_array(values, prec: str, scale_exp: int = 0) -> np.ndarray:
+    """Operand rounding of the reduced-precision forms (e4m3: q(v 2^e) 2^-e)."""
+    v = _d(values).ravel()
+    out = np.empty_like(v)
+    _load().ora_round_array(PREC[prec], int(scale_exp), _p(v), _p(out), v.size)
+    return out.reshape(np.shape(values))

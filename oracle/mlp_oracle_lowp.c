@@ -70,14 +70,23 @@ static double q_op(double v, int prec, int sexp) {
 
 static double sigmoid(double z) { return 1.0 / (1.0 + exp(-z)); }
 
+/* Round n values to the operand format of prec with scale 2^sexp (e4m3). */
+void ora_round_array(int prec, int sexp, const double *in, double *out, int64_t n) {
+  for (int64_t q = 0; q < n; ++q) out[q] = q_op(in[q], prec, sexp);
+}
+
 /*
  * Training loop with rounded contraction operands.  Same loop, loss and
  * update as ora_train.  scale_log (may be NULL) receives, per step, the three
  * scale exponents used (X, W1, delta1); it is written only for prec 2.
+ * d1_first and bp_first (may be NULL; [batch][h]) receive, for the first
+ * step, delta1 and its back-propagated factor delta2 W2 before the sigmoid
+ * derivative is applied.
  */
 void ora_train_lowp(int64_t n, int d, int h, int k, int64_t batch, const double *X,
                     const double *T, double *W1, double *b1, double *W2, double *b2, double lr,
-                    int epochs, int prec, double *loss_hist, int32_t *scale_log) {
+                    int epochs, int prec, double *loss_hist, int32_t *scale_log, double *d1_first,
+                    double *bp_first) {
   if (batch <= 0 || batch > n) batch = n;
   int64_t steps = (n + batch - 1) / batch;
   int64_t bmax = batch;
@@ -164,6 +173,8 @@ void ora_train_lowp(int64_t n, int d, int h, int k, int64_t batch, const double 
           double a = A[r * h + j];
           delta1[r * h + j] = sum * a * (1.0 - a);
           amax_d1 = fmax(amax_d1, fabs(delta1[r * h + j]));
+          if (step_no == 0 && d1_first) d1_first[r * h + j] = delta1[r * h + j];
+          if (step_no == 0 && bp_first) bp_first[r * h + j] = sum;
         }
       for (int64_t q = 0; q < m * h; ++q) delta1q[q] = q_op(delta1[q], prec, ed);
       /* gradients */

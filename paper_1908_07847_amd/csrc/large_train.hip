@@ -1,18 +1,868 @@
-// Large-N minibatch trainer (placeholder until the persistent kernel lands).
+// Large-N minibatch trainer: one persistent, cooperatively launched kernel
+// runs every minibatch step of every epoch (arxiv 1908.07847, section 2.2:
+// feed forward, error, backpropagation, gradient-descent update; contiguous
+// minibatches in stored order).
+//
+// Work of one step (minibatch of m <= b rows) is split over a Gi x Gj grid
+// of workgroups: workgroup (i, j) owns row block i (RB = b / Gi rows) and
+// hidden block j (HB = Hp / Gj units; each of its 4 waves owns HB/4).  The
+// two large contractions run on MFMA:
+//   z1 = X W1^T           M = rows,   N = hidden,   K = features
+//   gW1 = delta1^T X      M = hidden, N = features, K = rows
+// in float32 (v_mfma_f32_16x16x4_f32), bf16 or OCP e4m3 (16x16x32, float32
+// accumulation).  Everything else -- biases, sigmoid, the K-output layer,
+// the deltas, gb1, gW2, gb2, the loss and the update of the float32 master
+// parameters -- is float32 VALU work.
+//
+// A step is three phases separated by grid barriers:
+//   1  each workgroup forms a = sigma(z1 + b1) for its tile, row chunk by row
+//      chunk, and the partial output pre-activation over its hidden block;
+//      the Gj partials of a row meet in the workspace (skipped when Gj = 1).
+//   2  each workgroup completes z2, y, delta2 (and the loss) for its rows,
+//      recomputes its tile of a (cheaper on MFMA than a trip through HBM),
+//      forms delta1 = (delta2 W2) . a (1 - a) with the pre-update W2, and
+//      accumulates its partial gW1, gb1, gW2 (and gb2) over its rows.
+//   3  every workgroup sums a slice of the Gi partials of each parameter in
+//      a fixed order and applies the (optionally Kahan-compensated) update.
+// All reductions use fixed orders, so runs are bitwise repeatable.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <string>
+
+#include "mlp_device.hpp"
 #include "mlp_large.hpp"
+
+namespace mlpk {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kLT = 256;     // threads per workgroup (4 waves)
+constexpr int kRC = 32;      // rows per chunk
+constexpr int kMaxD = 64;    // features
+constexpr int kMaxHW = 64;   // hidden units per wave
+constexpr int kMaxK = 4;     // outputs
+
+struct LargeArgs {
+  const float *X, *T;
+  float *theta, *comp, *loss_hist;
+  float *z2p;        // [Gj][b][4] partial output pre-activations
+  float *gp;         // [Gi][P] partial gradients
+  float *lossp;      // [Gi] partial squared errors
+  float *amax;       // [2][G] W1 amax partials, [2][G] delta1 amax partials
+  float *acc;        // [4]: epoch loss accumulator, dataset |X| amax, ...
+  unsigned *bar;     // [2]: barrier counter, error flag
+  int64_t N, b;
+  int D, H, Hp, K, Gi, Gj, epochs, steps_per_epoch;
+  float lr;
+};
+
+// ---------------------------------------------------------------- barrier
+// Monotonic grid barrier: the k-th barrier waits for the counter to reach
+// k * G.  Every workgroup is resident (cooperative launch).  A spin limit
+// turns a barrier that never completes into a sticky error flag instead of
+// a hang, so every wave still leaves the kernel.
+__device__ __forceinline__ void grid_barrier(unsigned *bar, unsigned target) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned spins = 0;
+    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > (1u << 26)) {
+        __hip_atomic_store(bar + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+    }
+    __threadfence();
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- operands
+// OCP e4m3 with a power-of-two scale 2^e: saturate to +-448 first (the
+// hardware conversion would give NaN above 448), round to nearest even.
+__device__ __forceinline__ uint32_t pack_e4m3x4(float a, float b, float c, float d) {
+  a = fminf(fmaxf(a, -448.f), 448.f);
+  b = fminf(fmaxf(b, -448.f), 448.f);
+  c = fminf(fmaxf(c, -448.f), 448.f);
+  d = fminf(fmaxf(d, -448.f), 448.f);
+  int v = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+  v = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, v, true);
+  return (uint32_t)v;
+}
+
+// e such that amax * 2^e <= 448 < amax * 2^(e+1) (0 for amax == 0).
+__device__ __forceinline__ int e4m3_scale_exp(float amax) {
+  if (!(amax > 0.0f)) return 0;
+  int ex;
+  float f = frexpf(amax, &ex);  // amax = f * 2^ex, f in [0.5, 1); 448 = 0.875 * 2^9
+  return (f <= 0.875f) ? 9 - ex : 8 - ex;
+}
+
+template <int PREC>
+struct Ops;
+
+// float32: operands are floats, one per lane per 16x16x4 step.
+template <>
+struct Ops<0> {
+  static constexpr int KSTEP = 4;
+  typedef float elem;
+  static constexpr int XROW = 66;   // LDS row stride (floats) of X rows and W1 rows
+  static constexpr int DST = 16;    // delta1 staging: [32 rows][16]
+};
+// bf16 / e4m3: 8 operands per lane per 16x16x32 step.
+template <>
+struct Ops<1> {
+  static constexpr int KSTEP = 32;
+  typedef __bf16 elem;
+  static constexpr int XROW = 72;   // bf16 elements per X / W1 row (64 + pad)
+  static constexpr int XT = 40;     // transposed X chunk row (32 rows + pad)
+  static constexpr int DST = 40;    // delta1 staging: [16 hidden][32 rows + pad]
+};
+template <>
+struct Ops<2> {
+  static constexpr int KSTEP = 32;
+  typedef uint8_t elem;
+  static constexpr int XROW = 80;   // bytes per X / W1 row (64 + pad)
+  static constexpr int XT = 48;
+  static constexpr int DST = 48;
+};
+
+// LDS plan (bytes), shared by host and device.
+template <int PREC>
+struct LLayout {
+  int HB, RB;
+  __host__ __device__ LLayout(int hb, int rb) : HB(hb), RB(rb) {}
+  static constexpr int esz = sizeof(typename Ops<PREC>::elem);
+  __host__ __device__ int xr() const { return 0; }
+  __host__ __device__ int xt() const { return xr() + kRC * Ops<PREC>::XROW * esz; }
+  __host__ __device__ int w1() const {
+    return xt() + (PREC == 0 ? 0 : kMaxD * Ops<(PREC == 0 ? 1 : PREC)>::XT * esz);
+  }
+  __host__ __device__ int b1() const { return w1() + HB * Ops<PREC>::XROW * esz; }
+  __host__ __device__ int w2() const { return b1() + HB * 4; }
+  __host__ __device__ int d2() const { return w2() + kMaxK * HB * 4; }
+  __host__ __device__ int z2w() const { return d2() + RB * 16; }
+  __host__ __device__ int dst() const { return z2w() + 4 * kRC * 16; }
+  __host__ __device__ int red() const {
+    return dst() + 4 * (PREC == 0 ? kRC * 16 * 4 : 16 * Ops<(PREC == 0 ? 1 : PREC)>::DST * esz);
+  }
+  __host__ __device__ int total() const { return red() + 64 * 4; }
+};
+
+template <int PREC>
+__global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
+  using O = Ops<PREC>;
+  using E = typename O::elem;
+  constexpr int XROW = O::XROW;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int G = a.Gi * a.Gj;
+  // XCD-aware placement: workgroups are dispatched round-robin over the 8
+  // XCDs, so the Gj workgroups that share a row block (and its X rows) get
+  // the same blockIdx % 8 and hence the same L2.
+  const int bid = blockIdx.x;
+  int gi, gj;
+  if (G % 8 == 0 && a.Gi % 8 == 0) {
+    const int xcd = bid & 7, q = bid >> 3;
+    gj = q % a.Gj;
+    gi = (q / a.Gj) * 8 + xcd;
+  } else {
+    gi = bid / a.Gj;
+    gj = bid - gi * a.Gj;
+  }
+  const int D = a.D, H = a.H, K = a.K;
+  const int HB = a.Hp / a.Gj, HW = HB / 4, NHB = HW / 16;
+  const int RB = (int)(a.b / a.Gi);
+  const int h0 = gj * HB + wave * HW;     // first hidden unit of this wave
+  const int64_t P = (int64_t)D * H + H + (int64_t)H * K + K;
+  const int64_t oB1 = (int64_t)D * H, oW2 = oB1 + H, oB2 = oW2 + (int64_t)H * K;
+  const LLayout<PREC> L(HB, RB);
+  const int KS = O::KSTEP;
+  const int DK = (D + KS - 1) / KS * KS;      // padded contraction length of z1
+  const int NFB = (D + 15) / 16;              // 16-wide feature blocks of gW1
+  const int l16 = lane & 15, lg = lane >> 4;  // MFMA lane coordinates
+
+  extern __shared__ float4 smem4[];
+  char *smb = reinterpret_cast<char *>(smem4);
+  E *xr = reinterpret_cast<E *>(smb + L.xr());
+  E *xt = reinterpret_cast<E *>(smb + L.xt());
+  E *w1s = reinterpret_cast<E *>(smb + L.w1());
+  float *b1s = reinterpret_cast<float *>(smb + L.b1());
+  float *w2s = reinterpret_cast<float *>(smb + L.w2());
+  float *d2s = reinterpret_cast<float *>(smb + L.d2());
+  float *z2w = reinterpret_cast<float *>(smb + L.z2w());
+  char *dstb = smb + L.dst();
+  float *red = reinterpret_cast<float *>(smb + L.red());
+
+  unsigned nbar = 0;
+  auto barrier = [&]() {
+    nbar += 1;
+    grid_barrier(a.bar, nbar * (unsigned)G);
+  };
+
+  // ---- one-time: dataset amax of |X| for the e4m3 X scale
+  int ex = 0;
+  if (PREC == 2) {
+    float m = 0.0f;
+    const int64_t nx = a.N * D;
+    for (int64_t q = (int64_t)bid * kLT + tid; q < nx; q += (int64_t)G * kLT) m = fmaxf(m, fabsf(a.X[q]));
+    for (int off = 32; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, kWave));
+    if (lane == 0) red[wave] = m;
+    __syncthreads();
+    if (tid == 0) a.amax[4 * G + bid] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    barrier();
+    float mm = 0.0f;
+    for (int g = 0; g < G; ++g) mm = fmaxf(mm, a.amax[4 * G + g]);
+    ex = e4m3_scale_exp(mm);
+  }
+  const float sx = ldexpf(1.0f, ex), isx = ldexpf(1.0f, -ex);
+
+  const int total_steps = a.epochs * a.steps_per_epoch;
+  for (int step = 0; step < total_steps; ++step) {
+    const int e = step / a.steps_per_epoch, sidx = step - e * a.steps_per_epoch;
+    const int64_t r0 = (int64_t)sidx * a.b;
+    const int64_t m = min((int64_t)a.b, a.N - r0);      // rows in this minibatch
+    const int64_t rb0 = r0 + (int64_t)gi * RB;          // first row of this block
+    const int rows_here = (int)max((int64_t)0, min((int64_t)RB, m - (int64_t)gi * RB));
+    const float dscale = 2.0f / ((float)m * (float)K);
+
+    // ---- scales of this step (e4m3): W1 from the master, delta1 delayed
+    int ew = 0, ed = 0;
+    if (PREC == 2) {
+      const int par = step & 1;
+      if (step == 0) {
+        float mw = 0.0f;
+        for (int64_t q = tid; q < (int64_t)H * D; q += kLT) mw = fmaxf(mw, fabsf(a.theta[q]));
+        for (int off = 32; off >= 1; off >>= 1) mw = fmaxf(mw, __shfl_xor(mw, off, kWave));
+        if (lane == 0) red[wave] = mw;
+        __syncthreads();
+        ew = e4m3_scale_exp(fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3])));
+        __syncthreads();
+        // first step: the bound max_h sum_k |W2[k][h]| / (8 m K), in float32, left to right
+        float bound = 0.0f;
+        for (int h = 0; h < H; ++h) {
+          float col = 0.0f;
+          for (int k = 0; k < K; ++k) col = col + fabsf(a.theta[oW2 + (int64_t)k * H + h]);
+          if (col > bound) bound = col;
+        }
+        bound = bound / (float)(8 * m * K);
+        ed = e4m3_scale_exp(bound);
+      } else {
+        float mw = 0.0f, md = 0.0f;
+        for (int g = 0; g < G; ++g) {
+          mw = fmaxf(mw, a.amax[par * G + g]);              // written by the previous update
+          md = fmaxf(md, a.amax[2 * G + (par ^ 1) * G + g]);  // previous step's delta1
+        }
+        ew = e4m3_scale_exp(mw);
+        ed = e4m3_scale_exp(md);
+      }
+    }
+    const float sw = ldexpf(1.0f, ew), isw = ldexpf(1.0f, -ew);
+    const float sd = ldexpf(1.0f, ed), isd = ldexpf(1.0f, -ed);
+
+    // ---- stage this workgroup's slice of W1 (operand precision), b1, W2
+    for (int q = tid; q < HB * XROW; q += kLT) {
+      const int hl = q / XROW, c = q - hl * XROW;
+      const int h = gj * HB + hl;
+      float v = (h < H && c < D) ? a.theta[(int64_t)h * D + c] : 0.0f;
+      if (PREC == 0) reinterpret_cast<float *>(w1s)[q] = v;
+      if (PREC == 1) reinterpret_cast<__bf16 *>(w1s)[q] = (__bf16)v;
+      if (PREC == 2 && (c & 3) == 0) {
+        // four neighbours at once (rows are 16-byte multiples)
+        float v1 = (h < H && c + 1 < D) ? a.theta[(int64_t)h * D + c + 1] : 0.0f;
+        float v2 = (h < H && c + 2 < D) ? a.theta[(int64_t)h * D + c + 2] : 0.0f;
+        float v3 = (h < H && c + 3 < D) ? a.theta[(int64_t)h * D + c + 3] : 0.0f;
+        *reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(w1s) + q) =
+            pack_e4m3x4(v * sw, v1 * sw, v2 * sw, v3 * sw);
+      }
+    }
+    for (int q = tid; q < HB; q += kLT) {
+      const int h = gj * HB + q;
+      b1s[q] = h < H ? a.theta[oB1 + h] : 0.0f;
+    }
+    for (int q = tid; q < kMaxK * HB; q += kLT) {
+      const int k = q / HB, hl = q - k * HB, h = gj * HB + hl;
+      w2s[q] = (k < K && h < H) ? a.theta[oW2 + (int64_t)k * H + h] : 0.0f;
+    }
+
+    // Stage rows [c0, c0+kRC) of this block into xr (and xt), operand precision.
+    auto stage_x = [&](int c0) {
+      __syncthreads();
+      for (int q = tid; q < kRC * 16; q += kLT) {   // 16 groups of 4 columns per row
+        const int rr = q >> 4, c = (q & 15) * 4;
+        const int rloc = c0 + rr;
+        const bool on = rloc < rows_here;
+        const float *src = a.X + (rb0 + rloc) * D;
+        float v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = (on && c + u < D) ? src[c + u] : 0.0f;
+        if (PREC == 0) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) reinterpret_cast<float *>(xr)[rr * XROW + c + u] = v[u];
+        } else if (PREC == 1) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const __bf16 bv = (__bf16)v[u];
+            reinterpret_cast<__bf16 *>(xr)[rr * XROW + c + u] = bv;
+            reinterpret_cast<__bf16 *>(xt)[(c + u) * Ops<1>::XT + rr] = bv;
+          }
+        } else {
+          const uint32_t pk = pack_e4m3x4(v[0] * sx, v[1] * sx, v[2] * sx, v[3] * sx);
+          *reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(xr) + rr * XROW + c) = pk;
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            reinterpret_cast<uint8_t *>(xt)[(c + u) * Ops<2>::XT + rr] = (uint8_t)(pk >> (8 * u));
+        }
+      }
+      __syncthreads();
+    };
+
+    // z1 block for rows [rs*16, rs*16+16) of the chunk and hidden block hb of
+    // this wave: lane holds rows 4*lg+i, hidden unit 16*hb + l16.
+    auto z1_block = [&](int rs, int hb) -> f32x4 {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      const int hl = wave * HW + hb * 16 + l16;   // local hidden row in w1s
+      if (PREC == 0) {
+        const float *xa = reinterpret_cast<const float *>(xr) + (rs * 16 + l16) * XROW + lg;
+        const float *wb = reinterpret_cast<const float *>(w1s) + hl * XROW + lg;
+        for (int k0 = 0; k0 < DK; k0 += 4)
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[k0], wb[k0], acc, 0, 0, 0);
+      } else if (PREC == 1) {
+        const __bf16 *xa = reinterpret_cast<const __bf16 *>(xr) + (rs * 16 + l16) * XROW + 8 * lg;
+        const __bf16 *wb = reinterpret_cast<const __bf16 *>(w1s) + hl * XROW + 8 * lg;
+        for (int k0 = 0; k0 < DK; k0 += 32) {
+          const bf16x8 av = *reinterpret_cast<const bf16x8 *>(xa + k0);
+          const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(wb + k0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+        }
+      } else {
+        const uint8_t *xa = reinterpret_cast<const uint8_t *>(xr) + (rs * 16 + l16) * XROW + 8 * lg;
+        const uint8_t *wb = reinterpret_cast<const uint8_t *>(w1s) + hl * XROW + 8 * lg;
+        for (int k0 = 0; k0 < DK; k0 += 32) {
+          const long av = *reinterpret_cast<const long *>(xa + k0);
+          const long bv = *reinterpret_cast<const long *>(wb + k0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bv, acc, 0, 0, 0);
+        }
+        acc *= isx * isw;
+      }
+      return acc;
+    };
+
+    // ================================================================ phase 1
+    const bool split = a.Gj > 1;
+    if (split) {
+      for (int c0 = 0; c0 < RB; c0 += kRC) {
+        stage_x(c0);
+        float zp[2][4][kMaxK];
+#pragma unroll
+        for (int rs = 0; rs < 2; ++rs)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int k = 0; k < kMaxK; ++k) zp[rs][i][k] = 0.0f;
+        for (int hb = 0; hb < NHB; ++hb) {
+          const int hl = wave * HW + hb * 16 + l16;
+          const float bias = b1s[hl];
+          float w2v[kMaxK];
+#pragma unroll
+          for (int k = 0; k < kMaxK; ++k) w2v[k] = w2s[k * HB + hl];
+#pragma unroll
+          for (int rs = 0; rs < 2; ++rs) {
+            const f32x4 z = z1_block(rs, hb);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const float av = sigmoid(z[i] + bias);
+#pragma unroll
+              for (int k = 0; k < kMaxK; ++k) zp[rs][i][k] = fmaf(av, w2v[k], zp[rs][i][k]);
+            }
+          }
+        }
+        // sum over the 16 hidden lanes of each row (fixed butterfly)
+#pragma unroll
+        for (int rs = 0; rs < 2; ++rs)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int k = 0; k < kMaxK; ++k) {
+              float v = zp[rs][i][k];
+              for (int off = 8; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+              zp[rs][i][k] = v;
+            }
+        if (l16 == 0) {
+#pragma unroll
+          for (int rs = 0; rs < 2; ++rs)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+              for (int k = 0; k < kMaxK; ++k)
+                z2w[(wave * kRC + rs * 16 + 4 * lg + i) * 4 + k] = zp[rs][i][k];
+        }
+        __syncthreads();
+        for (int q = tid; q < kRC * 4; q += kLT) {
+          const int rr = q >> 2, k = q & 3;
+          const float v = (z2w[(0 * kRC + rr) * 4 + k] + z2w[(1 * kRC + rr) * 4 + k]) +
+                          (z2w[(2 * kRC + rr) * 4 + k] + z2w[(3 * kRC + rr) * 4 + k]);
+          a.z2p[((int64_t)gj * a.b + (int64_t)gi * RB + c0 + rr) * 4 + k] = v;
+        }
+      }
+      barrier();
+    }
+
+    // ================================================================ phase 2
+    // output layer, error and delta2 for this block's rows
+    if (!split) {
+      // Gj == 1: z2 partials are complete inside this workgroup
+      for (int c0 = 0; c0 < RB; c0 += kRC) {
+        stage_x(c0);
+        float zp[2][4][kMaxK];
+#pragma unroll
+        for (int rs = 0; rs < 2; ++rs)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int k = 0; k < kMaxK; ++k) zp[rs][i][k] = 0.0f;
+        for (int hb = 0; hb < NHB; ++hb) {
+          const int hl = wave * HW + hb * 16 + l16;
+          const float bias = b1s[hl];
+          float w2v[kMaxK];
+#pragma unroll
+          for (int k = 0; k < kMaxK; ++k) w2v[k] = w2s[k * HB + hl];
+#pragma unroll
+          for (int rs = 0; rs < 2; ++rs) {
+            const f32x4 z = z1_block(rs, hb);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const float av = sigmoid(z[i] + bias);
+#pragma unroll
+              for (int k = 0; k < kMaxK; ++k) zp[rs][i][k] = fmaf(av, w2v[k], zp[rs][i][k]);
+            }
+          }
+        }
+#pragma unroll
+        for (int rs = 0; rs < 2; ++rs)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int k = 0; k < kMaxK; ++k) {
+              float v = zp[rs][i][k];
+              for (int off = 8; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+              zp[rs][i][k] = v;
+            }
+        if (l16 == 0) {
+#pragma unroll
+          for (int rs = 0; rs < 2; ++rs)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+              for (int k = 0; k < kMaxK; ++k)
+                z2w[(wave * kRC + rs * 16 + 4 * lg + i) * 4 + k] = zp[rs][i][k];
+        }
+        __syncthreads();
+        for (int q = tid; q < kRC * 4; q += kLT) {
+          const int rr = q >> 2, k = q & 3;
+          d2s[(c0 + rr) * 4 + k] = (z2w[(0 * kRC + rr) * 4 + k] + z2w[(1 * kRC + rr) * 4 + k]) +
+                                   (z2w[(2 * kRC + rr) * 4 + k] + z2w[(3 * kRC + rr) * 4 + k]);
+        }
+      }
+      __syncthreads();
+    }
+    float sq = 0.0f;
+    for (int q = tid; q < RB * 4; q += kLT) {
+      const int rr = q >> 2, k = q & 3;
+      float d = 0.0f;
+      if (k < K && rr < rows_here) {
+        float z = a.theta[oB2 + k];
+        if (split) {
+          for (int g = 0; g < a.Gj; ++g) z += a.z2p[((int64_t)g * a.b + (int64_t)gi * RB + rr) * 4 + k];
+        } else {
+          z += d2s[q];
+        }
+        const float y = sigmoid(z);
+        const float err = y - a.T[(rb0 + rr) * K + k];
+        sq = fmaf(err, err, sq);
+        d = dscale * err * y * (1.0f - y);
+      }
+      d2s[q] = d;  // each entry is read and rewritten by the same thread
+    }
+    __syncthreads();
+    // loss and gb2 partials (hidden block 0 only; other blocks hold copies)
+    if (gj == 0) {
+      for (int off = 32; off >= 1; off >>= 1) sq += __shfl_xor(sq, off, kWave);
+      if (lane == 0) red[wave] = sq;
+      float gb2 = 0.0f;
+      if (tid < 4 * 64) {
+        // wave w sums output w over the block's rows
+        const int k = wave;
+        for (int rr = lane; rr < RB; rr += 64) gb2 += d2s[rr * 4 + k];
+        for (int off = 32; off >= 1; off >>= 1) gb2 += __shfl_xor(gb2, off, kWave);
+      }
+      __syncthreads();
+      if (tid == 0) a.lossp[gi] = (red[0] + red[1]) + (red[2] + red[3]);
+      if (lane == 0 && wave < K) a.gp[(int64_t)gi * P + oB2 + wave] = gb2;
+    }
+
+    // recompute a, form delta1, accumulate gW1 (MFMA), gb1, gW2
+    f32x4 gacc[4][4];
+#pragma unroll
+    for (int hb = 0; hb < 4; ++hb)
+#pragma unroll
+      for (int fb = 0; fb < 4; ++fb) gacc[hb][fb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float gb1[4] = {0.f, 0.f, 0.f, 0.f};
+    float gw2[4][kMaxK];
+#pragma unroll
+    for (int hb = 0; hb < 4; ++hb)
+#pragma unroll
+      for (int k = 0; k < kMaxK; ++k) gw2[hb][k] = 0.0f;
+    float d1max = 0.0f;
+
+    for (int c0 = 0; c0 < RB; c0 += kRC) {
+      stage_x(c0);
+#pragma unroll
+      for (int hb = 0; hb < 4; ++hb) {
+        if (hb < NHB) {
+          const int hl = wave * HW + hb * 16 + l16;
+          const float bias = b1s[hl];
+          float w2v[kMaxK];
+#pragma unroll
+          for (int k = 0; k < kMaxK; ++k) w2v[k] = w2s[k * HB + hl];
+#pragma unroll
+          for (int rs = 0; rs < 2; ++rs) {
+            const f32x4 z = z1_block(rs, hb);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int rr = rs * 16 + 4 * lg + i;          // row within the chunk
+              float slope;
+              const float av = sigmoid_slope(z[i] + bias, slope);
+              const float4 dv = *reinterpret_cast<const float4 *>(d2s + (c0 + rr) * 4);
+              const float dd[4] = {dv.x, dv.y, dv.z, dv.w};
+              float bp = 0.0f;
+#pragma unroll
+              for (int k = 0; k < kMaxK; ++k) {
+                bp = fmaf(dd[k], w2v[k], bp);
+                gw2[hb][k] = fmaf(dd[k], av, gw2[hb][k]);
+              }
+              const float d1 = bp * slope;
+              gb1[hb] += d1;
+              // stage delta1 in the operand layout of the gW1 contraction
+              if (PREC == 0) {
+                reinterpret_cast<float *>(dstb)[wave * kRC * 16 + rr * 16 + l16] = d1;
+              } else if (PREC == 1) {
+                reinterpret_cast<__bf16 *>(dstb)[(wave * 16 + l16) * Ops<1>::DST + rr] = (__bf16)d1;
+              } else {
+                d1max = fmaxf(d1max, fabsf(d1));
+                float q = fminf(fmaxf(d1 * sd, -448.f), 448.f);
+                const int pk = __builtin_amdgcn_cvt_pk_fp8_f32(q, 0.0f, 0, false);
+                reinterpret_cast<uint8_t *>(dstb)[(wave * 16 + l16) * Ops<2>::DST + rr] = (uint8_t)pk;
+              }
+            }
+          }
+          // gW1[hidden block][feature blocks] += delta1^T X over the chunk's rows
+          if (PREC == 0) {
+            const float *da = reinterpret_cast<const float *>(dstb) + wave * kRC * 16 + lg * 16 + l16;
+            const float *xb = reinterpret_cast<const float *>(xr) + lg * XROW + l16;
+#pragma unroll
+            for (int fb = 0; fb < 4; ++fb) {
+              if (fb < NFB) {
+                f32x4 g = gacc[hb][fb];
+                for (int k0 = 0; k0 < kRC; k0 += 4)
+                  g = __builtin_amdgcn_mfma_f32_16x16x4f32(da[k0 * 16], xb[k0 * XROW + fb * 16], g, 0, 0, 0);
+                gacc[hb][fb] = g;
+              }
+            }
+          } else if (PREC == 1) {
+            const __bf16 *da = reinterpret_cast<const __bf16 *>(dstb) + (wave * 16 + l16) * Ops<1>::DST + 8 * lg;
+            const bf16x8 av = *reinterpret_cast<const bf16x8 *>(da);
+#pragma unroll
+            for (int fb = 0; fb < 4; ++fb) {
+              if (fb < NFB) {
+                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(
+                    reinterpret_cast<const __bf16 *>(xt) + (fb * 16 + l16) * Ops<1>::XT + 8 * lg);
+                gacc[hb][fb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, gacc[hb][fb], 0, 0, 0);
+              }
+            }
+          } else {
+            const uint8_t *da = reinterpret_cast<const uint8_t *>(dstb) + (wave * 16 + l16) * Ops<2>::DST + 8 * lg;
+            const long av = *reinterpret_cast<const long *>(da);
+#pragma unroll
+            for (int fb = 0; fb < 4; ++fb) {
+              if (fb < NFB) {
+                const long bv = *reinterpret_cast<const long *>(
+                    reinterpret_cast<const uint8_t *>(xt) + (fb * 16 + l16) * Ops<2>::XT + 8 * lg);
+                gacc[hb][fb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bv, gacc[hb][fb], 0, 0, 0);
+              }
+            }
+          }
+        }
+      }
+    }
+
+    // write this workgroup's partial gradients
+    {
+      float *gpi = a.gp + (int64_t)gi * P;
+      const float gscale = PREC == 2 ? isd * isx : 1.0f;
+#pragma unroll
+      for (int hb = 0; hb < 4; ++hb) {
+        if (hb < NHB) {
+#pragma unroll
+          for (int fb = 0; fb < 4; ++fb) {
+            if (fb < NFB) {
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                const int h = h0 + hb * 16 + 4 * lg + i, d = fb * 16 + l16;
+                if (h < H && d < D) gpi[(int64_t)h * D + d] = gacc[hb][fb][i] * gscale;
+              }
+            }
+          }
+          float v = gb1[hb];
+          v += __shfl_xor(v, 16, kWave);
+          v += __shfl_xor(v, 32, kWave);
+          float w[kMaxK];
+#pragma unroll
+          for (int k = 0; k < kMaxK; ++k) {
+            float t = gw2[hb][k];
+            t += __shfl_xor(t, 16, kWave);
+            t += __shfl_xor(t, 32, kWave);
+            w[k] = t;
+          }
+          const int h = h0 + hb * 16 + l16;
+          if (lg == 0 && h < H) {
+            gpi[oB1 + h] = v;
+#pragma unroll
+            for (int k = 0; k < kMaxK; ++k)
+              if (k < K) gpi[oW2 + (int64_t)k * H + h] = w[k];
+          }
+        }
+      }
+      if (PREC == 2) {
+        for (int off = 32; off >= 1; off >>= 1) d1max = fmaxf(d1max, __shfl_xor(d1max, off, kWave));
+        __syncthreads();
+        if (lane == 0) red[8 + wave] = d1max;
+        __syncthreads();
+        if (tid == 0)
+          a.amax[2 * G + (step & 1) * G + bid] =
+              fmaxf(fmaxf(red[8], red[9]), fmaxf(red[10], red[11]));
+      }
+    }
+    barrier();
+
+    // ================================================================ phase 3
+    // Sum the Gi partials of a slice of parameters (lanes over partials,
+    // fixed butterfly), update the master copy.
+    {
+      const int64_t per = (P + G - 1) / G;
+      const int64_t p0 = (int64_t)bid * per, p1 = min(P, p0 + per);
+      float wmax = 0.0f;
+      for (int64_t p = p0 + wave; p < p1; p += 4) {
+        float s = 0.0f;
+        for (int g = lane; g < a.Gi; g += 64) s += a.gp[(int64_t)g * P + p];
+        for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, kWave);
+        if (lane == 0) {
+          float w = a.theta[p], c = a.comp ? a.comp[p] : 0.0f;
+          gd_update(w, c, a.lr, s, a.comp != nullptr);
+          a.theta[p] = w;
+          if (a.comp) a.comp[p] = c;
+          if (p < oB1) wmax = fmaxf(wmax, fabsf(w));
+        }
+      }
+      if (PREC == 2) {
+        for (int off = 32; off >= 1; off >>= 1) wmax = fmaxf(wmax, __shfl_xor(wmax, off, kWave));
+        if (lane == 0) red[16 + wave] = wmax;
+        __syncthreads();
+        if (tid == 0)
+          a.amax[((step + 1) & 1) * G + bid] = fmaxf(fmaxf(red[16], red[17]), fmaxf(red[18], red[19]));
+      }
+      if (bid == 0 && tid == 0) {
+        float s = 0.0f;
+        for (int g = 0; g < a.Gi; ++g) s += a.lossp[g];
+        const float lstep = s / ((float)m * (float)K);
+        const float accum = (sidx == 0 ? 0.0f : a.acc[0]) + lstep;
+        a.acc[0] = accum;
+        if (sidx == a.steps_per_epoch - 1 && a.loss_hist)
+          a.loss_hist[e] = accum / (float)a.steps_per_epoch;
+      }
+    }
+    barrier();
+  }
+}
+
+__global__ void k_zero_u32(unsigned *p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+}
+
+}  // namespace mlpk
 
 namespace mlph {
 
-mlp_status large_workspace_bytes(const mlp_config &, size_t *bytes) {
-  *bytes = 0;
-  return MLP_ERR_UNSUPPORTED;
+namespace {
+
+constexpr int kMaxRowBlocks = 256, kMaxHiddenBlocks = 16;
+
+struct Plan {
+  int Gi, Gj, Hp;
+  size_t lds;
+};
+
+template <int PREC>
+size_t lds_bytes(int HB, int RB) {
+  return (size_t)mlpk::LLayout<PREC>(HB, RB).total();
 }
 
-mlp_status large_train(const mlp_config &, const mlp_params &, float *, void *, size_t, int,
-                       const float *, const float *, int, float *, hipStream_t,
-                       std::string *err) {
-  *err = "no large-N trainer for this configuration";
-  return MLP_ERR_UNSUPPORTED;
+size_t lds_for(int prec, int HB, int RB) {
+  if (prec == 0) return lds_bytes<0>(HB, RB);
+  if (prec == 1) return lds_bytes<1>(HB, RB);
+  return lds_bytes<2>(HB, RB);
+}
+
+int64_t batch_of(const mlp_config &c) { return (c.batch <= 0 || c.batch >= c.n_rows) ? c.n_rows : c.batch; }
+
+// Workspace layout (bytes, 256-aligned pieces).
+struct WsLayout {
+  size_t z2p, gp, lossp, amax, acc, bar, total;
+};
+
+WsLayout ws_layout(const mlp_config &c, int Gi, int Gj) {
+  const int64_t b = batch_of(c);
+  const int64_t P = (int64_t)c.n_in * c.n_hidden + c.n_hidden + (int64_t)c.n_hidden * c.n_out + c.n_out;
+  const int64_t bp = (b + 31) / 32 * 32 * 2;   // rows padded for any Gi that divides the block
+  auto up = [](size_t v) { return (v + 255) / 256 * 256; };
+  WsLayout w{};
+  size_t o = 0;
+  w.z2p = o; o += up(sizeof(float) * (size_t)Gj * bp * 4);
+  w.gp = o; o += up(sizeof(float) * (size_t)Gi * P);
+  w.lossp = o; o += up(sizeof(float) * (size_t)Gi);
+  w.amax = o; o += up(sizeof(float) * (size_t)5 * Gi * Gj);
+  w.acc = o; o += up(sizeof(float) * 4);
+  w.bar = o; o += up(sizeof(unsigned) * 4);
+  w.total = o;
+  return w;
+}
+
+}  // namespace
+
+// Grid shape: Gj hidden blocks of <= 256 units (a multiple of 64), Gi row
+// blocks of >= 32 rows; Gi*Gj workgroups, at most one per CU, and an
+// environment override for the autotuner.
+static bool plan_for(const mlp_config &c, int n_cu, Plan *pl, std::string *why) {
+  const int64_t b = batch_of(c);
+  const int H = c.n_hidden;
+  int Gj = 1;   // hidden blocks: at most 256 units each (4 waves x 64)
+  while ((H + 64 * Gj - 1) / (64 * Gj) * 64 > 256) Gj *= 2;
+  int Gi = 1;   // row blocks: at least 32 rows each, at most one workgroup per CU
+  while (Gi * 2 * Gj <= n_cu && b % (Gi * 2 * 32) == 0) Gi *= 2;
+  // fill the remaining CUs by splitting the hidden layer further
+  while (Gi * Gj * 2 <= n_cu && (H + 64 * Gj * 2 - 1) / (64 * Gj * 2) * 64 >= 64 &&
+         H > 64 * Gj)
+    Gj *= 2;
+  if (const char *env = getenv("MLP_LARGE_GRID")) {
+    int gi = 0, gj = 0;
+    if (sscanf(env, "%dx%d", &gi, &gj) == 2 && gi > 0 && gj > 0) { Gi = gi; Gj = gj; }
+  }
+  const int Hp = (H + 64 * Gj - 1) / (64 * Gj) * 64 * Gj;
+  if (Hp / Gj > 256) { *why = "hidden block above 256 units"; return false; }
+  if (Gi > kMaxRowBlocks || Gj > kMaxHiddenBlocks) { *why = "grid above the workspace plan"; return false; }
+  if (b % Gi != 0 || (b / Gi) % 32 != 0) { *why = "rows per block must be a multiple of 32"; return false; }
+  pl->Gi = Gi;
+  pl->Gj = Gj;
+  pl->Hp = Hp;
+  pl->lds = lds_for(c.prec, Hp / Gj, (int)(b / Gi));
+  return true;
+}
+
+mlp_status large_workspace_bytes(const mlp_config &c, size_t *bytes) {
+  if (c.n_in > mlpk::kMaxD || c.n_out > mlpk::kMaxK) return MLP_ERR_UNSUPPORTED;
+  const int64_t b = batch_of(c);
+  if (b % 32 != 0) return MLP_ERR_UNSUPPORTED;
+  // Size for the largest grid any plan may use.
+  size_t best = 0;
+  for (int gj = 1; gj <= kMaxHiddenBlocks; gj *= 2)
+    for (int gi = 1; gi <= kMaxRowBlocks; gi *= 2) best = std::max(best, ws_layout(c, gi, gj).total);
+  *bytes = best;
+  return MLP_OK;
+}
+
+mlp_status large_train(const mlp_config &c, const mlp_params &theta, float *comp, void *ws,
+                       size_t ws_bytes, int n_cu, const float *X, const float *T, int epochs,
+                       float *loss_hist, hipStream_t s, std::string *err) {
+  if (c.n_in > mlpk::kMaxD || c.n_out > mlpk::kMaxK) {
+    *err = "large-N trainer supports n_in <= 64 and n_out <= 4";
+    return MLP_ERR_UNSUPPORTED;
+  }
+  const int64_t D = c.n_in, H = c.n_hidden, K = c.n_out;
+  if (theta.b1 != theta.W1 + D * H || theta.W2 != theta.b1 + H || theta.b2 != theta.W2 + H * K) {
+    *err = "large-N training needs W1, b1, W2, b2 contiguous in packed order";
+    return MLP_ERR_UNSUPPORTED;
+  }
+  const int64_t b = batch_of(c);
+  if (b % 32 != 0) {
+    *err = "large-N training needs a minibatch that is a multiple of 32 rows";
+    return MLP_ERR_UNSUPPORTED;
+  }
+  Plan pl;
+  std::string why;
+  if (!plan_for(c, n_cu, &pl, &why)) {
+    *err = "no grid for this shape: " + why;
+    return MLP_ERR_UNSUPPORTED;
+  }
+  const WsLayout wl = ws_layout(c, pl.Gi, pl.Gj);
+  if (!ws || ws_bytes < wl.total) {
+    *err = "workspace too small for the large-N trainer";
+    return MLP_ERR_WORKSPACE;
+  }
+  char *w = static_cast<char *>(ws);
+  mlpk::LargeArgs a{};
+  a.X = X;
+  a.T = T;
+  a.theta = theta.W1;
+  a.comp = comp;
+  a.loss_hist = loss_hist;
+  a.z2p = reinterpret_cast<float *>(w + wl.z2p);
+  a.gp = reinterpret_cast<float *>(w + wl.gp);
+  a.lossp = reinterpret_cast<float *>(w + wl.lossp);
+  a.amax = reinterpret_cast<float *>(w + wl.amax);
+  a.acc = reinterpret_cast<float *>(w + wl.acc);
+  a.bar = reinterpret_cast<unsigned *>(w + wl.bar);
+  a.N = c.n_rows;
+  a.b = b;
+  a.D = (int)D;
+  a.H = (int)H;
+  a.Hp = pl.Hp;
+  a.K = (int)K;
+  a.Gi = pl.Gi;
+  a.Gj = pl.Gj;
+  a.epochs = epochs;
+  a.steps_per_epoch = (int)((c.n_rows + b - 1) / b);
+  a.lr = c.lr;
+
+  hipLaunchKernelGGL(mlpk::k_zero_u32, dim3(1), dim3(64), 0, s, a.bar, 4);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) { *err = hipGetErrorString(e); return MLP_ERR_HIP; }
+
+  const void *kern = c.prec == MLP_FP32 ? (const void *)mlpk::k_large_train<0>
+                   : c.prec == MLP_BF16 ? (const void *)mlpk::k_large_train<1>
+                                        : (const void *)mlpk::k_large_train<2>;
+  e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.lds);
+  if (e != hipSuccess) { *err = std::string("hipFuncSetAttribute: ") + hipGetErrorString(e); return MLP_ERR_HIP; }
+  int per_cu = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, mlpk::kLT, pl.lds);
+  if (e != hipSuccess) { *err = std::string("occupancy query: ") + hipGetErrorString(e); return MLP_ERR_HIP; }
+  const int G = pl.Gi * pl.Gj;
+  if (per_cu * n_cu < G) {
+    *err = "grid of " + std::to_string(G) + " workgroups cannot be co-resident (" +
+           std::to_string(per_cu) + " per CU)";
+    return MLP_ERR_UNSUPPORTED;
+  }
+  void *args[] = {&a};
+  e = hipLaunchCooperativeKernel(kern, dim3(G), dim3(mlpk::kLT), args, (unsigned)pl.lds, s);
+  if (e != hipSuccess) { *err = std::string("cooperative launch: ") + hipGetErrorString(e); return MLP_ERR_HIP; }
+  return MLP_OK;
 }
 
 }  // namespace mlph

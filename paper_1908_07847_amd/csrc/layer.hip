@@ -13,6 +13,8 @@
 //                  its gradient over all rows in row order, so the result
 //                  is bitwise repeatable.
 //  k_step          theta <- theta - lr g, optionally Kahan-compensated.
+#include <algorithm>
+
 #include "mlp_device.hpp"
 
 namespace mlpk {
@@ -37,13 +39,13 @@ __global__ __launch_bounds__(256) void k_forward(int64_t n, int D, int H, int K,
 }
 
 __global__ __launch_bounds__(256) void k_backward_rows(
-    int64_t n, int D, int H, int K, const float *__restrict__ A, const float *__restrict__ Y,
+    int64_t n, int64_t n_total, int D, int H, int K, const float *__restrict__ A, const float *__restrict__ Y,
     const float *__restrict__ dY, const float *__restrict__ T, mlp_params p,
     float *__restrict__ dX, float *__restrict__ d1_out, float *__restrict__ d2_out,
     float *__restrict__ sq_out) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
-  const float mse_scale = 2.0f / ((float)n * (float)K);
+  const float mse_scale = 2.0f / ((float)n_total * (float)K);
   float sq = 0.0f;
   for (int k = 0; k < K; ++k) {
     float y = Y[r * K + k];
@@ -75,9 +77,9 @@ __global__ __launch_bounds__(256) void k_backward_rows(
 
 // Parameter index q in packed order [W1 | b1 | W2 | b2], plus q == P for the loss.
 __global__ __launch_bounds__(256) void k_backward_sum(
-    int64_t n, int D, int H, int K, const float *__restrict__ X, const float *__restrict__ A,
-    const float *__restrict__ d1, const float *__restrict__ d2, const float *__restrict__ sq,
-    mlp_params g, float *__restrict__ loss) {
+    int64_t n, int64_t n_total, int accumulate, int D, int H, int K, const float *__restrict__ X,
+    const float *__restrict__ A, const float *__restrict__ d1, const float *__restrict__ d2,
+    const float *__restrict__ sq, mlp_params g, float *__restrict__ loss) {
   const int64_t P = (int64_t)D * H + H + (int64_t)H * K + K;
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q > P) return;
@@ -85,23 +87,24 @@ __global__ __launch_bounds__(256) void k_backward_sum(
   if (q < (int64_t)D * H) {
     const int h = (int)(q / D), d = (int)(q - (int64_t)h * D);
     for (int64_t r = 0; r < n; ++r) s += d1[r * H + h] * X[r * D + d];
-    g.W1[q] = s;
+    g.W1[q] = accumulate ? g.W1[q] + s : s;
   } else if (q < (int64_t)D * H + H) {
     const int h = (int)(q - (int64_t)D * H);
     for (int64_t r = 0; r < n; ++r) s += d1[r * H + h];
-    g.b1[h] = s;
+    g.b1[h] = accumulate ? g.b1[h] + s : s;
   } else if (q < (int64_t)D * H + H + (int64_t)H * K) {
     const int64_t o = q - ((int64_t)D * H + H);
     const int k = (int)(o / H), h = (int)(o - (int64_t)k * H);
     for (int64_t r = 0; r < n; ++r) s += d2[r * K + k] * A[r * H + h];
-    g.W2[o] = s;
+    g.W2[o] = accumulate ? g.W2[o] + s : s;
   } else if (q < P) {
     const int k = (int)(q - ((int64_t)D * H + H + (int64_t)H * K));
     for (int64_t r = 0; r < n; ++r) s += d2[r * K + k];
-    g.b2[k] = s;
+    g.b2[k] = accumulate ? g.b2[k] + s : s;
   } else if (loss) {
     for (int64_t r = 0; r < n; ++r) s += sq[r];
-    loss[0] = s / ((float)n * (float)K);
+    s = s / ((float)n_total * (float)K);
+    loss[0] = accumulate ? loss[0] + s : s;
   }
 }
 
@@ -135,19 +138,30 @@ hipError_t launch_forward(int64_t n, int D, int H, int K, const float *X, mlp_pa
   return hipGetLastError();
 }
 
-// ws layout (floats): delta1 [n][H] | delta2 [n][K] | sq [n]
-hipError_t launch_backward(int64_t n, int D, int H, int K, const float *X, const float *A,
-                           const float *Y, const float *dY, const float *T, mlp_params p,
-                           mlp_params g, float *dX, float *loss, float *ws, hipStream_t s) {
-  float *d1 = ws, *d2 = ws + n * H, *sq = d2 + n * K;
-  hipLaunchKernelGGL(mlpk::k_backward_rows, grid_for(n, 256), dim3(256), 0, s, n, D, H, K, A, Y,
-                     dY, T, p, dX, d1, d2, sq);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+// ws layout (floats): delta1 [chunk][H] | delta2 [chunk][K] | sq [chunk].  Rows
+// are processed in chunks of at most ws_rows; each chunk's sums are
+// added to the previous ones in chunk order (fixed, so still repeatable).
+hipError_t launch_backward(int64_t n, int64_t ws_rows, int D, int H, int K, const float *X,
+                           const float *A, const float *Y, const float *dY, const float *T,
+                           mlp_params p, mlp_params g, float *dX, float *loss, float *ws,
+                           hipStream_t s) {
+  const int64_t chunk = std::min<int64_t>(n, ws_rows);
+  float *d1 = ws, *d2 = ws + chunk * H, *sq = d2 + chunk * K;
   const int64_t P = (int64_t)D * H + H + (int64_t)H * K + K;
-  hipLaunchKernelGGL(mlpk::k_backward_sum, grid_for(P + 1, 256), dim3(256), 0, s, n, D, H, K, X,
-                     A, d1, d2, sq, g, dY ? nullptr : loss);
-  return hipGetLastError();
+  for (int64_t r0 = 0; r0 < n; r0 += chunk) {
+    const int64_t m = std::min(chunk, n - r0);
+    hipLaunchKernelGGL(mlpk::k_backward_rows, grid_for(m, 256), dim3(256), 0, s, m, n, D, H, K,
+                       A + r0 * H, Y + r0 * K, dY ? dY + r0 * K : nullptr, T ? T + r0 * K : nullptr,
+                       p, dX ? dX + r0 * D : nullptr, d1, d2, sq);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(mlpk::k_backward_sum, grid_for(P + 1, 256), dim3(256), 0, s, m, n,
+                       r0 > 0 ? 1 : 0, D, H, K, X + r0 * D, A + r0 * H, d1, d2, sq, g,
+                       dY ? nullptr : loss);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_step(int D, int H, int K, mlp_params p, mlp_params g, float *comp, float lr,

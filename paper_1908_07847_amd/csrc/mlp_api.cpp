@@ -80,7 +80,8 @@ bool small_path(const mlp_config &c) {
 }
 
 size_t backward_ws_bytes(const mlp_config &c) {
-  return sizeof(float) * (size_t)c.n_rows * (size_t)(c.n_hidden + c.n_out + 1);
+  const int64_t rows = std::min<int64_t>(c.n_rows, mlph::kBackwardChunk);
+  return sizeof(float) * (size_t)rows * (size_t)(c.n_hidden + c.n_out + 1);
 }
 
 }  // namespace
@@ -176,9 +177,6 @@ mlp_status mlp_backward(mlp_net *net, const float *X, const float *A, const floa
   if (!dY && !T) return fail(MLP_ERR_ARG, "either dY or T must be given");
   if (n <= 0) return fail(MLP_ERR_SHAPE, "n must be positive");
   const mlp_config &c = net->cfg;
-  if (n > c.n_rows)
-    return fail(MLP_ERR_SHAPE, "n = %lld rows exceeds the n_rows = %lld the workspace was sized for",
-                (long long)n, (long long)c.n_rows);
   mlp_status s = check_params(grads, "grads");
   if (s != MLP_OK) return s;
   const void *ptrs[] = {A, Y, dY, T, dX, loss};
@@ -187,8 +185,10 @@ mlp_status mlp_backward(mlp_net *net, const float *X, const float *A, const floa
   if (!aligned16(X)) return fail(MLP_ERR_ALIGN, "X must be 16-byte aligned");
   if (!net->ws || net->ws_bytes < backward_ws_bytes(c))
     return fail(MLP_ERR_WORKSPACE, "backward needs %zu workspace bytes", backward_ws_bytes(c));
-  hipError_t e = mlph::launch_backward(n, c.n_in, c.n_hidden, c.n_out, X, A, Y, dY, T, net->theta,
-                                       grads, dX, loss, (float *)net->ws, (hipStream_t)stream);
+  const int64_t ws_rows = std::min<int64_t>(c.n_rows, mlph::kBackwardChunk);
+  hipError_t e = mlph::launch_backward(n, ws_rows, c.n_in, c.n_hidden, c.n_out, X, A, Y, dY, T,
+                                       net->theta, grads, dX, loss, (float *)net->ws,
+                                       (hipStream_t)stream);
   return e == hipSuccess ? MLP_OK : hip_fail(e, "mlp_backward launch");
 }
 

@@ -10,9 +10,44 @@ namespace mlpk {
 constexpr int kWave = 64;
 constexpr int kLayerMaxOut = 16;  // outputs supported by the generic layer kernels
 
-// Equation 1 of the paper: sigma(z) = 1 / (1 + e^-z).  expf is the accurate
-// device exponential; exp(-z) overflowing to +inf gives 0, the right limit.
-__device__ __forceinline__ float sigmoid(float z) { return 1.0f / (1.0f + expf(-z)); }
+// Logistic sigmoid (Equation 1) from the hardware base-2 exponential and
+// reciprocal.  e^-z = 2^(-z log2 e); the product -z log2 e is carried in two
+// parts (its rounded value and the exact rounding error from an FMA, plus
+// the tail of log2 e), so the exponent keeps ~48 bits and the result is
+// within a few float ulps of the exact sigmoid (checked against float64 in
+// the tests).  One Newton step sharpens the hardware reciprocal.  For
+// z < -87 the exponent is clamped at 2^126 (sigma ~ 1e-38 instead of 0).
+__device__ __forceinline__ float sigmoid_e(float z, float &e_out) {
+  const float L_HI = 1.44269502162933349609375f;    // float(log2 e)
+  const float L_LO = 1.925963033500011079e-08f;     // log2 e - L_HI
+  const float LN2 = 0.693147180559945309f;
+  float th = -z * L_HI;
+  float err = fmaf(-z, L_HI, -th);
+  float tl = fmaf(-z, L_LO, err);
+  th = fminf(th, 126.0f);
+  float e = __builtin_amdgcn_exp2f(th);
+  e = fmaf(e, tl * LN2, e);
+  float d = 1.0f + e;
+  float r = __builtin_amdgcn_rcpf(d);
+  r = fmaf(r, fmaf(-d, r, 1.0f), r);
+  e_out = e;
+  return r;
+}
+
+__device__ __forceinline__ float sigmoid(float z) {
+  float e;
+  return sigmoid_e(z, e);
+}
+
+// sigma(z) and its slope sigma(z) (1 - sigma(z)) = e^-z sigma(z)^2.  The
+// second form keeps full relative precision where sigma is close to 1 (there
+// 1 - sigma would cancel); for z < -87 it underflows to 0 instead of ~1e-38.
+__device__ __forceinline__ float sigmoid_slope(float z, float &slope) {
+  float e;
+  const float a = sigmoid_e(z, e);
+  slope = (e * a) * a;
+  return a;
+}
 
 // theta <- theta - lr*g.  With a compensation term c (Kahan summation of the
 // update stream) the low-order bits lost when a small step is added to a
@@ -42,9 +77,12 @@ __device__ __forceinline__ int round_up(int v, int m) { return (v + m - 1) / m *
 // Launch wrappers implemented in the .hip files and used by the host API.
 namespace mlph {
 
+// Rows of one pass of the generic backward kernels (bounds their workspace).
+constexpr int64_t kBackwardChunk = 16384;
+
 // Small-network trainer: one workgroup per net, all epochs in one launch.
 // items == nullptr means a single net described by `one`.
-size_t small_lds_bytes(int n_rows, int n_hidden, int n_in);
+size_t small_lds_bytes(int n_rows, int n_hidden, int n_in, int threads);
 hipError_t launch_small_train(const mlp_batch_item *items, mlp_batch_item one, int n_nets,
                               int n_in, int n_out, int max_rows, int max_hidden, const float *X,
                               const float *T, float *theta, float *comp, int epochs,
@@ -53,9 +91,10 @@ hipError_t launch_small_train(const mlp_batch_item *items, mlp_batch_item one, i
 // Generic layer kernels (any sizes) for mlp_forward / mlp_backward / mlp_step.
 hipError_t launch_forward(int64_t n, int D, int H, int K, const float *X, mlp_params p, float *A,
                           float *Y, hipStream_t s);
-hipError_t launch_backward(int64_t n, int D, int H, int K, const float *X, const float *A,
-                           const float *Y, const float *dY, const float *T, mlp_params p,
-                           mlp_params g, float *dX, float *loss, float *ws, hipStream_t s);
+hipError_t launch_backward(int64_t n, int64_t ws_rows, int D, int H, int K, const float *X,
+                           const float *A, const float *Y, const float *dY, const float *T,
+                           mlp_params p, mlp_params g, float *dX, float *loss, float *ws,
+                           hipStream_t s);
 hipError_t launch_step(int D, int H, int K, mlp_params p, mlp_params g, float *comp, float lr,
                        hipStream_t s);
 

@@ -1,0 +1,189 @@
+"""GPU parity of the large-N minibatch trainer (persistent kernel, MFMA
+contractions) against the FP64 oracle, on the same seeded inputs.
+
+float32: max|gpu - oracle| / max|oracle| <= 1e-5 per tensor and for the loss
+history.  bf16 / e4m3: one step from identical parameters against the oracle
+that rounds the same contraction operands the same way (only the summation
+order differs, plus the rare operand whose float32 and float64 values round
+to different neighbours); several steps against the exact float64 oracle are
+reported with sanity bounds.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import Params
+from paper_1908_07847_amd import synth
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def M():
+    from paper_1908_07847_amd import mlp
+    return mlp
+
+
+def normwise(got, ref):
+    got, ref = np.asarray(got, np.float64), np.asarray(ref, np.float64)
+    return float(np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-30))
+
+
+def errors(flat_gpu, q: Params):
+    d, h, k = q.shape
+    g = synth.Theta.unpack(flat_gpu, d, h, k)
+    return dict(W1=normwise(g.W1, q.W1), b1=normwise(g.b1, q.b1), W2=normwise(g.W2, q.W2),
+                b2=normwise(g.b2, q.b2))
+
+
+def gpu_train(M, X, T, theta, epochs, batch, lr=0.1, prec="fp32", compensated=True):
+    net = M.Net(X.shape[1], theta.W1.shape[0], T.shape[1], X.shape[0], batch=batch, lr=lr, prec=prec,
+                compensated=compensated, theta=theta)
+    Xd, Td = torch.from_numpy(np.ascontiguousarray(X)).cuda(), torch.from_numpy(np.ascontiguousarray(T)).cuda()
+    hist = net.train(Xd, Td, epochs)
+    torch.cuda.synchronize()
+    return net, net.flat.cpu().numpy(), hist.cpu().numpy()
+
+
+def fp32_case(M, X, T, th, epochs, batch, lr=0.1, tol=TOL, label=""):
+    say(f"{label}: N={X.shape[0]} D={X.shape[1]} H={th.W1.shape[0]} K={T.shape[1]} batch={batch} epochs={epochs}")
+    _, flat, hist = gpu_train(M, X, T, th, epochs, batch, lr=lr)
+    q, ref_hist = oracle.train(X, T, Params.of(th), lr, epochs, batch=batch)
+    errs = errors(flat, q)
+    lerr = normwise(hist, ref_hist)
+    say(f"  errors {errs} loss {lerr:.2e}")
+    for name, e in errs.items():
+        assert e <= tol, (name, errs)
+    assert lerr <= tol
+
+
+def test_workload4_shape_prefix_fp32(M):
+    w = synth.single(4, n_rows=8 * 4096)
+    fp32_case(M, w["X"], w["T"], w["theta"], 2, 4096, label="workload 4 prefix (16 steps)")
+
+
+def test_workload5_shape_prefix_fp32(M):
+    w = synth.single(5, n_rows=2 * 16384)
+    fp32_case(M, w["X"], w["T"], w["theta"], 1, 16384, label="workload 5 prefix (2 steps)")
+
+
+@pytest.mark.parametrize("n,d,h,k,batch,epochs", [
+    (5000, 20, 100, 2, 1024, 2),     # ragged last minibatch, hidden padded 100 -> 128
+    (2048, 64, 64, 4, 2048, 3),      # full batch, every limit of D and K
+    (4096, 7, 300, 1, 512, 1),       # K = 1, hidden block split, D far from a multiple of 4
+    (96, 33, 16, 3, 32, 4),          # tiny: three 32-row minibatches
+])
+def test_ragged_and_edge_shapes_fp32(M, n, d, h, k, batch, epochs):
+    g = np.random.default_rng(n + d + h)
+    X = g.standard_normal((n, d)).astype(np.float32)
+    T = np.eye(k, dtype=np.float32)[g.integers(0, k, n)] if k > 1 else g.integers(0, 2, (n, 1)).astype(np.float32)
+    th = synth.theta0(d, h, k, g)
+    fp32_case(M, X, T, th, epochs, batch, lr=0.3, label="edge")
+
+
+def test_large_runs_are_bitwise_repeatable_and_resumable(M):
+    w = synth.single(4, n_rows=4 * 4096)
+    _, a, ha = gpu_train(M, w["X"], w["T"], w["theta"], 3, 4096)
+    _, b, hb = gpu_train(M, w["X"], w["T"], w["theta"], 3, 4096)
+    assert np.array_equal(a, b) and np.array_equal(ha, hb)
+    net = M.Net(33, 256, 3, 4 * 4096, batch=4096, theta=w["theta"])
+    Xd, Td = torch.from_numpy(w["X"]).cuda(), torch.from_numpy(w["T"]).cuda()
+    h1 = net.train(Xd, Td, 1).cpu().numpy()
+    h2 = net.train(Xd, Td, 2).cpu().numpy()
+    assert np.array_equal(net.flat.cpu().numpy(), a)
+    assert np.array_equal(np.concatenate([h1, h2]), ha)
+
+
+def test_large_lr_zero_leaves_parameters_bitwise(M):
+    w = synth.single(4, n_rows=2 * 4096)
+    _, flat, _ = gpu_train(M, w["X"], w["T"], w["theta"], 2, 4096, lr=0.0)
+    assert np.array_equal(flat, w["theta"].packed())
+
+
+def test_full_workload4_trains_and_is_deterministic(M):
+    """The whole 1,048,576-row workload for 2 epochs: properties that hold at any size."""
+    w = synth.single(4)
+    _, a, ha = gpu_train(M, w["X"], w["T"], w["theta"], 2, 4096)
+    _, b, hb = gpu_train(M, w["X"], w["T"], w["theta"], 2, 4096)
+    assert np.array_equal(a, b) and np.array_equal(ha, hb)
+    assert np.all(np.isfinite(a)) and ha[1] < ha[0]
+    # the first epoch's first minibatches equal a run on that prefix alone
+    say(f"  full workload 4: loss per epoch {ha}")
+
+
+def rounding_flip_bound(d1, bp, Xq, prec, ed, lr):
+    """Bound on |dW1_gpu - dW1_oracle| per entry from delta1 operands that lie so
+    close to a rounding tie of the operand format that the kernel's float32 delta1
+    may round to the other neighbour.  The kernel's delta1 = (delta2 W2) a (1 - a)
+    carries an absolute error of about |delta2 W2| * 1e-6 (the float32 activation
+    a, and hence a (1 - a), is good to ~1e-7 absolute; the margin is 10x) plus a few
+    float32 ulps of the product.  Such an operand may differ from the oracle's
+    rounded value by one spacing of the format; every other operand is identical.
+    Returns (bound [H][D], fraction of delta1 entries that are ambiguous)."""
+    unc = 1e-6 * np.abs(bp) + 1e-6 * np.abs(d1)
+    s = 2.0 ** ed if prec == "e4m3" else 1.0
+    au, us = np.abs(d1 * s), unc * s
+    ex = np.floor(np.log2(np.where(au > 0, au, 1.0)))
+    spacing = 2.0 ** (ex - 7) if prec == "bf16" else 2.0 ** (np.maximum(ex, -6) - 3)
+    frac = au / spacing - np.floor(au / spacing)
+    amb = np.abs(frac - 0.5) * spacing <= us
+    dq = np.where(amb, spacing / s, 0.0)
+    return lr * (dq.T @ np.abs(Xq)), float(amb.mean())
+
+
+@pytest.mark.parametrize("prec", ["bf16", "e4m3"])
+def test_lowp_single_step_matches_emulating_oracle(M, prec):
+    """One step from identical parameters against the oracle that rounds the same
+    operands the same way.  W2, b1, b2 (and the loss) do not depend on any rounding
+    decision the two sides could take differently: 1e-5.  W1 may differ where a
+    delta1 operand sits on a rounding tie (see rounding_flip_bound), plus the
+    float32 summation of the gradient (1e-6 of the sum of |terms|)."""
+    lr = 0.1
+    for wl, n, batch in [(4, 4096, 4096), (5, 16384, 16384)]:
+        w = synth.single(wl, n_rows=n)
+        _, flat, hist = gpu_train(M, w["X"], w["T"], w["theta"], 1, batch, lr=lr, prec=prec)
+        q, ref_hist, slog, d1, bp = oracle.train_lowp(w["X"], w["T"], Params.of(w["theta"]), lr, 1, batch,
+                                                      prec, first_step_detail=True)
+        p0 = Params.of(w["theta"])
+        d, h, k = p0.shape
+        g = synth.Theta.unpack(flat, d, h, k)
+        for name in ("b1", "W2", "b2"):
+            du = getattr(g, name).astype(np.float64) - getattr(p0, name)
+            dr = getattr(q, name) - getattr(p0, name)
+            e = normwise(du, dr)
+            say(f"  {prec} workload {wl} single step: update error {name} {e:.2e}")
+            assert e <= TOL, (name, e)
+        assert abs(hist[0] - ref_hist[0]) <= TOL * ref_hist[0]
+        ex, ed = (int(slog[0, 0]), int(slog[0, 2])) if prec == "e4m3" else (0, 0)
+        Xq = oracle.round_array(w["X"], prec, ex)
+        d1q = oracle.round_array(d1, prec, ed)
+        bound, amb = rounding_flip_bound(d1, bp, Xq, prec, ed, lr)
+        bound += lr * 1e-6 * (np.abs(d1q).T @ np.abs(Xq))
+        du = g.W1.astype(np.float64) - p0.W1
+        dr = q.W1 - p0.W1
+        excess = np.abs(du - dr) - bound
+        say(f"  {prec} workload {wl} single step: W1 update error {normwise(du, dr):.2e} "
+            f"(ambiguous delta1 operands {amb:.2e}, worst margin {excess.max():.2e})")
+        assert np.all(excess <= 0.0)
+
+
+@pytest.mark.parametrize("prec,loss_tol,w_tol", [("bf16", 1e-3, 1e-2), ("e4m3", 5e-2, 1e-1)])
+def test_lowp_many_steps_error_vs_exact_oracle(M, prec, loss_tol, w_tol):
+    w = synth.single(4, n_rows=16 * 4096)
+    _, flat, hist = gpu_train(M, w["X"], w["T"], w["theta"], 2, 4096, prec=prec)
+    q, ref_hist = oracle.train(w["X"], w["T"], Params.of(w["theta"]), 0.1, 2, batch=4096)
+    errs = errors(flat, q)
+    lerr = float(np.max(np.abs(hist - ref_hist) / ref_hist))
+    say(f"  {prec} vs exact float64 after 32 steps: params {errs} loss {lerr:.2e}")
+    assert lerr <= loss_tol
+    for name, e in errs.items():
+        assert e <= w_tol, (name, errs)

@@ -260,3 +260,37 @@ def test_batched_results_do_not_depend_on_order_or_company(M, batched_full):
     assert np.array_equal(ha, hb)
     s = _net_slice(w, items[10])
     assert np.array_equal(a[s], c[s]) and np.array_equal(ha[10], hc[0])
+
+
+def test_device_sigmoid_accuracy_through_forward(M):
+    """A 1-1-1 net with W1 = 1, b1 = 0 makes the hidden activation exactly sigma(x)
+    (Equation 1); compare it with float64 over [-85, 85] and check the limits."""
+    x = np.concatenate([np.linspace(-85, 85, 200001), [-1e4, -200.0, 200.0, 1e4, 0.0]]).astype(np.float32)
+    th = synth.Theta(np.ones((1, 1), np.float32), np.zeros(1, np.float32), np.ones((1, 1), np.float32),
+                     np.zeros(1, np.float32))
+    net = M.Net(1, 1, 1, x.size, theta=th)
+    A, _ = net.forward(torch.from_numpy(x[:, None].copy()).cuda())
+    a = A.cpu().numpy()[:, 0].astype(np.float64)
+    ref = 1.0 / (1.0 + np.exp(-x.astype(np.float64)))
+    core = np.abs(x) <= 85
+    rel = np.abs(a[core] - ref[core]) / ref[core]
+    say(f"  sigmoid max relative error {rel.max():.3e} ({rel.max() / 2**-24:.1f} half-ulps)")
+    assert rel.max() <= 4 * 2.0 ** -23
+    assert a[-1] == 0.5 and a[-2] == 1.0 and a[-3] == 1.0
+    assert 0.0 <= a[-5] <= 1e-37 and 0.0 <= a[-4] <= 1e-37
+
+
+def test_backward_over_many_row_chunks(M):
+    """More rows than one backward pass holds: chunk sums are added in order."""
+    g = np.random.default_rng(8)
+    n, d, h, k = 40000, 10, 8, 3
+    X = g.standard_normal((n, d)).astype(np.float32)
+    T = np.eye(k, dtype=np.float32)[g.integers(0, k, n)]
+    th = synth.theta0(d, h, k, g)
+    net = M.Net(d, h, k, n, theta=th)
+    Xd, Td = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+    A, Y = net.forward(Xd)
+    gr, _, loss = net.backward(Xd, A, Y, T=Td)
+    L, ref = oracle.loss_grad(X, T, Params.of(th))
+    assert normwise(gr.flat.cpu().numpy(), ref.flat()) <= TOL
+    assert abs(loss.item() - L) <= TOL * L
