@@ -1,15 +1,22 @@
 """Training throughput of the one-hidden-layer sigmoid MLP trainer on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload w2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload w2] [--prec fp32]
 
-A step is one pass of the whole hot path over one batch: forward, error,
-backpropagation and the gradient-descent update (arxiv 1908.07847,
-section 2.2).  The default workload is the differentiation workload
-(N=120 rows x 33 features, 33-16-3 net, full batch, so a step is one
-epoch); the timed region is K steps in one mlp_train call, with inputs
-already resident in HBM.  The JSON line carries the roofline of the
-dominant kernel (timed with HIP events on the stream it runs on) and the
-FP64 CPU oracle's throughput on the host cores.
+The metric is training samples*epochs/s: rows processed by full training
+steps (forward, error, backpropagation, gradient-descent update; arxiv
+1908.07847 section 2.2) per second, with inputs already resident in HBM.
+
+Workloads (all synthetic, from the seeded generator):
+  w1   60 rows x 33 features, 33-10-3 net, full batch           step = 1 epoch
+  w2   120 rows x 33 features, 33-16-3 net, full batch (default) step = 1 epoch
+  w3   4096 independent nets, H~U{4..64}, 40..120 rows each    step = 1 epoch of every net
+  w4   1,048,576 x 33, 33-256-3, minibatch 4096               step = 1 epoch (256 minibatches)
+  w5   4,194,304 x 64, 64-1024-3, minibatch 16384             step = 1 epoch (256 minibatches)
+w4/w5 take --prec fp32|bf16|e4m3 (operand precision of the two contractions).
+The timed region is one training call of K steps (one kernel launch).  The
+JSON line carries the roofline of that kernel, timed with HIP events on the
+stream it runs on, and the FP64 CPU oracle's throughput on a bounded sample
+of the same workload on the host cores.
 """
 from __future__ import annotations
 
@@ -24,7 +31,9 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X published fp32 vector peak (256 CUs, 2.4 GHz)
+# MI355X published peaks (dense): fp32 vector/matrix 157.3 TFLOP/s, bf16 2.5
+# PFLOP/s, fp8 5.0 PFLOP/s, HBM 8 TB/s.
+PEAK = {"fp32": 157.3, "bf16": 2516.6, "e4m3": 5033.2}
 PEAK_HBM_GBS = 8000.0
 
 
@@ -41,6 +50,11 @@ def flops_per_sample_epoch(D: int, H: int, K: int) -> int:
     return 4 * D * H + 6 * H * K + 7 * H + 11 * K
 
 
+def contraction_flops_per_sample(D: int, H: int) -> int:
+    """The two MFMA contractions, X W1^T and delta1^T X: 2DH each."""
+    return 4 * D * H
+
+
 def cpu_info() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -51,85 +65,164 @@ def cpu_info() -> str:
     return "unknown"
 
 
-def bench_w2(args):
+def timed(fn, stream):
+    import torch
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    fn()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, ev0.elapsed_time(ev1) / 1e3
+
+
+# ---------------------------------------------------------------- single nets (w1, w2, w4, w5)
+def bench_single(args):
     import torch
     from paper_1908_07847_amd import mlp, synth
 
-    w = synth.single(2)
+    wl = int(args.workload[1])
+    w = synth.single(wl)
     D, H, K, N = w["D"], w["H"], w["K"], w["X"].shape[0]
-    net = mlp.Net(D, H, K, N, lr=w["lr"], theta=w["theta"])
+    batch = w["batch"] or N
+    prec = args.prec if wl in (4, 5) else "fp32"
+    net = mlp.Net(D, H, K, N, batch=w["batch"], lr=w["lr"], prec=prec, theta=w["theta"])
     X = torch.from_numpy(w["X"]).cuda()
     T = torch.from_numpy(w["T"]).cuda()
-    steps, warmup = args.steps, args.warmup
+    steps = args.steps if args.steps is not None else w["epochs"]
+    warmup = args.warmup if args.warmup is not None else (100 if wl <= 2 else 1)
     hist = torch.empty(max(steps, warmup, 1), device="cuda")
     if warmup:
         net.train(X, T, warmup, loss_hist=hist[:warmup])
-    torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    net.train(X, T, steps, loss_hist=hist[:steps])       # one launch runs all K steps
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kern_s = ev0.elapsed_time(ev1) / 1e3
+    wall, kern = timed(lambda: net.train(X, T, steps, loss_hist=hist[:steps]), stream)
     P = D * H + H + H * K + K
-    flops = (flops_per_sample_epoch(D, H, K) * N + 2 * P) * steps
-    achieved = flops / kern_s / 1e12
+    n_updates = steps * (-(-N // batch))
+    if wl in (4, 5):
+        flops = contraction_flops_per_sample(D, H) * N * steps
+        bound, peak, unit, kname = "mfma", PEAK[prec], "TFLOP/s", f"k_large_train<{prec}>"
+    else:
+        flops = flops_per_sample_epoch(D, H, K) * N * steps + 2 * P * n_updates
+        bound, peak, unit, kname = "alu", PEAK["fp32"], "TFLOP/s", "k_small_train<1024>"
+    achieved = flops / kern / 1e12
+    names = {1: "plain-small: N=60 x 33, 33-10-3, full batch",
+             2: "differentiation: N=120 x 33, 33-16-3, full batch (fused mlp_train)",
+             4: "large-N: N=1,048,576 x 33, 33-256-3, minibatch 4096",
+             5: "wide: N=4,194,304 x 64, 64-1024-3, minibatch 16384"}
     res = dict(
-        metric="training samples*epochs/s",
-        value=N * steps / wall,
-        unit="samples*epochs/s",
-        ms_per_step=wall * 1e3 / steps,
-        dtype="f32",
-        config={"workload": "differentiation: N=120 x 33 features, 33-16-3 sigmoid MLP, MSE, full-batch GD "
-                            "lr=0.1, fused mlp_train (one launch for all steps)",
-                "n_rows": N, "n_in": D, "n_hidden": H, "n_out": K, "batch": N, "lr": w["lr"],
-                "compensated_update": True},
-        roofline={"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                  "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
-                  "kernel": "k_small_train", "kernel_ms": kern_s * 1e3, "flops_per_launch": flops},
-        final_loss=float(hist[steps - 1].item()) if steps else None,
-    )
-    return res, w
+        metric="training samples*epochs/s", value=N * steps / wall, unit="samples*epochs/s",
+        ms_per_step=wall * 1e3 / steps, dtype={"fp32": "f32", "bf16": "bf16", "e4m3": "e4m3"}[prec],
+        config={"workload": names[wl] + ", sigmoid both layers, MSE, GD lr=0.1", "n_rows": N, "n_in": D,
+                "n_hidden": H, "n_out": K, "batch": batch, "lr": w["lr"], "compensated_update": True,
+                "operand_precision": prec, "step": "one epoch"},
+        roofline={"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
+                  "traffic": None, "kernel": kname, "kernel_ms": kern * 1e3, "flops_per_launch": flops},
+        final_loss=float(hist[steps - 1].item()) if steps else None, steps=steps, warmup=warmup)
+    return res, dict(w=w, wl=wl, batch=batch)
 
 
-def cpu_baseline_w2(w, budget_s: float):
+def cpu_single(ctx, budget_s: float):
     import oracle
-    X, T, p = w["X"], w["T"], oracle.Params.of(w["theta"])
-    N = X.shape[0]
-    # one run of the whole workload (5000 epochs); repeat until the budget is used
-    reps, t_total, epochs_total = 0, 0.0, 0
-    epochs = w["epochs"]
-    while t_total < budget_s and reps < 50:
+    w, wl, batch = ctx["w"], ctx["wl"], ctx["batch"]
+    p = oracle.Params.of(w["theta"])
+    if wl in (1, 2):
+        X, T, epochs, rows = w["X"], w["T"], w["epochs"], w["X"].shape[0]
+        sample = f"the full workload ({rows} rows x {epochs} epochs)"
+    else:
+        rows = batch * (4 if wl == 4 else 1)   # a few minibatches of the same data
+        X, T, epochs = w["X"][:rows], w["T"][:rows], 1
+        sample = f"the first {rows} rows ({rows // batch} minibatch(es) of {batch}) for 1 epoch"
+    reps, t_total = 0, 0.0
+    while (t_total < budget_s or reps == 0) and reps < 50:
         t0 = time.perf_counter()
-        oracle.train(X, T, p, w["lr"], epochs)
+        oracle.train(X, T, p, w["lr"], epochs, batch=0 if wl in (1, 2) else batch)
         t_total += time.perf_counter() - t0
-        epochs_total += epochs
         reps += 1
-    return {"value": N * epochs_total / t_total, "unit": "samples*epochs/s", "cores": 1, "kind": "oracle",
-            "sample": f"the full workload ({N} rows x {epochs} epochs) run {reps} time(s), float64, "
-                      f"single thread, {cpu_info()}", "seconds": t_total}
+    return {"value": rows * epochs * reps / t_total, "unit": "samples*epochs/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sample}, run {reps} time(s), float64, single thread, {cpu_info()}",
+            "seconds": t_total}
+
+
+# ---------------------------------------------------------------- batched (w3)
+def bench_batched(args):
+    import torch
+    from paper_1908_07847_amd import mlp, synth
+
+    w = synth.batched()
+    items = w["items"]
+    plan = mlp.BatchPlan(items)
+    X = torch.from_numpy(w["X"]).cuda()
+    T = torch.from_numpy(w["T"]).cuda()
+    th = torch.from_numpy(w["theta"]).cuda()
+    comp = torch.zeros_like(th)
+    steps = args.steps if args.steps is not None else w["epochs"]
+    warmup = args.warmup if args.warmup is not None else 5
+    if warmup:
+        mlp.train_batched(plan, X, T, th.clone(), torch.zeros_like(th), warmup, 33, 3)
+    hist = torch.empty((len(items), steps), device="cuda")
+    stream = torch.cuda.current_stream()
+    wall, kern = timed(lambda: mlp.train_batched(plan, X, T, th, comp, steps, 33, 3, loss_hist=hist), stream)
+    rows = sum(it["n_rows"] for it in items)
+    flops = 0
+    for it in items:
+        H = it["n_hidden"]
+        P = 33 * H + H + 3 * H + 3
+        flops += (flops_per_sample_epoch(33, H, 3) * it["n_rows"] + 2 * P) * steps
+    achieved = flops / kern / 1e12
+    res = dict(
+        metric="training samples*epochs/s", value=rows * steps / wall, unit="samples*epochs/s",
+        ms_per_step=wall * 1e3 / steps, dtype="f32",
+        config={"workload": "batched: 4096 independent 33-H-3 nets, H~U{4..64}, 40..120 rows each "
+                            "(5-fold CV splits), lr~logU(0.01,1), full batch, one launch",
+                "nets": len(items), "total_rows": rows, "step": "one epoch of every net"},
+        roofline={"bound": "alu", "achieved": achieved, "peak": PEAK["fp32"], "unit": "TFLOP/s",
+                  "frac": achieved / PEAK["fp32"], "traffic": None, "kernel": "k_small_train<256>",
+                  "kernel_ms": kern * 1e3, "flops_per_launch": flops}, steps=steps, warmup=warmup)
+    return res, dict(w=w)
+
+
+def cpu_batched(ctx, budget_s: float):
+    import oracle
+    w = ctx["w"]
+    items = w["items"][:64]
+    epochs = 100
+    threads = oracle.max_threads()
+    reps, t_total = 0, 0.0
+    while (t_total < budget_s or reps == 0) and reps < 50:
+        t0 = time.perf_counter()
+        oracle.train_many(items, w["X"], w["T"], w["theta"], 33, 3, epochs, threads=threads)
+        t_total += time.perf_counter() - t0
+        reps += 1
+    rows = sum(it["n_rows"] for it in items)
+    return {"value": rows * epochs * reps / t_total, "unit": "samples*epochs/s", "cores": threads,
+            "kind": "oracle", "sample": f"the first 64 nets for {epochs} epochs, run {reps} time(s), float64, "
+                                        f"one net per thread, {cpu_info()}", "seconds": t_total}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5000)
-    ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="w2", choices=["w2"])
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the workload's epochs)")
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", default="w2", choices=["w1", "w2", "w3", "w4", "w5"])
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16", "e4m3"])
     ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this trainer runs on one GPU; multi-GPU sharding is designed but not "
-                                   "built (--gpus must be 1)"}))
+        print(json.dumps({"error": "this trainer runs on one GPU; the multi-GPU sharding is designed, not "
+                                   "built, so --gpus must be 1"}))
         sys.exit(2)
-    res, w = bench_w2(args)
-    res.update(n_gpus=1, steps=args.steps, warmup=args.warmup, higher_is_better=True, scaling="weak",
-               vs_baseline=None, data="synthetic (seeded generator; the paper's clinical table is not available)")
-    res["cpu_baseline"] = None if args.no_cpu else cpu_baseline_w2(w, args.cpu_budget)
+    if args.workload == "w3":
+        res, ctx = bench_batched(args)
+        cpu = None if args.no_cpu else cpu_batched(ctx, args.cpu_budget)
+    else:
+        res, ctx = bench_single(args)
+        cpu = None if args.no_cpu else cpu_single(ctx, args.cpu_budget)
+    res.update(n_gpus=1, higher_is_better=True, scaling="weak", vs_baseline=None,
+               data="synthetic (seeded generator; the paper's clinical table is not available)")
+    res["cpu_baseline"] = cpu
     print(json.dumps(res), flush=True)
 
 

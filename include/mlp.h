@@ -159,6 +159,25 @@ mlp_status mlp_train_batched(const mlp_batch_item *items_host, const mlp_batch_i
                              float *comp_packed, int64_t total_params, int32_t epochs,
                              float *loss_hist, void *stream);
 
+/* ---- launch-shape hints -------------------------------------------------- */
+
+/* Overrides of launch shapes that do not change results beyond summation
+ * order (0 = the library's own choice).  Process-wide; set it before the
+ * calls it should affect, not concurrently with them.  It exists for an
+ * autotuner that times candidate shapes and remembers the fastest:
+ *   small_threads        threads per net in the small / batched trainer:
+ *                        256, 512 or 1024;
+ *   large_row_blocks,    the Gi x Gj grid of the large-N trainer (row blocks
+ *   large_hidden_blocks  of >= 32 rows, hidden blocks of <= 256 units). */
+typedef struct {
+  int32_t small_threads;
+  int32_t large_row_blocks;
+  int32_t large_hidden_blocks;
+  int32_t reserved; /* must be 0 */
+} mlp_launch_hint;
+
+mlp_status mlp_set_launch_hint(const mlp_launch_hint *hint /*host; NULL resets*/);
+
 const char *mlp_status_string(mlp_status s);
 const char *mlp_last_error(void);
 

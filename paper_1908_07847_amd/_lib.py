@@ -40,11 +40,16 @@ class BatchItem(ctypes.Structure):
                 ("reserved", ctypes.c_int32), ("x_off", ctypes.c_int64), ("p_off", ctypes.c_int64)]
 
 
-assert ctypes.sizeof(BatchItem) == 32 and ctypes.sizeof(Config) == 40
+class LaunchHint(ctypes.Structure):
+    _fields_ = [("small_threads", ctypes.c_int32), ("large_row_blocks", ctypes.c_int32),
+                ("large_hidden_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+assert ctypes.sizeof(BatchItem) == 32 and ctypes.sizeof(Config) == 40 and ctypes.sizeof(LaunchHint) == 16
 
 # Every symbol include/mlp.h declares.
 SYMBOLS = ["mlp_workspace_size", "mlp_init", "mlp_destroy", "mlp_forward", "mlp_backward", "mlp_step",
-           "mlp_train", "mlp_train_batched", "mlp_status_string", "mlp_last_error"]
+           "mlp_train", "mlp_train_batched", "mlp_set_launch_hint", "mlp_status_string", "mlp_last_error"]
 
 
 def _load():
@@ -62,7 +67,8 @@ def _load():
     lib.mlp_train.argtypes = [vp, vp, vp, i32, vp, vp]
     lib.mlp_train_batched.argtypes = [ctypes.POINTER(BatchItem), vp, i32, i32, i32, vp, vp, i64, vp, vp,
                                       i64, i32, vp, vp]
-    for name in SYMBOLS[:8]:
+    lib.mlp_set_launch_hint.argtypes = [ctypes.POINTER(LaunchHint)]
+    for name in SYMBOLS[:9]:
         getattr(lib, name).restype = ctypes.c_int
     lib.mlp_status_string.argtypes = [ctypes.c_int]
     lib.mlp_status_string.restype = ctypes.c_char_p

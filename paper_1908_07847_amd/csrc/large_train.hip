@@ -44,7 +44,6 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 constexpr int kLT = 256;     // threads per workgroup (4 waves)
 constexpr int kRC = 32;      // rows per chunk
 constexpr int kMaxD = 64;    // features
-constexpr int kMaxHW = 64;   // hidden units per wave
 constexpr int kMaxK = 4;     // outputs
 
 struct LargeArgs {
@@ -55,35 +54,79 @@ struct LargeArgs {
   float *lossp;      // [Gi] partial squared errors
   float *amax;       // [2][G] W1 amax partials, [2][G] delta1 amax partials
   float *acc;        // [4]: epoch loss accumulator, dataset |X| amax, ...
-  unsigned *bar;     // [2]: barrier counter, error flag
+  unsigned *bar;     // grid-barrier counters (see GridSync)
   int64_t N, b;
   int D, H, Hp, K, Gi, Gj, epochs, steps_per_epoch;
   float lr;
 };
 
 // ---------------------------------------------------------------- barrier
-// Monotonic grid barrier: the k-th barrier waits for the counter to reach
-// k * G.  Every workgroup is resident (cooperative launch).  A spin limit
-// turns a barrier that never completes into a sticky error flag instead of
-// a hang, so every wave still leaves the kernel.
-__device__ __forceinline__ void grid_barrier(unsigned *bar, unsigned target) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+// Hierarchical grid barrier.  Every workgroup is resident (cooperative
+// launch).  Arrivals are counted per XCD (the physical XCC id, read from the
+// hardware register); the last arriver of an XCD makes that XCD's L2
+// contents visible device-wide (one agent-scope release per XCD instead of
+// one per workgroup) and bumps the global count; everyone waits for the
+// global count and then acquires.  Counters only grow: the k-th barrier waits
+// for k arrivals per member.  A spin limit turns a barrier that never
+// completes into a sticky error flag instead of a hang.
+//
+// Counter block (unsigned, 16 apart so each sits on its own 64-byte line):
+//   [0] XCD-leader arrivals, [16] error flag, [16*(2+x)] arrivals on XCD x,
+//   [16*(10+x)] members on XCD x, [16*18] registrations.
+constexpr int kBarWords = 16 * 19;
+
+__device__ __forceinline__ unsigned xcc_id() {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 7u;  // HW_REG_XCC_ID[3:0]
+#else
+  return 0;
+#endif
+}
+
+struct GridSync {
+  unsigned *bar;
+  unsigned x, members, n_xcd, k;
+  __device__ bool spin(unsigned *ctr, unsigned target) {
     unsigned spins = 0;
-    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      if (__hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       __builtin_amdgcn_s_sleep(1);
-      if (++spins > (1u << 26)) {
-        __hip_atomic_store(bar + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        break;
+      if ((++spins & 1023u) == 0) {
+        if (__hip_atomic_load(bar + 16, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+        if (spins > (1u << 22)) {
+          __hip_atomic_store(bar + 16, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          return false;
+        }
       }
     }
-    __threadfence();
+    return true;
   }
-  __syncthreads();
-}
+  // every workgroup registers its XCD once (thread 0 only)
+  __device__ void init(unsigned *b, unsigned G) {
+    bar = b;
+    x = xcc_id();
+    k = 0;
+    __hip_atomic_fetch_add(bar + 16 * (10 + x), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(bar + 16 * 18, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    spin(bar + 16 * 18, G);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    members = __hip_atomic_load(bar + 16 * (10 + x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    n_xcd = 0;
+    for (int q = 0; q < 8; ++q)
+      n_xcd += __hip_atomic_load(bar + 16 * (10 + q), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0u;
+  }
+  // thread 0 only, between two __syncthreads
+  __device__ void arrive_and_wait() {
+    k += 1;
+    const unsigned old =
+        __hip_atomic_fetch_add(bar + 16 * (2 + x), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old + 1 == k * members) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    spin(bar, k * n_xcd);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+};
 
 // ---------------------------------------------------------------- operands
 // OCP e4m3 with a power-of-two scale 2^e: saturate to +-448 first (the
@@ -123,7 +166,7 @@ struct Ops<1> {
   static constexpr int KSTEP = 32;
   typedef __bf16 elem;
   static constexpr int XROW = 72;   // bf16 elements per X / W1 row (64 + pad)
-  static constexpr int XT = 40;     // transposed X chunk row (32 rows + pad)
+  static constexpr int XTP = 8;     // pad of a transposed X row (RB rows + pad)
   static constexpr int DST = 40;    // delta1 staging: [16 hidden][32 rows + pad]
 };
 template <>
@@ -131,7 +174,7 @@ struct Ops<2> {
   static constexpr int KSTEP = 32;
   typedef uint8_t elem;
   static constexpr int XROW = 80;   // bytes per X / W1 row (64 + pad)
-  static constexpr int XT = 48;
+  static constexpr int XTP = 16;
   static constexpr int DST = 48;
 };
 
@@ -142,10 +185,11 @@ struct LLayout {
   __host__ __device__ LLayout(int hb, int rb) : HB(hb), RB(rb) {}
   static constexpr int esz = sizeof(typename Ops<PREC>::elem);
   __host__ __device__ int xr() const { return 0; }
-  __host__ __device__ int xt() const { return xr() + kRC * Ops<PREC>::XROW * esz; }
-  __host__ __device__ int w1() const {
-    return xt() + (PREC == 0 ? 0 : kMaxD * Ops<(PREC == 0 ? 1 : PREC)>::XT * esz);
-  }
+  // the whole row block is staged once per step: X rows (and, for the 8-wide
+  // operand formats, X transposed so that 8 consecutive rows are contiguous)
+  __host__ __device__ int xts() const { return RB + (PREC == 0 ? 0 : Ops<(PREC == 0 ? 1 : PREC)>::XTP); }
+  __host__ __device__ int xt() const { return xr() + RB * Ops<PREC>::XROW * esz; }
+  __host__ __device__ int w1() const { return xt() + (PREC == 0 ? 0 : kMaxD * xts() * esz); }
   __host__ __device__ int b1() const { return w1() + HB * Ops<PREC>::XROW * esz; }
   __host__ __device__ int w2() const { return b1() + HB * 4; }
   __host__ __device__ int d2() const { return w2() + kMaxK * HB * 4; }
@@ -202,10 +246,13 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
   char *dstb = smb + L.dst();
   float *red = reinterpret_cast<float *>(smb + L.red());
 
-  unsigned nbar = 0;
+  GridSync gs;
+  if (tid == 0) gs.init(a.bar, (unsigned)G);
+  __syncthreads();
   auto barrier = [&]() {
-    nbar += 1;
-    grid_barrier(a.bar, nbar * (unsigned)G);
+    __syncthreads();  // this workgroup's stores are complete (in L2) before it arrives
+    if (tid == 0) gs.arrive_and_wait();
+    __syncthreads();
   };
 
   // ---- one-time: dataset amax of |X| for the e4m3 X scale
@@ -293,50 +340,48 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
       w2s[q] = (k < K && h < H) ? a.theta[oW2 + (int64_t)k * H + h] : 0.0f;
     }
 
-    // Stage rows [c0, c0+kRC) of this block into xr (and xt), operand precision.
-    auto stage_x = [&](int c0) {
-      __syncthreads();
-      for (int q = tid; q < kRC * 16; q += kLT) {   // 16 groups of 4 columns per row
-        const int rr = q >> 4, c = (q & 15) * 4;
-        const int rloc = c0 + rr;
-        const bool on = rloc < rows_here;
-        const float *src = a.X + (rb0 + rloc) * D;
-        float v[4];
+    // Stage this workgroup's row block of X into xr (and xt), operand
+    // precision, once per step: one round of global loads for both phases.
+    const int XTS = L.xts();
+    for (int q = tid; q < RB * 16; q += kLT) {   // 16 groups of 4 columns per row
+      const int rr = q >> 4, c = (q & 15) * 4;
+      const bool on = rr < rows_here;
+      const float *src = a.X + (rb0 + rr) * D;
+      float v[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = (on && c + u < D) ? src[c + u] : 0.0f;
-        if (PREC == 0) {
+      for (int u = 0; u < 4; ++u) v[u] = (on && c + u < D) ? src[c + u] : 0.0f;
+      if (PREC == 0) {
 #pragma unroll
-          for (int u = 0; u < 4; ++u) reinterpret_cast<float *>(xr)[rr * XROW + c + u] = v[u];
-        } else if (PREC == 1) {
+        for (int u = 0; u < 4; ++u) reinterpret_cast<float *>(xr)[rr * XROW + c + u] = v[u];
+      } else if (PREC == 1) {
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const __bf16 bv = (__bf16)v[u];
-            reinterpret_cast<__bf16 *>(xr)[rr * XROW + c + u] = bv;
-            reinterpret_cast<__bf16 *>(xt)[(c + u) * Ops<1>::XT + rr] = bv;
-          }
-        } else {
-          const uint32_t pk = pack_e4m3x4(v[0] * sx, v[1] * sx, v[2] * sx, v[3] * sx);
-          *reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(xr) + rr * XROW + c) = pk;
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-            reinterpret_cast<uint8_t *>(xt)[(c + u) * Ops<2>::XT + rr] = (uint8_t)(pk >> (8 * u));
+        for (int u = 0; u < 4; ++u) {
+          const __bf16 bv = (__bf16)v[u];
+          reinterpret_cast<__bf16 *>(xr)[rr * XROW + c + u] = bv;
+          reinterpret_cast<__bf16 *>(xt)[(c + u) * XTS + rr] = bv;
         }
+      } else {
+        const uint32_t pk = pack_e4m3x4(v[0] * sx, v[1] * sx, v[2] * sx, v[3] * sx);
+        *reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(xr) + rr * XROW + c) = pk;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          reinterpret_cast<uint8_t *>(xt)[(c + u) * XTS + rr] = (uint8_t)(pk >> (8 * u));
       }
-      __syncthreads();
-    };
+    }
+    __syncthreads();
 
-    // z1 block for rows [rs*16, rs*16+16) of the chunk and hidden block hb of
+    // z1 block for rows [c0 + rs*16, +16) of the block and hidden block hb of
     // this wave: lane holds rows 4*lg+i, hidden unit 16*hb + l16.
-    auto z1_block = [&](int rs, int hb) -> f32x4 {
+    auto z1_block = [&](int c0, int rs, int hb) -> f32x4 {
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
       const int hl = wave * HW + hb * 16 + l16;   // local hidden row in w1s
       if (PREC == 0) {
-        const float *xa = reinterpret_cast<const float *>(xr) + (rs * 16 + l16) * XROW + lg;
+        const float *xa = reinterpret_cast<const float *>(xr) + (c0 + rs * 16 + l16) * XROW + lg;
         const float *wb = reinterpret_cast<const float *>(w1s) + hl * XROW + lg;
         for (int k0 = 0; k0 < DK; k0 += 4)
           acc = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[k0], wb[k0], acc, 0, 0, 0);
       } else if (PREC == 1) {
-        const __bf16 *xa = reinterpret_cast<const __bf16 *>(xr) + (rs * 16 + l16) * XROW + 8 * lg;
+        const __bf16 *xa = reinterpret_cast<const __bf16 *>(xr) + (c0 + rs * 16 + l16) * XROW + 8 * lg;
         const __bf16 *wb = reinterpret_cast<const __bf16 *>(w1s) + hl * XROW + 8 * lg;
         for (int k0 = 0; k0 < DK; k0 += 32) {
           const bf16x8 av = *reinterpret_cast<const bf16x8 *>(xa + k0);
@@ -344,7 +389,7 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
           acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
         }
       } else {
-        const uint8_t *xa = reinterpret_cast<const uint8_t *>(xr) + (rs * 16 + l16) * XROW + 8 * lg;
+        const uint8_t *xa = reinterpret_cast<const uint8_t *>(xr) + (c0 + rs * 16 + l16) * XROW + 8 * lg;
         const uint8_t *wb = reinterpret_cast<const uint8_t *>(w1s) + hl * XROW + 8 * lg;
         for (int k0 = 0; k0 < DK; k0 += 32) {
           const long av = *reinterpret_cast<const long *>(xa + k0);
@@ -360,7 +405,6 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
     const bool split = a.Gj > 1;
     if (split) {
       for (int c0 = 0; c0 < RB; c0 += kRC) {
-        stage_x(c0);
         float zp[2][4][kMaxK];
 #pragma unroll
         for (int rs = 0; rs < 2; ++rs)
@@ -376,7 +420,7 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
           for (int k = 0; k < kMaxK; ++k) w2v[k] = w2s[k * HB + hl];
 #pragma unroll
           for (int rs = 0; rs < 2; ++rs) {
-            const f32x4 z = z1_block(rs, hb);
+            const f32x4 z = z1_block(c0, rs, hb);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               const float av = sigmoid(z[i] + bias);
@@ -412,6 +456,7 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
                           (z2w[(2 * kRC + rr) * 4 + k] + z2w[(3 * kRC + rr) * 4 + k]);
           a.z2p[((int64_t)gj * a.b + (int64_t)gi * RB + c0 + rr) * 4 + k] = v;
         }
+        __syncthreads();  // z2w is rewritten by the next chunk
       }
       barrier();
     }
@@ -421,7 +466,6 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
     if (!split) {
       // Gj == 1: z2 partials are complete inside this workgroup
       for (int c0 = 0; c0 < RB; c0 += kRC) {
-        stage_x(c0);
         float zp[2][4][kMaxK];
 #pragma unroll
         for (int rs = 0; rs < 2; ++rs)
@@ -437,7 +481,7 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
           for (int k = 0; k < kMaxK; ++k) w2v[k] = w2s[k * HB + hl];
 #pragma unroll
           for (int rs = 0; rs < 2; ++rs) {
-            const f32x4 z = z1_block(rs, hb);
+            const f32x4 z = z1_block(c0, rs, hb);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               const float av = sigmoid(z[i] + bias);
@@ -471,6 +515,7 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
           d2s[(c0 + rr) * 4 + k] = (z2w[(0 * kRC + rr) * 4 + k] + z2w[(1 * kRC + rr) * 4 + k]) +
                                    (z2w[(2 * kRC + rr) * 4 + k] + z2w[(3 * kRC + rr) * 4 + k]);
         }
+        __syncthreads();  // z2w is rewritten by the next chunk
       }
       __syncthreads();
     }
@@ -524,7 +569,6 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
     float d1max = 0.0f;
 
     for (int c0 = 0; c0 < RB; c0 += kRC) {
-      stage_x(c0);
 #pragma unroll
       for (int hb = 0; hb < 4; ++hb) {
         if (hb < NHB) {
@@ -535,7 +579,7 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
           for (int k = 0; k < kMaxK; ++k) w2v[k] = w2s[k * HB + hl];
 #pragma unroll
           for (int rs = 0; rs < 2; ++rs) {
-            const f32x4 z = z1_block(rs, hb);
+            const f32x4 z = z1_block(c0, rs, hb);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               const int rr = rs * 16 + 4 * lg + i;          // row within the chunk
@@ -567,7 +611,7 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
           // gW1[hidden block][feature blocks] += delta1^T X over the chunk's rows
           if (PREC == 0) {
             const float *da = reinterpret_cast<const float *>(dstb) + wave * kRC * 16 + lg * 16 + l16;
-            const float *xb = reinterpret_cast<const float *>(xr) + lg * XROW + l16;
+            const float *xb = reinterpret_cast<const float *>(xr) + (c0 + lg) * XROW + l16;
 #pragma unroll
             for (int fb = 0; fb < 4; ++fb) {
               if (fb < NFB) {
@@ -584,7 +628,7 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
             for (int fb = 0; fb < 4; ++fb) {
               if (fb < NFB) {
                 const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(
-                    reinterpret_cast<const __bf16 *>(xt) + (fb * 16 + l16) * Ops<1>::XT + 8 * lg);
+                    reinterpret_cast<const __bf16 *>(xt) + (fb * 16 + l16) * XTS + c0 + 8 * lg);
                 gacc[hb][fb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, gacc[hb][fb], 0, 0, 0);
               }
             }
@@ -595,7 +639,7 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
             for (int fb = 0; fb < 4; ++fb) {
               if (fb < NFB) {
                 const long bv = *reinterpret_cast<const long *>(
-                    reinterpret_cast<const uint8_t *>(xt) + (fb * 16 + l16) * Ops<2>::XT + 8 * lg);
+                    reinterpret_cast<const uint8_t *>(xt) + (fb * 16 + l16) * XTS + c0 + 8 * lg);
                 gacc[hb][fb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bv, gacc[hb][fb], 0, 0, 0);
               }
             }
@@ -654,22 +698,41 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
     barrier();
 
     // ================================================================ phase 3
-    // Sum the Gi partials of a slice of parameters (lanes over partials,
-    // fixed butterfly), update the master copy.
+    // Sum the Gi partials of this workgroup's slice of the parameters in a
+    // fixed order and update the master copy.  Lanes run over parameters
+    // (coalesced reads of each partial row); with few parameters per
+    // workgroup the four waves split the partials and meet in LDS.
     {
       const int64_t per = (P + G - 1) / G;
-      const int64_t p0 = (int64_t)bid * per, p1 = min(P, p0 + per);
+      const int64_t p0 = (int64_t)bid * per;
+      const int np = (int)max((int64_t)0, min(P, p0 + per) - p0);
       float wmax = 0.0f;
-      for (int64_t p = p0 + wave; p < p1; p += 4) {
-        float s = 0.0f;
-        for (int g = lane; g < a.Gi; g += 64) s += a.gp[(int64_t)g * P + p];
-        for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, kWave);
-        if (lane == 0) {
-          float w = a.theta[p], c = a.comp ? a.comp[p] : 0.0f;
-          gd_update(w, c, a.lr, s, a.comp != nullptr);
-          a.theta[p] = w;
-          if (a.comp) a.comp[p] = c;
-          if (p < oB1) wmax = fmaxf(wmax, fabsf(w));
+      auto update = [&](int64_t p, float gsum) {
+        float w = a.theta[p], c = a.comp ? a.comp[p] : 0.0f;
+        gd_update(w, c, a.lr, gsum, a.comp != nullptr);
+        a.theta[p] = w;
+        if (a.comp) a.comp[p] = c;
+        if (p < oB1) wmax = fmaxf(wmax, fabsf(w));
+      };
+      if (np <= 64) {
+        const int g0 = (a.Gi * wave) / 4, g1 = (a.Gi * (wave + 1)) / 4;
+        float sum = 0.0f;
+        if (lane < np) {
+          const float *src = a.gp + p0 + lane;
+#pragma unroll 16
+          for (int g = g0; g < g1; ++g) sum += src[(int64_t)g * P];
+        }
+        z2w[wave * 64 + lane] = sum;
+        __syncthreads();
+        if (wave == 0 && lane < np)
+          update(p0 + lane, (z2w[lane] + z2w[64 + lane]) + (z2w[128 + lane] + z2w[192 + lane]));
+      } else {
+        for (int q = tid; q < np; q += kLT) {
+          const float *src = a.gp + p0 + q;
+          float sum = 0.0f;
+#pragma unroll 16
+          for (int g = 0; g < a.Gi; ++g) sum += src[(int64_t)g * P];
+          update(p0 + q, sum);
         }
       }
       if (PREC == 2) {
@@ -680,9 +743,9 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
           a.amax[((step + 1) & 1) * G + bid] = fmaxf(fmaxf(red[16], red[17]), fmaxf(red[18], red[19]));
       }
       if (bid == 0 && tid == 0) {
-        float s = 0.0f;
-        for (int g = 0; g < a.Gi; ++g) s += a.lossp[g];
-        const float lstep = s / ((float)m * (float)K);
+        float sl = 0.0f;
+        for (int g = 0; g < a.Gi; ++g) sl += a.lossp[g];
+        const float lstep = sl / ((float)m * (float)K);
         const float accum = (sidx == 0 ? 0.0f : a.acc[0]) + lstep;
         a.acc[0] = accum;
         if (sidx == a.steps_per_epoch - 1 && a.loss_hist)
@@ -694,7 +757,7 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
 }
 
 __global__ void k_zero_u32(unsigned *p, int n) {
-  if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
 }
 
 }  // namespace mlpk
@@ -704,6 +767,7 @@ namespace mlph {
 namespace {
 
 constexpr int kMaxRowBlocks = 256, kMaxHiddenBlocks = 16;
+int g_grid_rows = 0, g_grid_hidden = 0;  // launch hint (0: automatic)
 
 struct Plan {
   int Gi, Gj, Hp;
@@ -740,7 +804,7 @@ WsLayout ws_layout(const mlp_config &c, int Gi, int Gj) {
   w.lossp = o; o += up(sizeof(float) * (size_t)Gi);
   w.amax = o; o += up(sizeof(float) * (size_t)5 * Gi * Gj);
   w.acc = o; o += up(sizeof(float) * 4);
-  w.bar = o; o += up(sizeof(unsigned) * 4);
+  w.bar = o; o += up(sizeof(unsigned) * mlpk::kBarWords);
   w.total = o;
   return w;
 }
@@ -761,9 +825,9 @@ static bool plan_for(const mlp_config &c, int n_cu, Plan *pl, std::string *why) 
   while (Gi * Gj * 2 <= n_cu && (H + 64 * Gj * 2 - 1) / (64 * Gj * 2) * 64 >= 64 &&
          H > 64 * Gj)
     Gj *= 2;
-  if (const char *env = getenv("MLP_LARGE_GRID")) {
-    int gi = 0, gj = 0;
-    if (sscanf(env, "%dx%d", &gi, &gj) == 2 && gi > 0 && gj > 0) { Gi = gi; Gj = gj; }
+  if (g_grid_rows > 0 && g_grid_hidden > 0) {
+    Gi = g_grid_rows;
+    Gj = g_grid_hidden;
   }
   const int Hp = (H + 64 * Gj - 1) / (64 * Gj) * 64 * Gj;
   if (Hp / Gj > 256) { *why = "hidden block above 256 units"; return false; }
@@ -773,7 +837,13 @@ static bool plan_for(const mlp_config &c, int n_cu, Plan *pl, std::string *why) 
   pl->Gj = Gj;
   pl->Hp = Hp;
   pl->lds = lds_for(c.prec, Hp / Gj, (int)(b / Gi));
+  if (pl->lds > 160 * 1024) { *why = "row block too large for LDS (use more row blocks)"; return false; }
   return true;
+}
+
+void set_large_grid_hint(int row_blocks, int hidden_blocks) {
+  g_grid_rows = row_blocks;
+  g_grid_hidden = hidden_blocks;
 }
 
 mlp_status large_workspace_bytes(const mlp_config &c, size_t *bytes) {
@@ -841,7 +911,7 @@ mlp_status large_train(const mlp_config &c, const mlp_params &theta, float *comp
   a.steps_per_epoch = (int)((c.n_rows + b - 1) / b);
   a.lr = c.lr;
 
-  hipLaunchKernelGGL(mlpk::k_zero_u32, dim3(1), dim3(64), 0, s, a.bar, 4);
+  hipLaunchKernelGGL(mlpk::k_zero_u32, dim3(1), dim3(256), 0, s, a.bar, mlpk::kBarWords);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) { *err = hipGetErrorString(e); return MLP_ERR_HIP; }
 

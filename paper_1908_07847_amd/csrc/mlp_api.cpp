@@ -27,6 +27,7 @@ struct mlp_net {
 namespace {
 
 thread_local std::string g_last_error;
+mlp_launch_hint g_hint{};
 
 mlp_status fail(mlp_status s, const char *fmt, ...) {
   char buf[512];
@@ -102,6 +103,25 @@ const char *mlp_status_string(mlp_status s) {
 }
 
 const char *mlp_last_error(void) { return g_last_error.c_str(); }
+
+mlp_status mlp_set_launch_hint(const mlp_launch_hint *hint) {
+  if (!hint) {
+    g_hint = mlp_launch_hint{};
+    return MLP_OK;
+  }
+  const int t = hint->small_threads;
+  if (t != 0 && t != 256 && t != 512 && t != 1024)
+    return fail(MLP_ERR_ARG, "small_threads must be 0, 256, 512 or 1024");
+  if (hint->large_row_blocks < 0 || hint->large_row_blocks > 256 || hint->large_hidden_blocks < 0 ||
+      hint->large_hidden_blocks > 16)
+    return fail(MLP_ERR_ARG, "large grid hint outside [0,256] x [0,16]");
+  if ((hint->large_row_blocks == 0) != (hint->large_hidden_blocks == 0))
+    return fail(MLP_ERR_ARG, "give both large grid dimensions or neither");
+  if (hint->reserved != 0) return fail(MLP_ERR_ARG, "reserved must be 0");
+  g_hint = *hint;
+  mlph::set_large_grid_hint(hint->large_row_blocks, hint->large_hidden_blocks);
+  return MLP_OK;
+}
 
 mlp_status mlp_workspace_size(const mlp_config *cfg, size_t *bytes) {
   mlp_status s = check_config(cfg);
@@ -229,6 +249,7 @@ mlp_status mlp_train(mlp_net *net, const float *X, const float *T, int32_t epoch
     one.p_off = 0;
     hipError_t e = mlph::launch_small_train(nullptr, one, 1, (int)D, (int)K, (int)c.n_rows, (int)H,
                                             X, T, p.W1, net->comp, epochs, loss_hist,
+                                            mlph::small_threads(1, g_hint.small_threads),
                                             (hipStream_t)stream);
     return e == hipSuccess ? MLP_OK : hip_fail(e, "mlp_train (small) launch");
   }
@@ -254,7 +275,6 @@ mlp_status mlp_train_batched(const mlp_batch_item *items_host, const mlp_batch_i
   const void *ptrs4[] = {theta_packed, comp_packed, loss_hist};
   for (const void *p : ptrs4)
     if (p && !aligned4(p)) return fail(MLP_ERR_ALIGN, "theta, comp, loss_hist must be 4-byte aligned");
-  int max_rows = 0, max_h = 0;
   for (int32_t i = 0; i < n_nets; ++i) {
     const mlp_batch_item &it = items_host[i];
     if (it.n_rows <= 0 || it.n_rows > MLP_SMALL_MAX_ROWS || it.n_hidden <= 0 ||
@@ -269,14 +289,18 @@ mlp_status mlp_train_batched(const mlp_batch_item *items_host, const mlp_batch_i
     if (it.p_off < 0 || it.p_off + n_params(n_in, it.n_hidden, n_out) > total_params)
       return fail(MLP_ERR_SHAPE, "net %d: parameters outside the %lld packed floats", i,
                   (long long)total_params);
-    max_rows = std::max(max_rows, it.n_rows);
-    max_h = std::max(max_h, it.n_hidden);
   }
   if (epochs == 0) return MLP_OK;
+  int max_rows = 0, max_h = 0;
+  for (int32_t i = 0; i < n_nets; ++i) {
+    max_rows = std::max(max_rows, items_host[i].n_rows);
+    max_h = std::max(max_h, items_host[i].n_hidden);
+  }
   mlp_batch_item none{};
-  hipError_t e = mlph::launch_small_train(items_dev, none, n_nets, n_in, n_out, max_rows, max_h,
-                                          X_packed, T_packed, theta_packed, comp_packed, epochs,
-                                          loss_hist, (hipStream_t)stream);
+  hipError_t e = mlph::launch_small_train(items_dev, none, n_nets, n_in, n_out, max_rows, max_h, X_packed,
+                                          T_packed, theta_packed, comp_packed, epochs, loss_hist,
+                                          mlph::small_threads(n_nets, g_hint.small_threads),
+                                          (hipStream_t)stream);
   return e == hipSuccess ? MLP_OK : hip_fail(e, "mlp_train_batched launch");
 }
 

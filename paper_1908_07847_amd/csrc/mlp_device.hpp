@@ -81,12 +81,15 @@ namespace mlph {
 constexpr int64_t kBackwardChunk = 16384;
 
 // Small-network trainer: one workgroup per net, all epochs in one launch.
-// items == nullptr means a single net described by `one`.
+// items == nullptr means a single net described by `one`.  threads is 256,
+// 512 or 1024 (small_threads picks it from the net count and a hint).
 size_t small_lds_bytes(int n_rows, int n_hidden, int n_in, int threads);
+size_t small_launch_lds_bytes(int max_rows, int max_hidden, int n_in, int threads);
+int small_threads(int n_nets, int hint);
 hipError_t launch_small_train(const mlp_batch_item *items, mlp_batch_item one, int n_nets,
                               int n_in, int n_out, int max_rows, int max_hidden, const float *X,
                               const float *T, float *theta, float *comp, int epochs,
-                              float *loss_hist, hipStream_t s);
+                              float *loss_hist, int threads, hipStream_t s);
 
 // Generic layer kernels (any sizes) for mlp_forward / mlp_backward / mlp_step.
 hipError_t launch_forward(int64_t n, int D, int H, int K, const float *X, mlp_params p, float *A,

@@ -347,7 +347,10 @@ size_t small_lds_bytes(int n_rows, int n_hidden, int n_in, int threads) {
   return sizeof(float) * (size_t)L.total();
 }
 
-int small_threads(int n_nets) { return n_nets <= 64 ? 1024 : 256; }
+int small_threads(int n_nets, int hint) {
+  if (hint == 256 || hint == 512 || hint == 1024) return hint;
+  return n_nets <= 64 ? 1024 : 256;
+}
 
 size_t small_launch_lds_bytes(int max_rows, int max_hidden, int n_in, int threads) {
   // The layout grows with N and H but also depends on the phase-F split S,
@@ -360,15 +363,18 @@ size_t small_launch_lds_bytes(int max_rows, int max_hidden, int n_in, int thread
 hipError_t launch_small_train(const mlp_batch_item *items, mlp_batch_item one, int n_nets,
                               int n_in, int n_out, int max_rows, int max_hidden, const float *X,
                               const float *T, float *theta, float *comp, int epochs,
-                              float *loss_hist, hipStream_t s) {
+                              float *loss_hist, int threads, hipStream_t s) {
   // One net (or a few) alone on the chip: 1024 threads shorten each epoch's
   // critical path.  Many nets: 256 threads per net, several nets per CU.
-  const int nt = small_threads(n_nets);
-  const size_t lds = small_launch_lds_bytes(max_rows, max_hidden, n_in, nt);
-  return nt == 1024 ? mlpk::launch_one<1024>(items, one, n_nets, n_in, n_out, lds, X, T, theta,
-                                             comp, epochs, loss_hist, s)
-                    : mlpk::launch_one<256>(items, one, n_nets, n_in, n_out, lds, X, T, theta,
-                                            comp, epochs, loss_hist, s);
+  const size_t lds = small_launch_lds_bytes(max_rows, max_hidden, n_in, threads);
+  if (threads == 1024)
+    return mlpk::launch_one<1024>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs,
+                                  loss_hist, s);
+  if (threads == 512)
+    return mlpk::launch_one<512>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs,
+                                 loss_hist, s);
+  return mlpk::launch_one<256>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs,
+                               loss_hist, s);
 }
 
 }  // namespace mlph

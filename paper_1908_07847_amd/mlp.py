@@ -14,7 +14,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import BatchItem, Config, Params, check, lib
+from ._lib import BatchItem, Config, LaunchHint, Params, check, lib
 
 
 def _ptr(t: torch.Tensor | None) -> int | None:
@@ -185,6 +185,17 @@ def train_batched(plan: BatchPlan, X: torch.Tensor, T: torch.Tensor, theta: torc
                                 X.shape[0], _ptr(theta), _ptr(comp), theta.numel(), int(epochs),
                                 _ptr(loss_hist), _stream(stream)))
     return loss_hist
+
+
+def set_launch_hint(small_threads: int = 0, large_grid: tuple[int, int] | None = None) -> None:
+    """Launch-shape override for the autotuner (0 / None: the library's choice)."""
+    gi, gj = large_grid if large_grid else (0, 0)
+    h = LaunchHint(int(small_threads), int(gi), int(gj), 0)
+    check(lib.mlp_set_launch_hint(ctypes.byref(h)))
+
+
+def reset_launch_hint() -> None:
+    check(lib.mlp_set_launch_hint(None))
 
 
 # ---------------------------------------------------------------- autograd

@@ -148,9 +148,19 @@ def test_lowp_single_step_matches_emulating_oracle(M, prec):
     delta1 operand sits on a rounding tie (see rounding_flip_bound), plus the
     float32 summation of the gradient (1e-6 of the sum of |terms|)."""
     lr = 0.1
+    # float32 summation error of one contraction, relative to the sum of |terms|:
+    # bf16 products are summed in IEEE float32 (a few ulps over the short MFMA
+    # chains); the e4m3 MFMA's internal sum measured ~7.5e-6 (gfx950, 32-term dot
+    # products of e4m3 values against exact float64), so its bound is 1e-5 and
+    # the rounding-free updates inherit it through the hidden pre-activation.
+    acc_rel = {"bf16": 1e-6, "e4m3": 1e-5}[prec]
+    tol = {"bf16": TOL, "e4m3": 5e-5}[prec]
     for wl, n, batch in [(4, 4096, 4096), (5, 16384, 16384)]:
         w = synth.single(wl, n_rows=n)
-        _, flat, hist = gpu_train(M, w["X"], w["T"], w["theta"], 1, batch, lr=lr, prec=prec)
+        net, flat, hist = gpu_train(M, w["X"], w["T"], w["theta"], 1, batch, lr=lr, prec=prec)
+        # the compensated update keeps the bits that do not fit in theta in the
+        # compensation term: the applied update is (theta1 - comp1) - theta0
+        flat = flat.astype(np.float64) - net.comp.cpu().numpy().astype(np.float64)
         q, ref_hist, slog, d1, bp = oracle.train_lowp(w["X"], w["T"], Params.of(w["theta"]), lr, 1, batch,
                                                       prec, first_step_detail=True)
         p0 = Params.of(w["theta"])
@@ -161,13 +171,13 @@ def test_lowp_single_step_matches_emulating_oracle(M, prec):
             dr = getattr(q, name) - getattr(p0, name)
             e = normwise(du, dr)
             say(f"  {prec} workload {wl} single step: update error {name} {e:.2e}")
-            assert e <= TOL, (name, e)
-        assert abs(hist[0] - ref_hist[0]) <= TOL * ref_hist[0]
+            assert e <= tol, (name, e)
+        assert abs(hist[0] - ref_hist[0]) <= tol * ref_hist[0]
         ex, ed = (int(slog[0, 0]), int(slog[0, 2])) if prec == "e4m3" else (0, 0)
         Xq = oracle.round_array(w["X"], prec, ex)
         d1q = oracle.round_array(d1, prec, ed)
         bound, amb = rounding_flip_bound(d1, bp, Xq, prec, ed, lr)
-        bound += lr * 1e-6 * (np.abs(d1q).T @ np.abs(Xq))
+        bound += lr * acc_rel * (np.abs(d1q).T @ np.abs(Xq))
         du = g.W1.astype(np.float64) - p0.W1
         dr = q.W1 - p0.W1
         excess = np.abs(du - dr) - bound
