@@ -166,7 +166,8 @@ mlp_status mlp_train_batched(const mlp_batch_item *items_host, const mlp_batch_i
  * calls it should affect, not concurrently with them.  It exists for an
  * autotuner that times candidate shapes and remembers the fastest:
  *   small_threads        threads per net in the small / batched trainer:
- *                        256, 512 or 1024;
+ *                        128, 256 or 512 (fewer are used when the larger
+ *                        count's LDS plan would not fit);
  *   large_row_blocks,    the Gi x Gj grid of the large-N trainer (row blocks
  *   large_hidden_blocks  of >= 32 rows, hidden blocks of <= 256 units). */
 typedef struct {

@@ -3,28 +3,29 @@
 // forward, error, backpropagation, gradient-descent update, repeated for a
 // number of epochs).
 //
-// Everything a net touches lives in LDS for the whole run: its rows X (with
-// a constant-1 column appended, so b1 is the last column of W1), the one-hot
-// targets, W1|b1, W2|b2, and per epoch the activations A (with a constant-1
-// column, so b2 is the last column of W2), the hidden deltas and the output
-// deltas.  HBM is read once at the start and written once at the end.
-// Each epoch is two barrier-separated phases:
+// The net lives in LDS for the whole run: its rows X with a constant-1
+// column (so b1 is the last column of W1), the targets, W1|b1, W2 and b2.
+// HBM is read once at the start and written once at the end.  Each of the
+// NW waves owns every NW-th 16-row tile of the batch and, per epoch:
 //
-//   F (row-parallel): S threads per row, each owning a contiguous slice of
-//     the hidden units.  z1 = [x 1].[W1 b1]^T, a = sigma(z1), partial
-//     z2 = a.[W2 b2]^T over the slice, summed across the row's S lanes,
-//     y = sigma(z2), delta2 = 2 (y - t) / (N K) . y (1 - y),
-//     delta1 = (delta2 W2) . a (1 - a) with the pre-update W2.
-//   G (parameter-parallel): the gradient is cut into 4x4 tiles of [W1 b1]
-//     and [W2 b2]; C adjacent lanes share a tile and each sums every C-th
-//     row, then a fixed butterfly over those lanes adds the C partial sums
-//     (bitwise repeatable).  The tile's first lane keeps the master weights
-//     and their Kahan compensation in registers for the whole run, applies
-//     the update and publishes the new weights to LDS.
+//   z1 = [X 1][W1 b1]^T        v_mfma_f32_16x16x4_f32, M = rows, N = hidden
+//   a = sigma(z1), slope = a (1 - a) (as e^-z a^2), kept in registers in the
+//       MFMA accumulator layout (lane: 4 rows x 1 hidden unit per 16x16 tile)
+//   z2 = a W2^T + b2           per lane over its hidden units, then summed
+//                              across the 16 lanes of each row
+//   y = sigma(z2), delta2 = 2 (y - t) / (N K) . y (1 - y)
+//   delta1 = (delta2 W2) . slope   (the pre-update W2)
+//   gW1 += delta1^T [X 1]      v_mfma_f32_16x16x4_f32, M = hidden, N = features,
+//                              K = the tile's rows (delta1 staged through a
+//                              wave-private LDS tile to transpose it)
+//   gW2 += delta2^T a, gb2 += sum delta2   (lane partials)
 //
-// NT (threads per workgroup) is a template parameter: 1024 when one net has
-// the chip to itself (its epoch latency is the whole story), 256 when many
-// nets share the CUs (several workgroups per CU hide each other's latency).
+// After a barrier the NW wave partials of every parameter are summed in wave
+// order (bitwise repeatable) and the owner thread applies the update to the
+// master copy in LDS, with its Kahan compensation term kept in registers;
+// a second barrier publishes the new weights.  Padded rows carry zero X (so
+// zero delta) and padded hidden units zero W2 (so zero delta1).
+//
 // Limits: N <= 128 rows, H <= 64, D <= 48, K <= 4.
 #include <algorithm>
 
@@ -32,310 +33,335 @@
 
 namespace mlpk {
 
+typedef float f32x4_s __attribute__((ext_vector_type(4)));
+
+// LDS plan (floats).
 struct SmallLayout {
-  int N, H, D, K, DP, HA, HP4, S, HPT, HR, HS;
-  __host__ __device__ SmallLayout(int n, int h, int d, int k, int nt) : N(n), H(h), D(d), K(k) {
-    DP = (d + 1 + 3) / 4 * 4;         // features + bias column, float4 padded
-    HA = h + 1;                       // hidden units + bias column
-    HP4 = (HA + 3) / 4 * 4;
-    S = 1;                            // threads per row in phase F
-    while (S * 2 * n <= nt && S < 16) S *= 2;
-    HPT = (HP4 + S - 1) / S;          // hidden columns per phase-F thread
-    HR = S * HPT;                     // rows of the W1 copy (zero past H)
-    HS = (HR + 3) / 4 * 4;            // LDS row stride of A and delta1
-    if (HS % 8 == 0) HS += 4;         // rows 4 floats apart modulo 8: no b128 bank aliasing
+  int N, H, D, K, NW, NP, NPT, DA, DK, DN, XS, HP, HT, FT, PW;
+  __host__ __device__ SmallLayout(int n, int h, int d, int k, int nw)
+      : N(n), H(h), D(d), K(k), NW(nw) {
+    NP = (n + 15) / 16 * 16;  // rows padded to 16-row tiles
+    NPT = NP / 16;
+    DA = d + 1;               // features + the constant-1 column
+    DK = (DA + 3) / 4 * 4;    // contraction length of z1 (steps of 4)
+    DN = (DA + 15) / 16 * 16; // feature tiles of gW1
+    FT = DN / 16;
+    XS = DN + 2;              // row stride of X and W1: 16 rows of a tile hit distinct banks
+    HP = (h + 15) / 16 * 16;  // hidden units padded to 16-unit tiles
+    HT = HP / 16;
+    PW = HP * DN + 4 * HP + 4 + 4;  // one wave's partials: gW1 | gW2 | gb2 | loss
   }
-  // float offsets of each LDS region (all multiples of 4)
-  __host__ __device__ int xs() const { return 0; }               // X|1     [N][DP]
-  __host__ __device__ int w1() const { return xs() + N * DP; }   // W1|b1   [HR][DP] master
-  __host__ __device__ int c1() const { return w1() + HR * DP; }  // its Kahan terms [H][DP]
-  __host__ __device__ int w2() const { return c1() + H * DP; }   // W2|b2   [4][HS] master
-  __host__ __device__ int c2() const { return w2() + 4 * HS; }   // its Kahan terms [4][HS]
-  __host__ __device__ int a() const { return c2() + 4 * HS; }    // A|1     [N][HS]
-  __host__ __device__ int d1() const { return a() + N * HS; }    // delta1  [N][HS]
-  __host__ __device__ int d2() const { return d1() + N * HS; }   // delta2  [N][4]
-  __host__ __device__ int ts() const { return d2() + N * 4; }    // T       [N][4]
-  __host__ __device__ int red() const { return ts() + N * 4; }   // per-wave loss partials
-  __host__ __device__ int total() const { return red() + 16; }
+  __host__ __device__ int xs() const { return 0; }                  // [NP][XS]
+  __host__ __device__ int w1() const { return xs() + NP * XS; }     // [HP][XS] master W1|b1
+  __host__ __device__ int w2() const { return w1() + HP * XS; }     // [4][HP]  master W2
+  __host__ __device__ int b2() const { return w2() + 4 * HP; }      // [4]      master b2
+  __host__ __device__ int ts() const { return b2() + 4; }           // [NP][4]  targets
+  __host__ __device__ int dst() const { return ts() + NP * 4; }     // [NW][16][16] delta1 staging
+  __host__ __device__ int part() const { return dst() + NW * 256; } // [NW][PW] partials
+  __host__ __device__ int total() const { return part() + NW * PW; }
 };
 
-template <int NT>
-__global__ __launch_bounds__(NT) void k_small_train(
+// Sum over the 16 lanes that share lane / 16 (fixed butterfly).
+__device__ __forceinline__ float sum16(float v) {
+  v += __shfl_xor(v, 1, kWave);
+  v += __shfl_xor(v, 2, kWave);
+  v += __shfl_xor(v, 4, kWave);
+  v += __shfl_xor(v, 8, kWave);
+  return v;
+}
+
+template <int NW, int HTM>
+__global__ __launch_bounds__(NW * 64) void k_small_train(
     const mlp_batch_item *__restrict__ items, mlp_batch_item one, int D, int K,
     const float *__restrict__ X, const float *__restrict__ T, float *__restrict__ theta,
     float *__restrict__ comp, int epochs, float *__restrict__ loss_hist) {
-  constexpr int HPTM = (72 * 128 + NT - 1) / NT;  // max hidden columns per phase-F thread
-  constexpr int DPM = 52;                          // max padded feature columns (D <= 48)
-  constexpr int CM = 8;                            // max lanes sharing a phase-G tile
+  constexpr int NT = NW * 64;
+  constexpr int PMAX = 48 * 64 + 64 + 64 * 4 + 4;   // largest parameter count
+  constexpr int JM = (PMAX + NT - 1) / NT;          // parameters per thread
   const mlp_batch_item it = items ? items[blockIdx.x] : one;
   const int N = it.n_rows, H = it.n_hidden;
   const float lr = it.lr;
-  const SmallLayout L(N, H, D, K, NT);
-  const int DP = L.DP, HA = L.HA, HS = L.HS, S = L.S, HPT = L.HPT, HR = L.HR;
-  const int tid = threadIdx.x;
+  const SmallLayout L(N, H, D, K, NW);
+  const int XS = L.XS, HP = L.HP, HT = L.HT, FT = L.FT, DN = L.DN, DK = L.DK, PW = L.PW;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, lg = lane >> 4;
 
   extern __shared__ float4 smem4[];
   float *sm = reinterpret_cast<float *>(smem4);
   float *Xs = sm + L.xs();
   float *W1s = sm + L.w1();
-  float *C1s = sm + L.c1();
   float *W2s = sm + L.w2();
-  float *C2s = sm + L.c2();
-  float *As = sm + L.a();
-  float *D1s = sm + L.d1();
-  float *D2s = sm + L.d2();
+  float *b2s = sm + L.b2();
   float *Ts = sm + L.ts();
-  float *red = sm + L.red();
+  float *Dst = sm + L.dst() + wave * 256;
+  float *Part = sm + L.part();
 
   const float *Xg = X + it.x_off * D;
   const float *Tg = T + it.x_off * K;
   float *P = theta + it.p_off;
   float *Cp = comp ? comp + it.p_off : nullptr;
   const bool compensated = Cp != nullptr;
+  const int D1 = D + 1;
   const int oB1 = H * D, oW2 = oB1 + H, oB2 = oW2 + K * H;
+  const int nP = H * D1 + K * H + K;   // parameters, in update order: [W1 b1] rows, W2, b2
 
-  // ---- stage rows, targets, parameters and compensation (coalesced);
-  //      zero every padding entry that a later read may touch
-  for (int i = tid; i < N * DP; i += NT) {
-    int r = i / DP, c = i - r * DP;
-    Xs[i] = c < D ? Xg[(int64_t)r * D + c] : (c == D ? 1.0f : 0.0f);
+  // ---- stage rows, targets, parameters (coalesced); zero every padding entry
+  for (int i = tid; i < L.NP * XS; i += NT) {
+    const int r = i / XS, c = i - r * XS;
+    Xs[i] = (r < N && c < D) ? Xg[(int64_t)r * D + c] : ((r < N && c == D) ? 1.0f : 0.0f);
   }
-  for (int i = tid; i < N * 4; i += NT) {
-    int r = i >> 2, k = i & 3;
-    Ts[i] = k < K ? Tg[(int64_t)r * K + k] : 0.0f;
+  for (int i = tid; i < L.NP * 4; i += NT) {
+    const int r = i >> 2, k = i & 3;
+    Ts[i] = (r < N && k < K) ? Tg[(int64_t)r * K + k] : 0.0f;
   }
-  for (int i = tid; i < HR * DP; i += NT) {
-    int h = i / DP, c = i - h * DP;
-    float v = 0.0f, cv = 0.0f;
-    if (h < H && c <= D) {
-      int o = c < D ? h * D + c : oB1 + h;
-      v = P[o];
-      cv = compensated ? Cp[o] : 0.0f;
+  for (int i = tid; i < HP * XS; i += NT) {
+    const int h = i / XS, c = i - h * XS;
+    W1s[i] = (h < H && c < D) ? P[h * D + c] : ((h < H && c == D) ? P[oB1 + h] : 0.0f);
+  }
+  for (int i = tid; i < 4 * HP; i += NT) {
+    const int k = i / HP, h = i - k * HP;
+    W2s[i] = (k < K && h < H) ? P[oW2 + k * H + h] : 0.0f;
+  }
+  if (tid < 4) b2s[tid] = tid < K ? P[oB2 + tid] : 0.0f;
+  // Kahan terms of the parameters this thread updates (q = tid + j*NT)
+  float ccomp[JM];
+#pragma unroll
+  for (int j = 0; j < JM; ++j) {
+    const int q = tid + j * NT;
+    float c = 0.0f;
+    if (compensated && q < nP) {
+      int o;
+      if (q < H * D1) {
+        const int h = q / D1, d = q - h * D1;
+        o = d < D ? h * D + d : oB1 + h;
+      } else if (q < H * D1 + K * H) {
+        o = oW2 + (q - H * D1);
+      } else {
+        o = oB2 + (q - H * D1 - K * H);
+      }
+      c = Cp[o];
     }
-    W1s[i] = v;
-    if (h < H) C1s[i] = cv;
+    ccomp[j] = c;
   }
-  for (int i = tid; i < 4 * HS; i += NT) {
-    int k = i / HS, h = i - k * HS;
-    float v = 0.0f, cv = 0.0f;
-    if (k < K && h <= H) {
-      int o = h < H ? oW2 + k * H + h : oB2 + k;
-      v = P[o];
-      cv = compensated ? Cp[o] : 0.0f;
-    }
-    W2s[i] = v;
-    C2s[i] = cv;
-  }
-  for (int i = tid; i < 2 * N * HS; i += NT) As[i] = 0.0f;  // As and D1s are adjacent
   __syncthreads();
 
-  // ---- phase-G tile ownership (fixed for the whole run)
-  const int nTD = DP / 4;
-  const int T1 = ((H + 3) / 4) * nTD;  // tiles of [W1 b1]: 4 hidden x 4 columns
-  const int T2 = (HA + 3) / 4;         // tiles of [W2 b2]: 4 outputs x 4 hidden(+bias)
-  int C = 1;
-  while (C * 2 <= CM && (T1 + T2) * C * 2 <= NT && C * 2 <= N) C *= 2;
-  const int tile = tid / C, chunk = tid - tile * C;
-  const bool g1 = tile < T1, g2 = !g1 && tile < T1 + T2;
-  const bool owner = chunk == 0 && (g1 || g2);
-  int th = 0, td = 0, tj = 0;
-  if (g1) { th = tile / nTD; td = tile - th * nTD; }
-  if (g2) tj = tile - T1;
-
-  // ---- phase-F row ownership
-  const int r = tid / S, s = tid - r * S;
-  const bool row_on = r < N;
-  const int hbeg = s * HPT;
-  float tr[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) tr[k] = row_on ? Ts[r * 4 + k] : 0.0f;
   const float dscale = 2.0f / (float)(N * K);
   const float inv_nk = 1.0f / (float)(N * K);
 
   for (int e = 0; e < epochs; ++e) {
-    // ============================ phase F
+    // ======================= rows of this wave: forward, deltas, partial gradients
+    f32x4_s gacc[HTM][4];
+#pragma unroll
+    for (int ht = 0; ht < HTM; ++ht)
+#pragma unroll
+      for (int ft = 0; ft < 4; ++ft) gacc[ht][ft] = f32x4_s{0.f, 0.f, 0.f, 0.f};
+    float gw2[4][HTM];   // [k][ht]: this lane's hidden unit, summed over its rows
+    float gb2[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int ht = 0; ht < HTM; ++ht) gw2[k][ht] = 0.0f;
     float sq = 0.0f;
-    if (row_on) {
-      float a[HPTM];
+
+    for (int rt = wave; rt < L.NPT; rt += NW) {
+      const int r0 = rt * 16;
+      // z1 tiles over every hidden tile; a and its slope stay in registers
+      float av[HTM][4], sl[HTM][4];
 #pragma unroll
-      for (int j = 0; j < HPTM; ++j) a[j] = 0.0f;
-      const float4 *xr = reinterpret_cast<const float4 *>(Xs + r * DP);
-      const float4 *wr = reinterpret_cast<const float4 *>(W1s + hbeg * DP);
-      const int dp4 = DP / 4;
+      for (int ht = 0; ht < HTM; ++ht) {
 #pragma unroll
-      for (int c4 = 0; c4 < DPM / 4; ++c4) {
-        if (c4 < dp4) {
-          const float4 xv = xr[c4];
+        for (int i = 0; i < 4; ++i) { av[ht][i] = 0.0f; sl[ht][i] = 0.0f; }
+        if (ht < HT) {
+          f32x4_s z = {0.f, 0.f, 0.f, 0.f};
+          const float *xa = Xs + (r0 + l16) * XS + lg;
+          const float *wb = W1s + (ht * 16 + l16) * XS + lg;
+          for (int k0 = 0; k0 < DK; k0 += 4)
+            z = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[k0], wb[k0], z, 0, 0, 0);
 #pragma unroll
-          for (int j = 0; j < HPTM; ++j) {
-            if (j < HPT) {
-              const float4 wv = wr[j * dp4 + c4];
-              a[j] = fmaf(xv.x, wv.x, a[j]);
-              a[j] = fmaf(xv.y, wv.y, a[j]);
-              a[j] = fmaf(xv.z, wv.z, a[j]);
-              a[j] = fmaf(xv.w, wv.w, a[j]);
+          for (int i = 0; i < 4; ++i) av[ht][i] = sigmoid_slope(z[i], sl[ht][i]);
+        }
+      }
+      // output layer for this lane's 4 rows: partial over its hidden units,
+      // then summed across the 16 lanes of the row group
+      float d2[4][4];  // [i][k]
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = r0 + 4 * lg + i;
+        const bool valid = r < N;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          float zp = 0.0f;
+          if (k < K) {
+#pragma unroll
+            for (int ht = 0; ht < HTM; ++ht)
+              if (ht < HT) zp = fmaf(av[ht][i], W2s[k * HP + ht * 16 + l16], zp);
+          }
+          zp = sum16(zp);
+          float dv = 0.0f;
+          if (k < K && valid) {
+            const float y = sigmoid(zp + b2s[k]);
+            const float err = y - Ts[r * 4 + k];
+            if (l16 == 0) sq = fmaf(err, err, sq);
+            dv = dscale * err * y * (1.0f - y);
+          }
+          d2[i][k] = dv;
+        }
+      }
+      if (l16 == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) gb2[k] += (d2[0][k] + d2[1][k]) + (d2[2][k] + d2[3][k]);
+      }
+      // hidden deltas, gW2 lane partials, and gW1 on MFMA
+#pragma unroll
+      for (int ht = 0; ht < HTM; ++ht) {
+        if (ht < HT) {
+          const int hc = ht * 16 + l16;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            float bp = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              bp = fmaf(d2[i][k], W2s[k * HP + hc], bp);
+              gw2[k][ht] = fmaf(d2[i][k], av[ht][i], gw2[k][ht]);
+            }
+            Dst[(4 * lg + i) * 16 + l16] = bp * sl[ht][i];
+          }
+          const float *da = Dst + lg * 16 + l16;
+#pragma unroll
+          for (int ft = 0; ft < 4; ++ft) {
+            if (ft < FT) {
+              const float *xb = Xs + (r0 + lg) * XS + ft * 16 + l16;
+              f32x4_s g = gacc[ht][ft];
+#pragma unroll
+              for (int s = 0; s < 4; ++s)
+                g = __builtin_amdgcn_mfma_f32_16x16x4f32(da[s * 64], xb[s * 4 * XS], g, 0, 0, 0);
+              gacc[ht][ft] = g;
             }
           }
         }
       }
-#pragma unroll
-      for (int j = 0; j < HPTM; ++j) {
-        const int h = hbeg + j;
-        a[j] = h < H ? sigmoid(a[j]) : (h == H ? 1.0f : 0.0f);  // column H: bias of layer 2
-      }
-      float z2[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        float acc = 0.0f;
-        if (k < K) {
-          const float *w2r = W2s + k * HS + hbeg;
-#pragma unroll
-          for (int j = 0; j < HPTM; ++j)
-            if (j < HPT) acc = fmaf(a[j], w2r[j], acc);
-        }
-        z2[k] = acc;
-      }
-      for (int off = 1; off < S; off <<= 1)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) z2[k] += __shfl_xor(z2[k], off, kWave);
-      float d2[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        d2[k] = 0.0f;
-        if (k < K) {
-          float y = sigmoid(z2[k]);
-          float err = y - tr[k];
-          sq = fmaf(err, err, sq);
-          d2[k] = dscale * err * y * (1.0f - y);
-        }
-      }
-      if (s) sq = 0.0f;  // each row's error is counted once
-      float *arow = As + r * HS + hbeg;
-      float *drow = D1s + r * HS + hbeg;
-#pragma unroll
-      for (int j = 0; j < HPTM; ++j) {
-        const int h = hbeg + j;
-        if (j < HPT) {
-          float bp = 0.0f;
-#pragma unroll
-          for (int k = 0; k < 4; ++k)
-            if (k < K) bp = fmaf(d2[k], W2s[k * HS + h], bp);
-          arow[j] = a[j];
-          drow[j] = h < H ? bp * a[j] * (1.0f - a[j]) : 0.0f;
-        }
-      }
-      if (!s) reinterpret_cast<float4 *>(D2s)[r] = make_float4(d2[0], d2[1], d2[2], d2[3]);
     }
-    if (loss_hist) {
-      sq = wave_sum(sq);
-      if ((tid & (kWave - 1)) == 0) red[tid / kWave] = sq;
+
+    // ======================= wave partials to LDS
+    float *pw = Part + wave * PW;
+#pragma unroll
+    for (int ht = 0; ht < HTM; ++ht) {
+      if (ht < HT) {
+#pragma unroll
+        for (int ft = 0; ft < 4; ++ft) {
+          if (ft < FT) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) pw[(ht * 16 + 4 * lg + i) * DN + ft * 16 + l16] = gacc[ht][ft][i];
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          float v = gw2[k][ht];
+          v += __shfl_xor(v, 16, kWave);
+          v += __shfl_xor(v, 32, kWave);
+          if (lg == 0) pw[HP * DN + k * HP + ht * 16 + l16] = v;
+        }
+      }
     }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      float v = gb2[k];
+      v += __shfl_xor(v, 16, kWave);
+      v += __shfl_xor(v, 32, kWave);
+      if (lane == 0) pw[HP * DN + 4 * HP + k] = v;
+    }
+    sq = wave_sum(sq);
+    if (lane == 0) pw[HP * DN + 4 * HP + 4] = sq;
     __syncthreads();
 
-    // ============================ phase G
+    // ======================= sum the wave partials in order; update
     if (loss_hist && tid == 0) {
-      float tot = 0.0f;
-      for (int q = 0; q < NT / kWave; ++q) tot += red[q];
-      loss_hist[(int64_t)blockIdx.x * epochs + e] = tot * inv_nk;
+      float s = 0.0f;
+      for (int w = 0; w < NW; ++w) s += Part[w * PW + HP * DN + 4 * HP + 4];
+      loss_hist[(int64_t)blockIdx.x * epochs + e] = s * inv_nk;
     }
-    float acc[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) acc[q] = 0.0f;
-    if (g1 || g2) {
-      const float *pa = g1 ? D1s + 4 * th : D2s;         // left factor: delta1 cols or delta2
-      const float *pb = g1 ? Xs + 4 * td : As + 4 * tj;  // right factor: x cols or a cols
-      const int sa = g1 ? HS : 4, sb = g1 ? DP : HS;
-      int n = chunk;
-      for (; n + C < N; n += 2 * C) {
-        const float4 u0 = *reinterpret_cast<const float4 *>(pa + n * sa);
-        const float4 v0 = *reinterpret_cast<const float4 *>(pb + n * sb);
-        const float4 u1 = *reinterpret_cast<const float4 *>(pa + (n + C) * sa);
-        const float4 v1 = *reinterpret_cast<const float4 *>(pb + (n + C) * sb);
-        const float uu0[4] = {u0.x, u0.y, u0.z, u0.w}, vv0[4] = {v0.x, v0.y, v0.z, v0.w};
-        const float uu1[4] = {u1.x, u1.y, u1.z, u1.w}, vv1[4] = {v1.x, v1.y, v1.z, v1.w};
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            acc[i * 4 + j] = fmaf(uu0[i], vv0[j], acc[i * 4 + j]);
-            acc[i * 4 + j] = fmaf(uu1[i], vv1[j], acc[i * 4 + j]);
-          }
-      }
-      if (n < N) {
-        const float4 u0 = *reinterpret_cast<const float4 *>(pa + n * sa);
-        const float4 v0 = *reinterpret_cast<const float4 *>(pb + n * sb);
-        const float uu0[4] = {u0.x, u0.y, u0.z, u0.w}, vv0[4] = {v0.x, v0.y, v0.z, v0.w};
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i * 4 + j] = fmaf(uu0[i], vv0[j], acc[i * 4 + j]);
-      }
-    }
-    for (int off = C / 2; off >= 1; off >>= 1)  // fixed butterfly over the tile's C lanes
-#pragma unroll
-      for (int q = 0; q < 16; ++q) acc[q] += __shfl_xor(acc[q], off, kWave);
-    if (owner) {
-      if (g1) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int h = 4 * th + i, d = 4 * td + j;
-            if (h < H && d <= D) {
-              float wv = W1s[h * DP + d], cv = C1s[h * DP + d];
-              gd_update(wv, cv, lr, acc[i * 4 + j], compensated);
-              W1s[h * DP + d] = wv;
-              C1s[h * DP + d] = cv;
-            }
-          }
-      } else {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int k = i, h = 4 * tj + j;
-            if (k < K && h <= H) {
-              float wv = W2s[k * HS + h], cv = C2s[k * HS + h];
-              gd_update(wv, cv, lr, acc[i * 4 + j], compensated);
-              W2s[k * HS + h] = wv;
-              C2s[k * HS + h] = cv;
-            }
-          }
+    for (int j = 0; j < JM; ++j) {
+      const int q = tid + j * NT;
+      if (q < nP) {
+        int po;       // partial offset within a wave's block
+        float *mw;    // master copy in LDS
+        if (q < H * D1) {
+          const int h = q / D1, d = q - h * D1;
+          po = h * DN + d;
+          mw = W1s + h * XS + d;
+        } else if (q < H * D1 + K * H) {
+          const int o = q - H * D1, k = o / H, h = o - k * H;
+          po = HP * DN + k * HP + h;
+          mw = W2s + k * HP + h;
+        } else {
+          const int k = q - H * D1 - K * H;
+          po = HP * DN + 4 * HP + k;
+          mw = b2s + k;
+        }
+        float g = 0.0f;
+        for (int w = 0; w < NW; ++w) g += Part[w * PW + po];
+        float wv = *mw;
+        gd_update(wv, ccomp[j], lr, g, compensated);
+        *mw = wv;
       }
     }
     __syncthreads();
   }
 
   // ---- write the trained parameters (and compensation) back once
-  for (int i = tid; i < H * DP; i += NT) {
-    int h = i / DP, c = i - h * DP;
-    if (c <= D) {
-      int o = c < D ? h * D + c : oB1 + h;
-      P[o] = W1s[i];
-      if (compensated) Cp[o] = C1s[i];
-    }
-  }
-  for (int i = tid; i < 4 * HS; i += NT) {
-    int k = i / HS, h = i - k * HS;
-    if (k < K && h <= H) {
-      int o = h < H ? oW2 + k * H + h : oB2 + k;
-      P[o] = W2s[i];
-      if (compensated) Cp[o] = C2s[i];
+#pragma unroll
+  for (int j = 0; j < JM; ++j) {
+    const int q = tid + j * NT;
+    if (q < nP) {
+      int o;
+      float wv;
+      if (q < H * D1) {
+        const int h = q / D1, d = q - h * D1;
+        o = d < D ? h * D + d : oB1 + h;
+        wv = W1s[h * XS + d];
+      } else if (q < H * D1 + K * H) {
+        const int oo = q - H * D1, k = oo / H, h = oo - k * H;
+        o = oW2 + oo;
+        wv = W2s[k * HP + h];
+      } else {
+        const int k = q - H * D1 - K * H;
+        o = oB2 + k;
+        wv = b2s[k];
+      }
+      P[o] = wv;
+      if (compensated) Cp[o] = ccomp[j];
     }
   }
 }
 
-template <int NT>
+template <int NW, int HTM>
 hipError_t launch_one(const mlp_batch_item *items, mlp_batch_item one, int n_nets, int n_in,
                       int n_out, size_t lds, const float *X, const float *T, float *theta,
                       float *comp, int epochs, float *loss_hist, hipStream_t s) {
-  auto kern = k_small_train<NT>;
+  auto kern = k_small_train<NW, HTM>;
   hipError_t e = hipFuncSetAttribute((const void *)kern,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(n_nets), dim3(NT), lds, s, items, one, n_in, n_out, X, T, theta,
-                     comp, epochs, loss_hist);
+  hipLaunchKernelGGL(kern, dim3(n_nets), dim3(NW * 64), lds, s, items, one, n_in, n_out, X, T,
+                     theta, comp, epochs, loss_hist);
   return hipGetLastError();
+}
+
+template <int NW>
+hipError_t launch_nw(int max_hidden, const mlp_batch_item *items, mlp_batch_item one, int n_nets,
+                     int n_in, int n_out, size_t lds, const float *X, const float *T,
+                     float *theta, float *comp, int epochs, float *loss_hist, hipStream_t s) {
+  // registers are sized for the widest hidden layer of the launch
+  const int ht = (max_hidden + 15) / 16;
+  if (ht <= 1)
+    return launch_one<NW, 1>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs,
+                             loss_hist, s);
+  if (ht <= 2)
+    return launch_one<NW, 2>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs,
+                             loss_hist, s);
+  return launch_one<NW, 4>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs,
+                           loss_hist, s);
 }
 
 }  // namespace mlpk
@@ -343,38 +369,36 @@ hipError_t launch_one(const mlp_batch_item *items, mlp_batch_item one, int n_net
 namespace mlph {
 
 size_t small_lds_bytes(int n_rows, int n_hidden, int n_in, int threads) {
-  mlpk::SmallLayout L(n_rows, n_hidden, n_in, 4, threads);
+  mlpk::SmallLayout L(n_rows, n_hidden, n_in, 4, threads / 64);
   return sizeof(float) * (size_t)L.total();
 }
 
 int small_threads(int n_nets, int hint) {
-  if (hint == 256 || hint == 512 || hint == 1024) return hint;
-  return n_nets <= 64 ? 1024 : 256;
+  if (hint == 128 || hint == 256 || hint == 512) return hint;
+  return n_nets <= 64 ? 512 : 128;
 }
 
 size_t small_launch_lds_bytes(int max_rows, int max_hidden, int n_in, int threads) {
-  // The layout grows with N and H but also depends on the phase-F split S,
-  // which shrinks as N grows; bound it over every N up to max_rows.
-  size_t lds = 0;
-  for (int n = 1; n <= max_rows; ++n) lds = std::max(lds, small_lds_bytes(n, max_hidden, n_in, threads));
-  return lds;
+  // the layout grows monotonically with N and H
+  return small_lds_bytes(max_rows, max_hidden, n_in, threads);
 }
 
 hipError_t launch_small_train(const mlp_batch_item *items, mlp_batch_item one, int n_nets,
                               int n_in, int n_out, int max_rows, int max_hidden, const float *X,
                               const float *T, float *theta, float *comp, int epochs,
                               float *loss_hist, int threads, hipStream_t s) {
-  // One net (or a few) alone on the chip: 1024 threads shorten each epoch's
-  // critical path.  Many nets: 256 threads per net, several nets per CU.
+  // fewer waves when the per-wave partial buffers would not fit in LDS
+  while (threads > 128 && small_launch_lds_bytes(max_rows, max_hidden, n_in, threads) > 160 * 1024)
+    threads /= 2;
   const size_t lds = small_launch_lds_bytes(max_rows, max_hidden, n_in, threads);
-  if (threads == 1024)
-    return mlpk::launch_one<1024>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs,
-                                  loss_hist, s);
   if (threads == 512)
-    return mlpk::launch_one<512>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs,
-                                 loss_hist, s);
-  return mlpk::launch_one<256>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs,
-                               loss_hist, s);
+    return mlpk::launch_nw<8>(max_hidden, items, one, n_nets, n_in, n_out, lds, X, T, theta, comp,
+                              epochs, loss_hist, s);
+  if (threads == 256)
+    return mlpk::launch_nw<4>(max_hidden, items, one, n_nets, n_in, n_out, lds, X, T, theta, comp,
+                              epochs, loss_hist, s);
+  return mlpk::launch_nw<2>(max_hidden, items, one, n_nets, n_in, n_out, lds, X, T, theta, comp,
+                            epochs, loss_hist, s);
 }
 
 }  // namespace mlph
