@@ -187,6 +187,30 @@ def train_batched(plan: BatchPlan, X: torch.Tensor, T: torch.Tensor, theta: torc
     return loss_hist
 
 
+class BatchedGraph:
+    """mlp_train_batched captured once in a HIP graph (torch.cuda.CUDAGraph):
+    every replay trains all nets of the plan for `epochs` more epochs, in
+    place, with one graph launch.  The captured work is the single trainer
+    kernel (no memset or copy nodes).  Buffers must stay alive and in place
+    for the graph's lifetime."""
+
+    def __init__(self, plan: BatchPlan, X, T, theta, comp, epochs: int, n_in: int, n_out: int,
+                 loss_hist=None):
+        self.tensors = (X, T, theta, comp, loss_hist)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):   # first launch outside capture (kernel attributes)
+            train_batched(plan, X, T, theta.clone(), None if comp is None else comp.clone(), 1, n_in, n_out)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph, capture_error_mode="thread_local"):
+            train_batched(plan, X, T, theta, comp, epochs, n_in, n_out, loss_hist=loss_hist)
+
+    def replay(self) -> None:
+        self.graph.replay()
+
+
 def set_launch_hint(small_threads: int = 0, large_grid: tuple[int, int] | None = None) -> None:
     """Launch-shape override for the autotuner (0 / None: the library's choice)."""
     gi, gj = large_grid if large_grid else (0, 0)

@@ -1,0 +1,176 @@
+"""Autotuner for libmlp launch shapes.
+
+Two choices are tuned, both through `mlp_set_launch_hint` (include/mlp.h):
+
+  * small / batched trainer: waves per net (128, 256 or 512 threads).  More
+    waves shorten one net's epoch (fewer row tiles per wave); fewer waves let
+    more nets share a CU.
+  * large-N trainer: the Gi x Gj grid (row blocks x hidden blocks).  More
+    row blocks spread the minibatch wider but add partial gradients to sum;
+    more hidden blocks shrink each workgroup's tile but add the cross-block
+    output exchange.
+
+Each candidate is timed on the caller's own data for a short run (HIP
+events on the current stream) and the fastest is cached in a JSON file
+(`$MLP_TUNE_CACHE`, default `~/.cache/paper_1908_07847_amd/tune.json`)
+under a key of the device name, the workload kind and its shape buckets.
+Results differ between launch shapes only in floating-point summation
+order; for a fixed shape every run is bitwise repeatable, so a cached
+choice also pins the bits.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+import torch
+
+from . import mlp
+from ._lib import MLPError
+
+CACHE_ENV = "MLP_TUNE_CACHE"
+SMALL_CHOICES = (128, 256, 512)
+
+
+def cache_path() -> str:
+    return os.environ.get(CACHE_ENV) or os.path.join(os.path.expanduser("~"), ".cache",
+                                                     "paper_1908_07847_amd", "tune.json")
+
+
+def _load_cache() -> dict:
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(key: str, value) -> None:
+    c = _load_cache()
+    c[key] = value
+    p = cache_path()
+    os.makedirs(os.path.dirname(p), exist_ok=True)
+    tmp = p + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as f:
+        json.dump(c, f, indent=1, sort_keys=True)
+    os.replace(tmp, p)
+
+
+def _device() -> str:
+    return torch.cuda.get_device_name() if torch.cuda.is_available() else "cpu"
+
+
+def _bucket(v: int) -> int:
+    """Power-of-two bucket (shapes within a factor of two share a choice)."""
+    b = 1
+    while b < v:
+        b *= 2
+    return b
+
+
+def small_key(n_in: int, max_rows: int, max_hidden: int, n_nets: int) -> str:
+    return f"{_device()}|small|D{n_in}|N{_bucket(max_rows)}|H{_bucket(max_hidden)}|nets{_bucket(n_nets)}"
+
+
+def large_key(n_in: int, n_hidden: int, batch: int, prec: str) -> str:
+    return f"{_device()}|large|D{n_in}|H{_bucket(n_hidden)}|b{_bucket(batch)}|{prec}"
+
+
+def large_candidates(n_hidden: int, batch: int, n_cu: int):
+    """(Gi, Gj) grids the large trainer accepts for this shape: hidden blocks
+    of 64..256 units, row blocks of >= 32 rows, at most one workgroup per CU."""
+    out = []
+    gj = 1
+    while gj <= 16:
+        hb = -(-n_hidden // (64 * gj)) * 64
+        if 64 <= hb <= 256 or (gj == 1 and hb <= 256):
+            gi = 1
+            while gi * gj <= n_cu and gi <= 256:
+                if batch % gi == 0 and (batch // gi) % 32 == 0 and (batch // gi) <= 512:
+                    out.append((gi, gj))
+                gi *= 2
+        gj *= 2
+    return out
+
+
+def _time(fn, reps: int = 2) -> float:
+    fn()
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        s = torch.cuda.current_stream()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(s)
+        fn()
+        b.record(s)
+        torch.cuda.synchronize()
+        best = min(best, a.elapsed_time(b))
+    return best
+
+
+def tune_batched(plan: "mlp.BatchPlan", X, T, theta, n_in: int, n_out: int, epochs: int = 20,
+                 force: bool = False) -> int:
+    """Pick threads per net for mlp_train_batched on this workload (theta is
+    not modified: candidates train copies)."""
+    key = small_key(n_in, plan.max_rows, plan.max_hidden, plan.n)
+    cached = _load_cache().get(key)
+    if cached and not force:
+        return int(cached["threads"])
+    times = {}
+    for t in SMALL_CHOICES:
+        mlp.set_launch_hint(small_threads=t)
+        th = theta.clone()
+        comp = torch.zeros_like(th)
+        try:
+            times[t] = _time(lambda: mlp.train_batched(plan, X, T, th, comp, epochs, n_in, n_out))
+        finally:
+            mlp.reset_launch_hint()
+    best = min(times, key=times.get)
+    _store(key, {"threads": best, "ms": times, "epochs": epochs, "when": time.time()})
+    return best
+
+
+def tune_large(n_in: int, n_hidden: int, n_out: int, batch: int, prec: str, X, T, theta,
+               steps: int = 8, force: bool = False):
+    """Pick the Gi x Gj grid of the large-N trainer by timing `steps`
+    minibatches of the caller's data (parameters are copied, not modified)."""
+    key = large_key(n_in, n_hidden, batch, prec)
+    cached = _load_cache().get(key)
+    if cached and not force:
+        return tuple(cached["grid"])
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    rows = min(X.shape[0], steps * batch)
+    Xs, Ts = X[:rows], T[:rows]
+    times = {}
+    for grid in large_candidates(n_hidden, batch, n_cu):
+        mlp.set_launch_hint(large_grid=grid)
+        try:
+            net = mlp.Net(n_in, n_hidden, n_out, rows, batch=batch, prec=prec, theta=theta)
+            times[grid] = _time(lambda: net.train(Xs, Ts, 1, record_loss=False))
+        except MLPError:
+            continue
+        finally:
+            mlp.reset_launch_hint()
+    best = min(times, key=times.get)
+    _store(key, {"grid": list(best), "ms": {f"{g[0]}x{g[1]}": v for g, v in times.items()},
+                 "steps": rows // batch, "when": time.time()})
+    return best
+
+
+def apply_small(n_in: int, max_rows: int, max_hidden: int, n_nets: int) -> bool:
+    """Set the cached threads-per-net hint for this shape, if any."""
+    c = _load_cache().get(small_key(n_in, max_rows, max_hidden, n_nets))
+    if c:
+        mlp.set_launch_hint(small_threads=int(c["threads"]))
+        return True
+    return False
+
+
+def apply_large(n_in: int, n_hidden: int, batch: int, prec: str) -> bool:
+    """Set the cached grid hint for this shape, if any."""
+    c = _load_cache().get(large_key(n_in, n_hidden, batch, prec))
+    if c:
+        mlp.set_launch_hint(large_grid=tuple(c["grid"]))
+        return True
+    return False

@@ -197,3 +197,22 @@ def test_lowp_many_steps_error_vs_exact_oracle(M, prec, loss_tol, w_tol):
     assert lerr <= loss_tol
     for name, e in errs.items():
         assert e <= w_tol, (name, errs)
+
+
+def test_tuned_grid_keeps_parity(M, tmp_path, monkeypatch):
+    """The autotuner times the candidate grids on the caller's data, caches the
+    fastest, and training with the cached grid still matches the oracle."""
+    monkeypatch.setenv("MLP_TUNE_CACHE", str(tmp_path / "tune.json"))
+    from paper_1908_07847_amd import tune
+    w = synth.single(4, n_rows=8 * 4096)
+    X, T = torch.from_numpy(w["X"]).cuda(), torch.from_numpy(w["T"]).cuda()
+    grid = tune.tune_large(33, 256, 3, 4096, "fp32", X, T, w["theta"], steps=8)
+    say(f"  tuned grid for workload 4: {grid}")
+    assert tune.apply_large(33, 256, 4096, "fp32")
+    try:
+        _, flat, hist = gpu_train(M, w["X"], w["T"], w["theta"], 2, 4096)
+    finally:
+        M.reset_launch_hint()
+    q, ref_hist = oracle.train(w["X"], w["T"], Params.of(w["theta"]), 0.1, 2, batch=4096)
+    for name, e in errors(flat, q).items():
+        assert e <= TOL, name

@@ -294,3 +294,26 @@ def test_backward_over_many_row_chunks(M):
     L, ref = oracle.loss_grad(X, T, Params.of(th))
     assert normwise(gr.flat.cpu().numpy(), ref.flat()) <= TOL
     assert abs(loss.item() - L) <= TOL * L
+
+
+def test_batched_training_as_a_replayed_hip_graph(M, batched_full):
+    """One capture, three replays with the program's own eager work and
+    synchronisations in between; every replay equals the eager call."""
+    w = batched_full
+    items = w["items"][:96]
+    plan = M.BatchPlan(items)
+    X, T = torch.from_numpy(w["X"]).cuda(), torch.from_numpy(w["T"]).cuda()
+    th_e = torch.from_numpy(w["theta"]).cuda()
+    th_g = th_e.clone()
+    c_e, c_g = torch.zeros_like(th_e), torch.zeros_like(th_e)
+    h_e = torch.zeros((len(items), 7), device="cuda")
+    h_g = torch.zeros_like(h_e)
+    graph = M.BatchedGraph(plan, X, T, th_g, c_g, 7, 33, 3, loss_hist=h_g)
+    for rep in range(3):
+        M.train_batched(plan, X, T, th_e, c_e, 7, 33, 3, loss_hist=h_e)
+        junk = torch.randn(1 << 16, device="cuda").sum()     # unrelated eager work
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert junk.isfinite()
+        assert torch.equal(th_g, th_e) and torch.equal(c_g, c_e) and torch.equal(h_g, h_e), rep
