@@ -41,7 +41,12 @@ def _load():
         return _lib
     if not os.path.exists(_SO):
         build()
-    lib = ctypes.CDLL(_SO)
+    _lib = _bind(_SO)
+    return _lib
+
+
+def _bind(path: str):
+    lib = ctypes.CDLL(path)
     P = ctypes.POINTER(ctypes.c_double)
     i64, i32, dbl = ctypes.c_int64, ctypes.c_int, ctypes.c_double
     lib.ora_forward.argtypes = [i64, i32, i32, i32, P, P, P, P, P, P, P]
@@ -65,8 +70,33 @@ def _load():
     lib.ora_train_lowp.argtypes = [i64, i32, i32, i32, i64, P, P, P, P, P, P, dbl, i32, i32, P,
                                    ctypes.c_void_p, P, P]
     lib.ora_round_array.argtypes = [i32, i32, P, P, i64]
-    _lib = lib
     return lib
+
+
+def build_variant(sources, out_path: str) -> str:
+    """Compile other oracle sources (the tests' planted-mistake copies) with the
+    same flags; returns the library path."""
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-w", "-o",
+           out_path] + list(sources) + ["-lm"]
+    subprocess.run(cmd, check=True)
+    return out_path
+
+
+class use_library:
+    """Context manager: route every oracle call to another compiled copy."""
+
+    def __init__(self, path: str):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        self.saved = _load()
+        _lib = _bind(self.path)
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
 
 
 def _d(a) -> np.ndarray:
