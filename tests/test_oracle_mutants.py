@@ -29,8 +29,7 @@ MUTANTS = {
                                        "s += delta2[r * k + o] * W2[(int64_t)j * k + o];"),
     "gW1 uses the activation instead of the input": ("s += delta1[r * h + j] * X[r * d + i];",
                                                      "s += delta1[r * h + j] * A[r * h + (i % h)];"),
-    "minibatch remainder uses the full batch size": ("int64_t m = (r0 + batch <= n) ? batch : n - r0;",
-                                                     "int64_t m = batch;"),
+    "short last minibatch dropped": ("int64_t steps = (n + batch - 1) / batch;", "int64_t steps = n / batch;"),
 }
 
 
