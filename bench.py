@@ -200,6 +200,17 @@ def cpu_batched(ctx, budget_s: float):
                                         f"one net per thread, {cpu_info()}", "seconds": t_total}
 
 
+def copy_probe(n_bytes: int = 1 << 30):
+    """A plain device-to-device copy of known size, used to scale the HBM
+    byte counters (FETCH_SIZE / WRITE_SIZE) of the profiler."""
+    import torch
+    a = torch.ones(n_bytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n_bytes}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -209,7 +220,11 @@ def main():
     ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16", "e4m3"])
     ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true", help="only run a 1 GiB device copy (counter scale)")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this trainer runs on one GPU; the multi-GPU sharding is designed, not "
                                    "built, so --gpus must be 1"}))

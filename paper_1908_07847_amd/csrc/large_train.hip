@@ -149,6 +149,42 @@ __device__ __forceinline__ int e4m3_scale_exp(float amax) {
   return (f <= 0.875f) ? 9 - ex : 8 - ex;
 }
 
+// One e4m3 byte (saturated, round to nearest even).
+__device__ __forceinline__ uint8_t e4m3_byte(float v) {
+  v = fminf(fmaxf(v, -448.f), 448.f);
+  return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0, false) & 0xff);
+}
+
+constexpr int kStageU = 16;  // loads in flight per thread while staging
+constexpr int kPre = 16;     // X elements per thread prefetched a step ahead
+constexpr int kRedU = 32;    // partial-gradient loads in flight per thread
+
+// q / D for 0 <= q < 2^16 and 1 <= D <= 64 with md = ceil(2^22 / D): the
+// error md*D - 2^22 <= D - 1 keeps q*md / 2^22 below the next integer.
+__device__ __forceinline__ int div_by(int q, uint32_t md) {
+  return (int)(((uint64_t)(uint32_t)q * md) >> 22);
+}
+
+// Copy n contiguous floats src[0..n) through registers: each thread loads
+// U elements (stride kLT) before storing any, so a batch costs one memory
+// round trip.  store(q, v) places element q.
+template <int U, typename F>
+__device__ __forceinline__ void stage_flat(const float *src, int n, int tid, F &&store) {
+  for (int base = 0; base < n; base += U * kLT) {
+    float v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = base + u * kLT + tid;
+      v[u] = q < n ? src[q] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = base + u * kLT + tid;
+      if (q < n) store(q, v[u]);
+    }
+  }
+}
+
 template <int PREC>
 struct Ops;
 
@@ -272,6 +308,81 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
   }
   const float sx = ldexpf(1.0f, ex), isx = ldexpf(1.0f, -ex);
 
+  // ---- X staging.  The row block of a step is a contiguous run of X
+  // (RB x D floats); rows past the end of a short last minibatch are zero.
+  // The first kPre * kLT elements go through registers (loaded one step
+  // ahead, during the previous update); larger blocks stage the remainder
+  // directly.
+  const int XTS = L.xts();
+  const uint32_t mdD = ((1u << 22) + (uint32_t)D - 1) / (uint32_t)D;
+  auto block_rows = [&](int st, int64_t &rb0_, int &rows_) {
+    const int sidx_ = st % a.steps_per_epoch;
+    const int64_t r0_ = (int64_t)sidx_ * a.b;
+    const int64_t m_ = min((int64_t)a.b, a.N - r0_);
+    rb0_ = r0_ + (int64_t)gi * RB;
+    rows_ = (int)max((int64_t)0, min((int64_t)RB, m_ - (int64_t)gi * RB));
+  };
+  auto put_x = [&](int q, float v) {
+    const int rr = div_by(q, mdD), c = q - rr * D;
+    if (PREC == 0) {
+      reinterpret_cast<float *>(xr)[rr * XROW + c] = v;
+    } else if (PREC == 1) {
+      const __bf16 bv = (__bf16)v;
+      reinterpret_cast<__bf16 *>(xr)[rr * XROW + c] = bv;
+      reinterpret_cast<__bf16 *>(xt)[c * XTS + rr] = bv;
+    } else {
+      const uint8_t bv = e4m3_byte(v * sx);
+      reinterpret_cast<uint8_t *>(xr)[rr * XROW + c] = bv;
+      reinterpret_cast<uint8_t *>(xt)[c * XTS + rr] = bv;
+    }
+  };
+  auto load_x = [&](int st, float (&v)[kPre]) {
+    int64_t rb0_;
+    int rows_;
+    block_rows(st, rb0_, rows_);
+    const float *src = a.X + rb0_ * D;
+    const int nv = rows_ * D;
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+      const int q = u * kLT + tid;
+      v[u] = q < nv ? src[q] : 0.0f;
+    }
+  };
+  auto store_x = [&](int st, const float (&v)[kPre]) {
+    const int n = RB * D;
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+      const int q = u * kLT + tid;
+      if (q < n) put_x(q, v[u]);
+    }
+    if (n > kPre * kLT) {
+      int64_t rb0_;
+      int rows_;
+      block_rows(st, rb0_, rows_);
+      const int nv = rows_ * D;
+      const float *src = a.X + rb0_ * D;
+      for (int base = kPre * kLT; base < n; base += kStageU * kLT) {
+        float w[kStageU];
+#pragma unroll
+        for (int u = 0; u < kStageU; ++u) {
+          const int q = base + u * kLT + tid;
+          w[u] = q < nv ? src[q] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kStageU; ++u) {
+          const int q = base + u * kLT + tid;
+          if (q < n) put_x(q, w[u]);
+        }
+      }
+    }
+  };
+  float xpre[kPre];
+
+  // LDS operand padding (feature columns D..DK, hidden rows past H) is
+  // written once here; the per-step staging writes only real entries.
+  for (int q = tid; q < L.b1() / 4; q += kLT) reinterpret_cast<float *>(smb)[q] = 0.0f;
+  __syncthreads();
+
   const int total_steps = a.epochs * a.steps_per_epoch;
   for (int step = 0; step < total_steps; ++step) {
     const int e = step / a.steps_per_epoch, sidx = step - e * a.steps_per_epoch;
@@ -304,10 +415,21 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
         ed = e4m3_scale_exp(bound);
       } else {
         float mw = 0.0f, md = 0.0f;
-        for (int g = 0; g < G; ++g) {
+        for (int g = tid; g < G; g += kLT) {
           mw = fmaxf(mw, a.amax[par * G + g]);              // written by the previous update
           md = fmaxf(md, a.amax[2 * G + (par ^ 1) * G + g]);  // previous step's delta1
         }
+        for (int off = 32; off >= 1; off >>= 1) {
+          mw = fmaxf(mw, __shfl_xor(mw, off, kWave));
+          md = fmaxf(md, __shfl_xor(md, off, kWave));
+        }
+        if (lane == 0) {
+          red[24 + wave] = mw;
+          red[28 + wave] = md;
+        }
+        __syncthreads();
+        mw = fmaxf(fmaxf(red[24], red[25]), fmaxf(red[26], red[27]));
+        md = fmaxf(fmaxf(red[28], red[29]), fmaxf(red[30], red[31]));
         ew = e4m3_scale_exp(mw);
         ed = e4m3_scale_exp(md);
       }
@@ -315,90 +437,130 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
     const float sw = ldexpf(1.0f, ew), isw = ldexpf(1.0f, -ew);
     const float sd = ldexpf(1.0f, ed), isd = ldexpf(1.0f, -ed);
 
-    // ---- stage this workgroup's slice of W1 (operand precision), b1, W2
-    for (int q = tid; q < HB * XROW; q += kLT) {
-      const int hl = q / XROW, c = q - hl * XROW;
-      const int h = gj * HB + hl;
-      float v = (h < H && c < D) ? a.theta[(int64_t)h * D + c] : 0.0f;
-      if (PREC == 0) reinterpret_cast<float *>(w1s)[q] = v;
-      if (PREC == 1) reinterpret_cast<__bf16 *>(w1s)[q] = (__bf16)v;
-      if (PREC == 2 && (c & 3) == 0) {
-        // four neighbours at once (rows are 16-byte multiples)
-        float v1 = (h < H && c + 1 < D) ? a.theta[(int64_t)h * D + c + 1] : 0.0f;
-        float v2 = (h < H && c + 2 < D) ? a.theta[(int64_t)h * D + c + 2] : 0.0f;
-        float v3 = (h < H && c + 3 < D) ? a.theta[(int64_t)h * D + c + 3] : 0.0f;
-        *reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(w1s) + q) =
-            pack_e4m3x4(v * sw, v1 * sw, v2 * sw, v3 * sw);
-      }
-    }
-    for (int q = tid; q < HB; q += kLT) {
-      const int h = gj * HB + q;
-      b1s[q] = h < H ? a.theta[oB1 + h] : 0.0f;
-    }
-    for (int q = tid; q < kMaxK * HB; q += kLT) {
-      const int k = q / HB, hl = q - k * HB, h = gj * HB + hl;
-      w2s[q] = (k < K && h < H) ? a.theta[oW2 + (int64_t)k * H + h] : 0.0f;
-    }
-
-    // Stage this workgroup's row block of X into xr (and xt), operand
-    // precision, once per step: one round of global loads for both phases.
-    const int XTS = L.xts();
-    for (int q = tid; q < RB * 16; q += kLT) {   // 16 groups of 4 columns per row
-      const int rr = q >> 4, c = (q & 15) * 4;
-      const bool on = rr < rows_here;
-      const float *src = a.X + (rb0 + rr) * D;
-      float v[4];
+    // ---- stage this workgroup's slice of W1 (operand precision), b1, W2.
+    // The slice is a contiguous run of theta; every thread issues all of its
+    // loads before the first store (one memory round trip, not one per row).
+    {
+      // b1 and W2 of the hidden block: (1 + kMaxK) HB <= 5 kLT values,
+      // loaded together with the first batch of W1
+      constexpr int kBW = (1 + kMaxK) * 256 / kLT;
+      float bw[kBW];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) v[u] = (on && c + u < D) ? src[c + u] : 0.0f;
-      if (PREC == 0) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) reinterpret_cast<float *>(xr)[rr * XROW + c + u] = v[u];
-      } else if (PREC == 1) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const __bf16 bv = (__bf16)v[u];
-          reinterpret_cast<__bf16 *>(xr)[rr * XROW + c + u] = bv;
-          reinterpret_cast<__bf16 *>(xt)[(c + u) * XTS + rr] = bv;
+      for (int u = 0; u < kBW; ++u) {
+        const int q = tid + u * kLT;             // q < HB: b1, else W2 row k = q / HB - 1
+        const int k = q / HB - 1, hl = q - (k + 1) * HB, h = gj * HB + hl;
+        bw[u] = 0.0f;
+        if (q < (1 + kMaxK) * HB && h < H) {
+          if (k < 0) bw[u] = a.theta[oB1 + h];
+          else if (k < K) bw[u] = a.theta[oW2 + (int64_t)k * H + h];
         }
-      } else {
-        const uint32_t pk = pack_e4m3x4(v[0] * sx, v[1] * sx, v[2] * sx, v[3] * sx);
-        *reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(xr) + rr * XROW + c) = pk;
+      }
+      const int hv = max(0, min(HB, H - gj * HB));          // real hidden units here
+      const float *w1src = a.theta + (int64_t)gj * HB * D;
+      stage_flat<kStageU>(w1src, hv * D, tid, [&](int q, float v) {
+        const int hl = div_by(q, mdD), c = q - hl * D;
+        const int o = hl * XROW + c;
+        if (PREC == 0) reinterpret_cast<float *>(w1s)[o] = v;
+        if (PREC == 1) reinterpret_cast<__bf16 *>(w1s)[o] = (__bf16)v;
+        if (PREC == 2) reinterpret_cast<uint8_t *>(w1s)[o] = e4m3_byte(v * sw);
+      });
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-          reinterpret_cast<uint8_t *>(xt)[(c + u) * XTS + rr] = (uint8_t)(pk >> (8 * u));
+      for (int u = 0; u < kBW; ++u) {
+        const int q = tid + u * kLT;
+        if (q < HB) b1s[q] = bw[u];
+        else if (q < (1 + kMaxK) * HB) w2s[q - HB] = bw[u];
       }
     }
+    // ---- this step's row block of X: the part prefetched into registers
+    // during the previous step's update, then the rest (if any) directly.
+    if (step == 0) load_x(step, xpre);
+    store_x(step, xpre);
     __syncthreads();
 
-    // z1 block for rows [c0 + rs*16, +16) of the block and hidden block hb of
-    // this wave: lane holds rows 4*lg+i, hidden unit 16*hb + l16.
-    auto z1_block = [&](int c0, int rs, int hb) -> f32x4 {
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-      const int hl = wave * HW + hb * 16 + l16;   // local hidden row in w1s
+    // z1 tiles for rows [c0, c0 + 32) of the block and every hidden block hb
+    // of this wave: zt[hb][rs] holds rows c0 + 16 rs + 4 lg + i, hidden unit
+    // 16 hb + l16.  The X operands of the 32 rows are loaded once and reused
+    // across hidden blocks; all MFMAs are issued before any result is used.
+    auto z1_tiles = [&](int c0, f32x4 (&zt)[4][2]) {
       if (PREC == 0) {
-        const float *xa = reinterpret_cast<const float *>(xr) + (c0 + rs * 16 + l16) * XROW + lg;
-        const float *wb = reinterpret_cast<const float *>(w1s) + hl * XROW + lg;
-        for (int k0 = 0; k0 < DK; k0 += 4)
-          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[k0], wb[k0], acc, 0, 0, 0);
+        float xa[2][16];
+#pragma unroll
+        for (int rs = 0; rs < 2; ++rs)
+#pragma unroll
+          for (int st = 0; st < 16; ++st)
+            xa[rs][st] = (4 * st < DK)
+                             ? reinterpret_cast<const float *>(xr)[(c0 + rs * 16 + l16) * XROW + lg + 4 * st]
+                             : 0.0f;
+#pragma unroll
+        for (int hb = 0; hb < 4; ++hb) {
+          f32x4 z0 = {0.f, 0.f, 0.f, 0.f}, z1v = {0.f, 0.f, 0.f, 0.f};
+          if (hb < NHB) {
+            const float *wb = reinterpret_cast<const float *>(w1s) + (wave * HW + hb * 16 + l16) * XROW + lg;
+#pragma unroll
+            for (int st = 0; st < 16; ++st) {
+              if (4 * st < DK) {
+                const float wv = wb[4 * st];
+                z0 = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[0][st], wv, z0, 0, 0, 0);
+                z1v = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[1][st], wv, z1v, 0, 0, 0);
+              }
+            }
+          }
+          zt[hb][0] = z0;
+          zt[hb][1] = z1v;
+        }
       } else if (PREC == 1) {
-        const __bf16 *xa = reinterpret_cast<const __bf16 *>(xr) + (c0 + rs * 16 + l16) * XROW + 8 * lg;
-        const __bf16 *wb = reinterpret_cast<const __bf16 *>(w1s) + hl * XROW + 8 * lg;
-        for (int k0 = 0; k0 < DK; k0 += 32) {
-          const bf16x8 av = *reinterpret_cast<const bf16x8 *>(xa + k0);
-          const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(wb + k0);
-          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+        bf16x8 xa[2][2];
+#pragma unroll
+        for (int rs = 0; rs < 2; ++rs)
+#pragma unroll
+          for (int ks = 0; ks < 2; ++ks)
+            if (32 * ks < DK)
+              xa[rs][ks] = *reinterpret_cast<const bf16x8 *>(
+                  reinterpret_cast<const __bf16 *>(xr) + (c0 + rs * 16 + l16) * XROW + 8 * lg + 32 * ks);
+#pragma unroll
+        for (int hb = 0; hb < 4; ++hb) {
+          f32x4 z0 = {0.f, 0.f, 0.f, 0.f}, z1v = {0.f, 0.f, 0.f, 0.f};
+          if (hb < NHB) {
+            const __bf16 *wb = reinterpret_cast<const __bf16 *>(w1s) + (wave * HW + hb * 16 + l16) * XROW + 8 * lg;
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+              if (32 * ks < DK) {
+                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(wb + 32 * ks);
+                z0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[0][ks], bv, z0, 0, 0, 0);
+                z1v = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[1][ks], bv, z1v, 0, 0, 0);
+              }
+            }
+          }
+          zt[hb][0] = z0;
+          zt[hb][1] = z1v;
         }
       } else {
-        const uint8_t *xa = reinterpret_cast<const uint8_t *>(xr) + (c0 + rs * 16 + l16) * XROW + 8 * lg;
-        const uint8_t *wb = reinterpret_cast<const uint8_t *>(w1s) + hl * XROW + 8 * lg;
-        for (int k0 = 0; k0 < DK; k0 += 32) {
-          const long av = *reinterpret_cast<const long *>(xa + k0);
-          const long bv = *reinterpret_cast<const long *>(wb + k0);
-          acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bv, acc, 0, 0, 0);
+        long xa[2][2];
+#pragma unroll
+        for (int rs = 0; rs < 2; ++rs)
+#pragma unroll
+          for (int ks = 0; ks < 2; ++ks)
+            if (32 * ks < DK)
+              xa[rs][ks] = *reinterpret_cast<const long *>(
+                  reinterpret_cast<const uint8_t *>(xr) + (c0 + rs * 16 + l16) * XROW + 8 * lg + 32 * ks);
+#pragma unroll
+        for (int hb = 0; hb < 4; ++hb) {
+          f32x4 z0 = {0.f, 0.f, 0.f, 0.f}, z1v = {0.f, 0.f, 0.f, 0.f};
+          if (hb < NHB) {
+            const uint8_t *wb = reinterpret_cast<const uint8_t *>(w1s) + (wave * HW + hb * 16 + l16) * XROW + 8 * lg;
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+              if (32 * ks < DK) {
+                const long bv = *reinterpret_cast<const long *>(wb + 32 * ks);
+                z0 = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(xa[0][ks], bv, z0, 0, 0, 0);
+                z1v = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(xa[1][ks], bv, z1v, 0, 0, 0);
+              }
+            }
+          }
+          zt[hb][0] = z0 * (isx * isw);
+          zt[hb][1] = z1v * (isx * isw);
         }
-        acc *= isx * isw;
       }
-      return acc;
     };
 
     // ================================================================ phase 1
@@ -412,7 +574,11 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
           for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int k = 0; k < kMaxK; ++k) zp[rs][i][k] = 0.0f;
-        for (int hb = 0; hb < NHB; ++hb) {
+        f32x4 zt[4][2];
+        z1_tiles(c0, zt);
+#pragma unroll
+        for (int hb = 0; hb < 4; ++hb) {
+          if (hb >= NHB) continue;
           const int hl = wave * HW + hb * 16 + l16;
           const float bias = b1s[hl];
           float w2v[kMaxK];
@@ -420,7 +586,7 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
           for (int k = 0; k < kMaxK; ++k) w2v[k] = w2s[k * HB + hl];
 #pragma unroll
           for (int rs = 0; rs < 2; ++rs) {
-            const f32x4 z = z1_block(c0, rs, hb);
+            const f32x4 z = zt[hb][rs];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               const float av = sigmoid(z[i] + bias);
@@ -436,9 +602,7 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
           for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int k = 0; k < kMaxK; ++k) {
-              float v = zp[rs][i][k];
-              for (int off = 8; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
-              zp[rs][i][k] = v;
+              zp[rs][i][k] = sum16(zp[rs][i][k]);
             }
         if (l16 == 0) {
 #pragma unroll
@@ -473,7 +637,11 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
           for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int k = 0; k < kMaxK; ++k) zp[rs][i][k] = 0.0f;
-        for (int hb = 0; hb < NHB; ++hb) {
+        f32x4 zt[4][2];
+        z1_tiles(c0, zt);
+#pragma unroll
+        for (int hb = 0; hb < 4; ++hb) {
+          if (hb >= NHB) continue;
           const int hl = wave * HW + hb * 16 + l16;
           const float bias = b1s[hl];
           float w2v[kMaxK];
@@ -481,7 +649,7 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
           for (int k = 0; k < kMaxK; ++k) w2v[k] = w2s[k * HB + hl];
 #pragma unroll
           for (int rs = 0; rs < 2; ++rs) {
-            const f32x4 z = z1_block(c0, rs, hb);
+            const f32x4 z = zt[hb][rs];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               const float av = sigmoid(z[i] + bias);
@@ -496,9 +664,7 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
           for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int k = 0; k < kMaxK; ++k) {
-              float v = zp[rs][i][k];
-              for (int off = 8; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
-              zp[rs][i][k] = v;
+              zp[rs][i][k] = sum16(zp[rs][i][k]);
             }
         if (l16 == 0) {
 #pragma unroll
@@ -520,22 +686,50 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
       __syncthreads();
     }
     float sq = 0.0f;
-    for (int q = tid; q < RB * 4; q += kLT) {
-      const int rr = q >> 2, k = q & 3;
-      float d = 0.0f;
-      if (k < K && rr < rows_here) {
-        float z = a.theta[oB2 + k];
-        if (split) {
-          for (int g = 0; g < a.Gj; ++g) z += a.z2p[((int64_t)g * a.b + (int64_t)gi * RB + rr) * 4 + k];
-        } else {
-          z += d2s[q];
-        }
-        const float y = sigmoid(z);
-        const float err = y - a.T[(rb0 + rr) * K + k];
-        sq = fmaf(err, err, sq);
-        d = dscale * err * y * (1.0f - y);
+    {
+      // entries (row, output) of this block, kIt per thread at the largest
+      // row block; every load (b2, targets, the Gj partials) is issued before
+      // the first use
+      constexpr int kIt = 512 * 4 / kLT;
+      float zv[kIt], tv[kIt];
+#pragma unroll
+      for (int it = 0; it < kIt; ++it) {
+        const int q = tid + it * kLT, rr = q >> 2, k = q & 3;
+        const bool on = q < RB * 4 && k < K && rr < rows_here;
+        zv[it] = on ? a.theta[oB2 + k] : 0.0f;
+        tv[it] = on ? a.T[(rb0 + rr) * K + k] : 0.0f;
       }
-      d2s[q] = d;  // each entry is read and rewritten by the same thread
+      if (split) {
+        const float *zb = a.z2p + (int64_t)gi * RB * 4;
+#pragma unroll 4
+        for (int g = 0; g < a.Gj; ++g) {
+#pragma unroll
+          for (int it = 0; it < kIt; ++it) {
+            const int q = tid + it * kLT, rr = q >> 2, k = q & 3;
+            if (q < RB * 4 && k < K && rr < rows_here) zv[it] += zb[(int64_t)g * a.b * 4 + q];
+          }
+        }
+      } else {
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+          const int q = tid + it * kLT, rr = q >> 2, k = q & 3;
+          if (q < RB * 4 && k < K && rr < rows_here) zv[it] += d2s[q];
+        }
+      }
+#pragma unroll
+      for (int it = 0; it < kIt; ++it) {
+        const int q = tid + it * kLT, rr = q >> 2, k = q & 3;
+        if (q < RB * 4) {
+          float d = 0.0f;
+          if (k < K && rr < rows_here) {
+            const float y = sigmoid(zv[it]);
+            const float err = y - tv[it];
+            sq = fmaf(err, err, sq);
+            d = dscale * err * y * (1.0f - y);
+          }
+          d2s[q] = d;  // each entry is read and rewritten by the same thread
+        }
+      }
     }
     __syncthreads();
     // loss and gb2 partials (hidden block 0 only; other blocks hold copies)
@@ -569,6 +763,8 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
     float d1max = 0.0f;
 
     for (int c0 = 0; c0 < RB; c0 += kRC) {
+      f32x4 zt[4][2];
+      z1_tiles(c0, zt);
 #pragma unroll
       for (int hb = 0; hb < 4; ++hb) {
         if (hb < NHB) {
@@ -579,7 +775,7 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
           for (int k = 0; k < kMaxK; ++k) w2v[k] = w2s[k * HB + hl];
 #pragma unroll
           for (int rs = 0; rs < 2; ++rs) {
-            const f32x4 z = z1_block(c0, rs, hb);
+            const f32x4 z = zt[hb][rs];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               const int rr = rs * 16 + 4 * lg + i;          // row within the chunk
@@ -702,37 +898,52 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
     // fixed order and update the master copy.  Lanes run over parameters
     // (coalesced reads of each partial row); with few parameters per
     // workgroup the four waves split the partials and meet in LDS.
+    // next step's X rows: loads in flight while the partials are summed
+    if (step + 1 < total_steps) load_x(step + 1, xpre);
     {
       const int64_t per = (P + G - 1) / G;
       const int64_t p0 = (int64_t)bid * per;
       const int np = (int)max((int64_t)0, min(P, p0 + per) - p0);
       float wmax = 0.0f;
-      auto update = [&](int64_t p, float gsum) {
-        float w = a.theta[p], c = a.comp ? a.comp[p] : 0.0f;
+      auto update = [&](int64_t p, float w, float c, float gsum) {
         gd_update(w, c, a.lr, gsum, a.comp != nullptr);
         a.theta[p] = w;
         if (a.comp) a.comp[p] = c;
         if (p < oB1) wmax = fmaxf(wmax, fabsf(w));
       };
+      // sum of partials g in [g0, g1) of parameter p, in increasing g; the
+      // loads of a batch are all issued before the first add
+      auto psum = [&](int64_t p, int g0, int g1) {
+        const float *src = a.gp + p;
+        float sum = 0.0f;
+        for (int gb = g0; gb < g1; gb += kRedU) {
+          float v[kRedU];
+#pragma unroll
+          for (int u = 0; u < kRedU; ++u) v[u] = (gb + u < g1) ? src[(int64_t)(gb + u) * P] : 0.0f;
+#pragma unroll
+          for (int u = 0; u < kRedU; ++u)
+            if (gb + u < g1) sum += v[u];
+        }
+        return sum;
+      };
       if (np <= 64) {
         const int g0 = (a.Gi * wave) / 4, g1 = (a.Gi * (wave + 1)) / 4;
-        float sum = 0.0f;
+        float w = 0.0f, c = 0.0f, sum = 0.0f;
         if (lane < np) {
-          const float *src = a.gp + p0 + lane;
-#pragma unroll 16
-          for (int g = g0; g < g1; ++g) sum += src[(int64_t)g * P];
+          if (wave == 0) {
+            w = a.theta[p0 + lane];
+            c = a.comp ? a.comp[p0 + lane] : 0.0f;
+          }
+          sum = psum(p0 + lane, g0, g1);
         }
         z2w[wave * 64 + lane] = sum;
         __syncthreads();
         if (wave == 0 && lane < np)
-          update(p0 + lane, (z2w[lane] + z2w[64 + lane]) + (z2w[128 + lane] + z2w[192 + lane]));
+          update(p0 + lane, w, c, (z2w[lane] + z2w[64 + lane]) + (z2w[128 + lane] + z2w[192 + lane]));
       } else {
         for (int q = tid; q < np; q += kLT) {
-          const float *src = a.gp + p0 + q;
-          float sum = 0.0f;
-#pragma unroll 16
-          for (int g = 0; g < a.Gi; ++g) sum += src[(int64_t)g * P];
-          update(p0 + q, sum);
+          const float w = a.theta[p0 + q], c = a.comp ? a.comp[p0 + q] : 0.0f;
+          update(p0 + q, w, c, psum(p0 + q, 0, a.Gi));
         }
       }
       if (PREC == 2) {
@@ -742,14 +953,18 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
         if (tid == 0)
           a.amax[((step + 1) & 1) * G + bid] = fmaxf(fmaxf(red[16], red[17]), fmaxf(red[18], red[19]));
       }
-      if (bid == 0 && tid == 0) {
+      if (bid == 0 && wave == 0) {
+        // lanes take every 64th row block, then a fixed butterfly
         float sl = 0.0f;
-        for (int g = 0; g < a.Gi; ++g) sl += a.lossp[g];
-        const float lstep = sl / ((float)m * (float)K);
-        const float accum = (sidx == 0 ? 0.0f : a.acc[0]) + lstep;
-        a.acc[0] = accum;
-        if (sidx == a.steps_per_epoch - 1 && a.loss_hist)
-          a.loss_hist[e] = accum / (float)a.steps_per_epoch;
+        for (int g = lane; g < a.Gi; g += kWave) sl += a.lossp[g];
+        sl = wave_sum(sl);
+        if (lane == 0) {
+          const float lstep = sl / ((float)m * (float)K);
+          const float accum = (sidx == 0 ? 0.0f : a.acc[0]) + lstep;
+          a.acc[0] = accum;
+          if (sidx == a.steps_per_epoch - 1 && a.loss_hist)
+            a.loss_hist[e] = accum / (float)a.steps_per_epoch;
+        }
       }
     }
     barrier();

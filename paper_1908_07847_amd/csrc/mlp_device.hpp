@@ -72,6 +72,25 @@ __device__ __forceinline__ float wave_sum(float v) {
 
 __device__ __forceinline__ int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
+// v plus lane (v) permuted by a DPP row pattern (a VALU op, no LDS traffic).
+template <int CTRL>
+__device__ __forceinline__ float add_dpp(float v) {
+  const int s = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false);
+  return v + __builtin_bit_cast(float, s);
+}
+
+// Sum over each row of 16 lanes: swap neighbours, swap pairs, mirror within
+// 8, mirror within 16.  Every lane of the row ends with the same value
+// (each step adds two equal-order partial sums), so the result is bitwise
+// identical across the row and across runs.
+__device__ __forceinline__ float sum16(float v) {
+  v = add_dpp<0xB1>(v);   // quad_perm [1,0,3,2]
+  v = add_dpp<0x4E>(v);   // quad_perm [2,3,0,1]
+  v = add_dpp<0x141>(v);  // row_half_mirror
+  v = add_dpp<0x140>(v);  // row_mirror
+  return v;
+}
+
 }  // namespace mlpk
 
 // Launch wrappers implemented in the .hip files and used by the host API.

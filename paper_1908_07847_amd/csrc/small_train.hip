@@ -61,15 +61,6 @@ struct SmallLayout {
   __host__ __device__ int total() const { return part() + NW * PW; }
 };
 
-// Sum over the 16 lanes that share lane / 16 (fixed butterfly).
-__device__ __forceinline__ float sum16(float v) {
-  v += __shfl_xor(v, 1, kWave);
-  v += __shfl_xor(v, 2, kWave);
-  v += __shfl_xor(v, 4, kWave);
-  v += __shfl_xor(v, 8, kWave);
-  return v;
-}
-
 template <int NW, int HTM>
 __global__ __launch_bounds__(NW * 64) void k_small_train(
     const mlp_batch_item *__restrict__ items, mlp_batch_item one, int D, int K,

@@ -120,7 +120,7 @@ def test_full_workload4_trains_and_is_deterministic(M):
     say(f"  full workload 4: loss per epoch {ha}")
 
 
-def rounding_flip_bound(d1, bp, Xq, prec, ed, lr):
+def rounding_flip_bound(d1, bp, Xq, prec, ed, lr, unc_extra=0.0):
     """Bound on |dW1_gpu - dW1_oracle| per entry from delta1 operands that lie so
     close to a rounding tie of the operand format that the kernel's float32 delta1
     may round to the other neighbour.  The kernel's delta1 = (delta2 W2) a (1 - a)
@@ -128,8 +128,10 @@ def rounding_flip_bound(d1, bp, Xq, prec, ed, lr):
     a, and hence a (1 - a), is good to ~1e-7 absolute; the margin is 10x) plus a few
     float32 ulps of the product.  Such an operand may differ from the oracle's
     rounded value by one spacing of the format; every other operand is identical.
+    unc_extra adds the part of the uncertainty that the rounded forward pass
+    carries (see propagated_delta1_uncertainty).
     Returns (bound [H][D], fraction of delta1 entries that are ambiguous)."""
-    unc = 1e-6 * np.abs(bp) + 1e-6 * np.abs(d1)
+    unc = 1e-6 * np.abs(bp) + 1e-6 * np.abs(d1) + unc_extra
     s = 2.0 ** ed if prec == "e4m3" else 1.0
     au, us = np.abs(d1 * s), unc * s
     ex = np.floor(np.log2(np.where(au > 0, au, 1.0)))
@@ -138,6 +140,29 @@ def rounding_flip_bound(d1, bp, Xq, prec, ed, lr):
     amb = np.abs(frac - 0.5) * spacing <= us
     dq = np.where(amb, spacing / s, 0.0)
     return lr * (dq.T @ np.abs(Xq)), float(amb.mean())
+
+
+def propagated_delta1_uncertainty(Xq, W1q, p0, T, acc_rel):
+    """First-order bound on how far the kernel's float32 delta1 may sit from the
+    oracle's because the hidden pre-activation z1 = Xq W1q^T comes out of an
+    MFMA whose internal sum is good to acc_rel of the sum of |terms|:
+      |dz1| <= acc_rel S,  S = |Xq| |W1q|^T
+      |da|  <= a (1 - a) |dz1|
+      |d delta2| <= c (y(1-y) + |y-t||1-2y|) y(1-y) sum_h |W2| |da|,  c = 2/(nK)
+      |d bp| <= sum_k |W2| |d delta2|
+      |d delta1| <= |bp| |1-2a| |da| + a(1-a) |d bp|
+    (Algebra of the backpropagation step of section 2.2 with the MSE reading.)"""
+    sig = lambda z: 1.0 / (1.0 + np.exp(-z))
+    a = sig(Xq @ W1q.T + p0.b1)
+    y = sig(a @ p0.W2.T + p0.b2)
+    n, k = y.shape
+    c = 2.0 / (n * k)
+    da = a * (1.0 - a) * acc_rel * (np.abs(Xq) @ np.abs(W1q).T)
+    gy = c * (y * (1.0 - y) + np.abs(y - T) * np.abs(1.0 - 2.0 * y))
+    dd2 = gy * y * (1.0 - y) * (da @ np.abs(p0.W2).T)
+    dbp = dd2 @ np.abs(p0.W2)
+    bp = (c * (y - T) * y * (1.0 - y)) @ p0.W2
+    return np.abs(bp) * np.abs(1.0 - 2.0 * a) * da + a * (1.0 - a) * dbp
 
 
 @pytest.mark.parametrize("prec", ["bf16", "e4m3"])
@@ -173,10 +198,12 @@ def test_lowp_single_step_matches_emulating_oracle(M, prec):
             say(f"  {prec} workload {wl} single step: update error {name} {e:.2e}")
             assert e <= tol, (name, e)
         assert abs(hist[0] - ref_hist[0]) <= tol * ref_hist[0]
-        ex, ed = (int(slog[0, 0]), int(slog[0, 2])) if prec == "e4m3" else (0, 0)
+        ex, ew, ed = (int(slog[0, 0]), int(slog[0, 1]), int(slog[0, 2])) if prec == "e4m3" else (0, 0, 0)
         Xq = oracle.round_array(w["X"], prec, ex)
+        W1q = oracle.round_array(p0.W1, prec, ew)
         d1q = oracle.round_array(d1, prec, ed)
-        bound, amb = rounding_flip_bound(d1, bp, Xq, prec, ed, lr)
+        unc = propagated_delta1_uncertainty(Xq, W1q, p0, w["T"].astype(np.float64), acc_rel)
+        bound, amb = rounding_flip_bound(d1, bp, Xq, prec, ed, lr, unc)
         bound += lr * acc_rel * (np.abs(d1q).T @ np.abs(Xq))
         du = g.W1.astype(np.float64) - p0.W1
         dr = q.W1 - p0.W1
