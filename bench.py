@@ -21,6 +21,7 @@ of the same workload on the host cores.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -35,6 +36,36 @@ sys.path.insert(0, ROOT)
 # PFLOP/s, fp8 5.0 PFLOP/s, HBM 8 TB/s.
 PEAK = {"fp32": 157.3, "bf16": 2516.6, "e4m3": 5033.2}
 PEAK_HBM_GBS = 8000.0
+
+
+# Source files that define each timed kernel: a counter record in
+# profiles/counters.json applies only while these are unchanged.
+KERNEL_SOURCES = {
+    "small": ["small_train.hip", "mlp_device.hpp"],
+    "large": ["large_train.hip", "mlp_device.hpp", "mlp_large.hpp"],
+}
+
+
+def kernel_source_hash(kind: str) -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kind]:
+        with open(os.path.join(ROOT, "paper_1908_07847_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(key: str, kind: str):
+    """HBM bytes per launch from the profiler's FETCH_SIZE and WRITE_SIZE
+    counters (scaled by a plain copy of known size), if a record for this
+    workload was taken on the current kernel source; else None."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "counters.json")) as f:
+            rec = json.load(f)[key]
+    except (OSError, ValueError, KeyError):
+        return None
+    if rec.get("source") != kernel_source_hash(kind):
+        return None
+    return rec["hbm_bytes_per_launch"]
 
 
 def flops_per_sample_epoch(D: int, H: int, K: int) -> int:
@@ -101,10 +132,12 @@ def bench_single(args):
     n_updates = steps * (-(-N // batch))
     if wl in (4, 5):
         flops = contraction_flops_per_sample(D, H) * N * steps
-        bound, peak, unit, kname = "mfma", PEAK[prec], "TFLOP/s", f"k_large_train<{prec}>"
+        pi = {"fp32": 0, "bf16": 1, "e4m3": 2}[prec]
+        bound, peak, unit, kname, kind = "mfma", PEAK[prec], "TFLOP/s", f"mlpk::k_large_train<{pi}>", "large"
     else:
         flops = flops_per_sample_epoch(D, H, K) * N * steps + 2 * P * n_updates
-        bound, peak, unit, kname = "alu", PEAK["fp32"], "TFLOP/s", "k_small_train<1024>"
+        bound, peak, unit, kname, kind = "alu", PEAK["fp32"], "TFLOP/s", "mlpk::k_small_train", "small"
+    tkey = f"{args.workload}-{prec}-steps{steps}"
     achieved = flops / kern / 1e12
     names = {1: "plain-small: N=60 x 33, 33-10-3, full batch",
              2: "differentiation: N=120 x 33, 33-16-3, full batch (fused mlp_train)",
@@ -117,7 +150,8 @@ def bench_single(args):
                 "n_hidden": H, "n_out": K, "batch": batch, "lr": w["lr"], "compensated_update": True,
                 "operand_precision": prec, "step": "one epoch"},
         roofline={"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
-                  "traffic": None, "kernel": kname, "kernel_ms": kern * 1e3, "flops_per_launch": flops},
+                  "traffic": measured_traffic(tkey, kind), "traffic_unit": "bytes per launch", "kernel": kname,
+                  "kernel_ms": kern * 1e3, "flops_per_launch": flops},
         final_loss=float(hist[steps - 1].item()) if steps else None, steps=steps, warmup=warmup)
     return res, dict(w=w, wl=wl, batch=batch)
 
@@ -147,7 +181,7 @@ def cpu_single(ctx, budget_s: float):
 # ---------------------------------------------------------------- batched (w3)
 def bench_batched(args):
     import torch
-    from paper_1908_07847_amd import mlp, synth
+    from paper_1908_07847_amd import mlp, synth, tune
 
     w = synth.batched()
     items = w["items"]
@@ -158,11 +192,17 @@ def bench_batched(args):
     comp = torch.zeros_like(th)
     steps = args.steps if args.steps is not None else w["epochs"]
     warmup = args.warmup if args.warmup is not None else 5
+    # launch shape from the autotuner (timed on copies, cached per device and shape)
+    threads = tune.tune_batched(plan, X, T, th, 33, 3, epochs=20)
+    mlp.set_launch_hint(small_threads=threads)
     if warmup:
         mlp.train_batched(plan, X, T, th.clone(), torch.zeros_like(th), warmup, 33, 3)
     hist = torch.empty((len(items), steps), device="cuda")
+    # the timed launch is one replay of a HIP graph holding the whole run
+    graph = mlp.BatchedGraph(plan, X, T, th, comp, steps, 33, 3, loss_hist=hist)
     stream = torch.cuda.current_stream()
-    wall, kern = timed(lambda: mlp.train_batched(plan, X, T, th, comp, steps, 33, 3, loss_hist=hist), stream)
+    wall, kern = timed(graph.replay, stream)
+    mlp.reset_launch_hint()
     rows = sum(it["n_rows"] for it in items)
     flops = 0
     for it in items:
@@ -175,9 +215,11 @@ def bench_batched(args):
         ms_per_step=wall * 1e3 / steps, dtype="f32",
         config={"workload": "batched: 4096 independent 33-H-3 nets, H~U{4..64}, 40..120 rows each "
                             "(5-fold CV splits), lr~logU(0.01,1), full batch, one launch",
-                "nets": len(items), "total_rows": rows, "step": "one epoch of every net"},
+                "nets": len(items), "total_rows": rows, "step": "one epoch of every net",
+                "threads_per_net": threads, "launch": "hipGraph replay of one persistent kernel"},
         roofline={"bound": "alu", "achieved": achieved, "peak": PEAK["fp32"], "unit": "TFLOP/s",
-                  "frac": achieved / PEAK["fp32"], "traffic": None, "kernel": "k_small_train<256>",
+                  "frac": achieved / PEAK["fp32"], "traffic": measured_traffic(f"w3-fp32-steps{steps}", "small"),
+                  "traffic_unit": "bytes per launch", "kernel": "mlpk::k_small_train",
                   "kernel_ms": kern * 1e3, "flops_per_launch": flops}, steps=steps, warmup=warmup)
     return res, dict(w=w)
 
