@@ -159,6 +159,35 @@ mlp_status mlp_train_batched(const mlp_batch_item *items_host, const mlp_batch_i
                              float *comp_packed, int64_t total_params, int32_t epochs,
                              float *loss_hist, void *stream);
 
+/* ---- networks sharing one dataset --------------------------------------- */
+
+#define MLP_MAX_SHARED_NETS 64
+
+/* Workspace bytes for mlp_train_shared with n_nets nets of shape cfg. */
+mlp_status mlp_shared_workspace_size(const mlp_config *cfg /*host*/, int32_t n_nets, size_t *bytes /*host out*/);
+
+/* Train n_nets independent networks of the shape in cfg on the same X[N][D]
+ * and T[N][K], in one kernel launch: the training loop of section 2.2 (the
+ * same minibatches, loss and update as mlp_train) for every net, with its
+ * own initial parameters and learning rate -- a grid over learning rates and
+ * initialisations evaluated on one dataset.  The nets exchange nothing; the
+ * launch shares the staging of X's row blocks between them.
+ *   cfg        shape, minibatch, operand precision and flags of every net;
+ *              n_in <= 64, n_out <= 4, batch a multiple of 32; FP8_E4M3
+ *              needs n_nets == 1 (its scales are per tensor)
+ *   n_nets     1 .. MLP_MAX_SHARED_NETS
+ *   lr         host [n_nets] learning rates, or NULL for cfg->lr for all
+ *   theta      [n_nets][P] packed parameters, updated in place
+ *   comp       [n_nets][P] compensation terms (needed iff MLP_F_COMPENSATED)
+ *   loss_hist  [n_nets][epochs] per-epoch losses as in mlp_train, or NULL
+ *   workspace  >= mlp_shared_workspace_size bytes, 16-byte aligned; its
+ *              contents on entry do not matter
+ * Results of net i equal mlp_train of net i alone up to float summation
+ * order; for a fixed device and n_nets they are bitwise repeatable. */
+mlp_status mlp_train_shared(const mlp_config *cfg /*host*/, int32_t n_nets, const float *lr /*host*/,
+                            const float *X, const float *T, float *theta, float *comp, int32_t epochs,
+                            float *loss_hist, void *workspace, size_t ws_bytes, void *stream);
+
 /* ---- launch-shape hints -------------------------------------------------- */
 
 /* Overrides of launch shapes that do not change results beyond summation

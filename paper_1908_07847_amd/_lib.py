@@ -16,6 +16,7 @@ MLP_OK, MLP_ERR_ARG, MLP_ERR_SHAPE, MLP_ERR_ALIGN, MLP_ERR_WORKSPACE, MLP_ERR_UN
 PREC = {"fp32": 0, "bf16": 1, "e4m3": 2}
 MLP_F_COMPENSATED = 1
 SMALL_MAX_ROWS, SMALL_MAX_HIDDEN, SMALL_MAX_IN, SMALL_MAX_OUT = 128, 64, 48, 4
+MAX_SHARED_NETS = 64
 
 
 class MLPError(RuntimeError):
@@ -49,7 +50,8 @@ assert ctypes.sizeof(BatchItem) == 32 and ctypes.sizeof(Config) == 40 and ctypes
 
 # Every symbol include/mlp.h declares.
 SYMBOLS = ["mlp_workspace_size", "mlp_init", "mlp_destroy", "mlp_forward", "mlp_backward", "mlp_step",
-           "mlp_train", "mlp_train_batched", "mlp_set_launch_hint", "mlp_status_string", "mlp_last_error"]
+           "mlp_train", "mlp_train_batched", "mlp_shared_workspace_size", "mlp_train_shared",
+           "mlp_set_launch_hint", "mlp_status_string", "mlp_last_error"]
 
 
 def _load():
@@ -67,8 +69,11 @@ def _load():
     lib.mlp_train.argtypes = [vp, vp, vp, i32, vp, vp]
     lib.mlp_train_batched.argtypes = [ctypes.POINTER(BatchItem), vp, i32, i32, i32, vp, vp, i64, vp, vp,
                                       i64, i32, vp, vp]
+    lib.mlp_shared_workspace_size.argtypes = [ctypes.POINTER(Config), i32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.mlp_train_shared.argtypes = [ctypes.POINTER(Config), i32, ctypes.POINTER(f32), vp, vp, vp, vp, i32, vp,
+                                     vp, ctypes.c_size_t, vp]
     lib.mlp_set_launch_hint.argtypes = [ctypes.POINTER(LaunchHint)]
-    for name in SYMBOLS[:9]:
+    for name in SYMBOLS[:11]:
         getattr(lib, name).restype = ctypes.c_int
     lib.mlp_status_string.argtypes = [ctypes.c_int]
     lib.mlp_status_string.restype = ctypes.c_char_p

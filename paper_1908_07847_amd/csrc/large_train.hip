@@ -45,19 +45,20 @@ constexpr int kLT = 256;     // threads per workgroup (4 waves)
 constexpr int kRC = 32;      // rows per chunk
 constexpr int kMaxD = 64;    // features
 constexpr int kMaxK = 4;     // outputs
+constexpr int kMaxNets = 64; // nets sharing X in one launch
 
 struct LargeArgs {
   const float *X, *T;
   float *theta, *comp, *loss_hist;
-  float *z2p;        // [Gj][b][4] partial output pre-activations
-  float *gp;         // [Gi][P] partial gradients
-  float *lossp;      // [Gi] partial squared errors
-  float *amax;       // [2][G] W1 amax partials, [2][G] delta1 amax partials
-  float *acc;        // [4]: epoch loss accumulator, dataset |X| amax, ...
+  float *z2p;        // [M Gj][b][4] partial output pre-activations
+  float *gp;         // [Gi][M P] partial gradients
+  float *lossp;      // [Gi][M] partial squared errors
+  float *amax;       // [2][G] W1 amax partials, [2][G] delta1 amax partials, [G] |X|
+  float *acc;        // [M]: epoch loss accumulators
   unsigned *bar;     // grid-barrier counters (see GridSync)
   int64_t N, b;
-  int D, H, Hp, K, Gi, Gj, epochs, steps_per_epoch;
-  float lr;
+  int D, H, Hp, K, Gi, Gj, M, RBP, epochs, steps_per_epoch;
+  float lr[kMaxNets];  // learning rate of each net
 };
 
 // ---------------------------------------------------------------- barrier
@@ -244,27 +245,33 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
   constexpr int XROW = O::XROW;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int G = a.Gi * a.Gj;
+  // Column blocks: M nets x Gj hidden blocks each (M > 1: nets that share X).
+  const int Gc = a.M * a.Gj, G = a.Gi * Gc;
   // XCD-aware placement: workgroups are dispatched round-robin over the 8
-  // XCDs, so the Gj workgroups that share a row block (and its X rows) get
+  // XCDs, so the Gc workgroups that share a row block (and its X rows) get
   // the same blockIdx % 8 and hence the same L2.
   const int bid = blockIdx.x;
-  int gi, gj;
+  int gi, gc;
   if (G % 8 == 0 && a.Gi % 8 == 0) {
     const int xcd = bid & 7, q = bid >> 3;
-    gj = q % a.Gj;
-    gi = (q / a.Gj) * 8 + xcd;
+    gc = q % Gc;
+    gi = (q / Gc) * 8 + xcd;
   } else {
-    gi = bid / a.Gj;
-    gj = bid - gi * a.Gj;
+    gi = bid / Gc;
+    gc = bid - gi * Gc;
   }
+  const int net = gc / a.Gj, gj = gc - net * a.Gj;
   const int D = a.D, H = a.H, K = a.K;
   const int HB = a.Hp / a.Gj, HW = HB / 4, NHB = HW / 16;
-  const int RB = (int)(a.b / a.Gi);
+  const int RB = (int)(a.b / a.Gi);     // rows of this workgroup's block
+  const int RBP = a.RBP;                // rows staged in LDS at a time (divides RB)
+  const int NPc = RB / RBP;             // pieces of the block
   const int h0 = gj * HB + wave * HW;     // first hidden unit of this wave
   const int64_t P = (int64_t)D * H + H + (int64_t)H * K + K;
+  const int64_t PT = P * a.M;           // parameters of all nets
   const int64_t oB1 = (int64_t)D * H, oW2 = oB1 + H, oB2 = oW2 + (int64_t)H * K;
-  const LLayout<PREC> L(HB, RB);
+  float *th = a.theta + (int64_t)net * P;   // this workgroup's net
+  const LLayout<PREC> L(HB, RBP);
   const int KS = O::KSTEP;
   const int DK = (D + KS - 1) / KS * KS;      // padded contraction length of z1
   const int NFB = (D + 15) / 16;              // 16-wide feature blocks of gW1
@@ -308,19 +315,20 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
   }
   const float sx = ldexpf(1.0f, ex), isx = ldexpf(1.0f, -ex);
 
-  // ---- X staging.  The row block of a step is a contiguous run of X
-  // (RB x D floats); rows past the end of a short last minibatch are zero.
-  // The first kPre * kLT elements go through registers (loaded one step
-  // ahead, during the previous update); larger blocks stage the remainder
-  // directly.
+  // ---- X staging.  A piece of a step's row block (RBP rows) is a
+  // contiguous run of X (RBP x D floats); rows past the end of a short last
+  // minibatch are zero.  For piece 0 the first kPre * kLT elements go
+  // through registers (loaded one step ahead, during the previous update);
+  // everything else is staged directly.
   const int XTS = L.xts();
   const uint32_t mdD = ((1u << 22) + (uint32_t)D - 1) / (uint32_t)D;
-  auto block_rows = [&](int st, int64_t &rb0_, int &rows_) {
+  auto block_rows = [&](int st, int pc, int64_t &rb0_, int &rows_) {
     const int sidx_ = st % a.steps_per_epoch;
     const int64_t r0_ = (int64_t)sidx_ * a.b;
     const int64_t m_ = min((int64_t)a.b, a.N - r0_);
-    rb0_ = r0_ + (int64_t)gi * RB;
-    rows_ = (int)max((int64_t)0, min((int64_t)RB, m_ - (int64_t)gi * RB));
+    const int64_t first = (int64_t)gi * RB + (int64_t)pc * RBP;   // within the minibatch
+    rb0_ = r0_ + first;
+    rows_ = (int)max((int64_t)0, min((int64_t)RBP, m_ - first));
   };
   auto put_x = [&](int q, float v) {
     const int rr = div_by(q, mdD), c = q - rr * D;
@@ -339,7 +347,7 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
   auto load_x = [&](int st, float (&v)[kPre]) {
     int64_t rb0_;
     int rows_;
-    block_rows(st, rb0_, rows_);
+    block_rows(st, 0, rb0_, rows_);
     const float *src = a.X + rb0_ * D;
     const int nv = rows_ * D;
 #pragma unroll
@@ -348,20 +356,26 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
       v[u] = q < nv ? src[q] : 0.0f;
     }
   };
-  auto store_x = [&](int st, const float (&v)[kPre]) {
-    const int n = RB * D;
+  // stage piece pc of step st; with v (piece 0 only) its first kPre * kLT
+  // elements come from the registers
+  auto store_x = [&](int st, int pc, const float (*v)[kPre]) {
+    const int n = RBP * D;
+    int from = 0;
+    if (v) {
 #pragma unroll
-    for (int u = 0; u < kPre; ++u) {
-      const int q = u * kLT + tid;
-      if (q < n) put_x(q, v[u]);
+      for (int u = 0; u < kPre; ++u) {
+        const int q = u * kLT + tid;
+        if (q < n) put_x(q, (*v)[u]);
+      }
+      from = kPre * kLT;
     }
-    if (n > kPre * kLT) {
+    if (n > from) {
       int64_t rb0_;
       int rows_;
-      block_rows(st, rb0_, rows_);
+      block_rows(st, pc, rb0_, rows_);
       const int nv = rows_ * D;
       const float *src = a.X + rb0_ * D;
-      for (int base = kPre * kLT; base < n; base += kStageU * kLT) {
+      for (int base = from; base < n; base += kStageU * kLT) {
         float w[kStageU];
 #pragma unroll
         for (int u = 0; u < kStageU; ++u) {
@@ -398,7 +412,7 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
       const int par = step & 1;
       if (step == 0) {
         float mw = 0.0f;
-        for (int64_t q = tid; q < (int64_t)H * D; q += kLT) mw = fmaxf(mw, fabsf(a.theta[q]));
+        for (int64_t q = tid; q < (int64_t)H * D; q += kLT) mw = fmaxf(mw, fabsf(th[q]));
         for (int off = 32; off >= 1; off >>= 1) mw = fmaxf(mw, __shfl_xor(mw, off, kWave));
         if (lane == 0) red[wave] = mw;
         __syncthreads();
@@ -408,7 +422,7 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
         float bound = 0.0f;
         for (int h = 0; h < H; ++h) {
           float col = 0.0f;
-          for (int k = 0; k < K; ++k) col = col + fabsf(a.theta[oW2 + (int64_t)k * H + h]);
+          for (int k = 0; k < K; ++k) col = col + fabsf(th[oW2 + (int64_t)k * H + h]);
           if (col > bound) bound = col;
         }
         bound = bound / (float)(8 * m * K);
@@ -451,12 +465,12 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
         const int k = q / HB - 1, hl = q - (k + 1) * HB, h = gj * HB + hl;
         bw[u] = 0.0f;
         if (q < (1 + kMaxK) * HB && h < H) {
-          if (k < 0) bw[u] = a.theta[oB1 + h];
-          else if (k < K) bw[u] = a.theta[oW2 + (int64_t)k * H + h];
+          if (k < 0) bw[u] = th[oB1 + h];
+          else if (k < K) bw[u] = th[oW2 + (int64_t)k * H + h];
         }
       }
       const int hv = max(0, min(HB, H - gj * HB));          // real hidden units here
-      const float *w1src = a.theta + (int64_t)gj * HB * D;
+      const float *w1src = th + (int64_t)gj * HB * D;
       stage_flat<kStageU>(w1src, hv * D, tid, [&](int q, float v) {
         const int hl = div_by(q, mdD), c = q - hl * D;
         const int o = hl * XROW + c;
@@ -474,7 +488,15 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
     // ---- this step's row block of X: the part prefetched into registers
     // during the previous step's update, then the rest (if any) directly.
     if (step == 0) load_x(step, xpre);
-    store_x(step, xpre);
+    store_x(step, 0, &xpre);
+    int cur_piece = 0;   // piece of the row block held in LDS
+    auto stage_piece = [&](int pc) {
+      if (pc == cur_piece) return;
+      __syncthreads();   // every wave is done with the previous piece
+      store_x(step, pc, nullptr);
+      cur_piece = pc;
+      __syncthreads();
+    };
     __syncthreads();
 
     // z1 tiles for rows [c0, c0 + 32) of the block and every hidden block hb
@@ -564,191 +586,78 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
     };
 
     // ================================================================ phase 1
-    const bool split = a.Gj > 1;
-    if (split) {
-      for (int c0 = 0; c0 < RB; c0 += kRC) {
-        float zp[2][4][kMaxK];
+    // z2 partial over this workgroup's hidden block for the 32 rows of chunk
+    // c0 of the piece in LDS; out(rr, k, v) receives row rr's sum for output k
+    auto z2_chunk = [&](int c0, auto &&out) {
+      float zp[2][4][kMaxK];
 #pragma unroll
-        for (int rs = 0; rs < 2; ++rs)
+      for (int rs = 0; rs < 2; ++rs)
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int k = 0; k < kMaxK; ++k) zp[rs][i][k] = 0.0f;
-        f32x4 zt[4][2];
-        z1_tiles(c0, zt);
+          for (int k = 0; k < kMaxK; ++k) zp[rs][i][k] = 0.0f;
+      f32x4 zt[4][2];
+      z1_tiles(c0, zt);
 #pragma unroll
-        for (int hb = 0; hb < 4; ++hb) {
-          if (hb >= NHB) continue;
-          const int hl = wave * HW + hb * 16 + l16;
-          const float bias = b1s[hl];
-          float w2v[kMaxK];
+      for (int hb = 0; hb < 4; ++hb) {
+        if (hb >= NHB) continue;
+        const int hl = wave * HW + hb * 16 + l16;
+        const float bias = b1s[hl];
+        float w2v[kMaxK];
 #pragma unroll
-          for (int k = 0; k < kMaxK; ++k) w2v[k] = w2s[k * HB + hl];
+        for (int k = 0; k < kMaxK; ++k) w2v[k] = w2s[k * HB + hl];
 #pragma unroll
-          for (int rs = 0; rs < 2; ++rs) {
-            const f32x4 z = zt[hb][rs];
+        for (int rs = 0; rs < 2; ++rs) {
+          const f32x4 z = zt[hb][rs];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const float av = sigmoid(z[i] + bias);
+          for (int i = 0; i < 4; ++i) {
+            const float av = sigmoid(z[i] + bias);
 #pragma unroll
-              for (int k = 0; k < kMaxK; ++k) zp[rs][i][k] = fmaf(av, w2v[k], zp[rs][i][k]);
-            }
+            for (int k = 0; k < kMaxK; ++k) zp[rs][i][k] = fmaf(av, w2v[k], zp[rs][i][k]);
           }
         }
-        // sum over the 16 hidden lanes of each row (fixed butterfly)
+      }
+      // sum over the 16 hidden lanes of each row (fixed butterfly)
+#pragma unroll
+      for (int rs = 0; rs < 2; ++rs)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int k = 0; k < kMaxK; ++k) zp[rs][i][k] = sum16(zp[rs][i][k]);
+      if (l16 == 0) {
 #pragma unroll
         for (int rs = 0; rs < 2; ++rs)
 #pragma unroll
           for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int k = 0; k < kMaxK; ++k) {
-              zp[rs][i][k] = sum16(zp[rs][i][k]);
-            }
-        if (l16 == 0) {
-#pragma unroll
-          for (int rs = 0; rs < 2; ++rs)
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-              for (int k = 0; k < kMaxK; ++k)
-                z2w[(wave * kRC + rs * 16 + 4 * lg + i) * 4 + k] = zp[rs][i][k];
-        }
-        __syncthreads();
-        for (int q = tid; q < kRC * 4; q += kLT) {
-          const int rr = q >> 2, k = q & 3;
-          const float v = (z2w[(0 * kRC + rr) * 4 + k] + z2w[(1 * kRC + rr) * 4 + k]) +
-                          (z2w[(2 * kRC + rr) * 4 + k] + z2w[(3 * kRC + rr) * 4 + k]);
-          a.z2p[((int64_t)gj * a.b + (int64_t)gi * RB + c0 + rr) * 4 + k] = v;
-        }
-        __syncthreads();  // z2w is rewritten by the next chunk
+            for (int k = 0; k < kMaxK; ++k) z2w[(wave * kRC + rs * 16 + 4 * lg + i) * 4 + k] = zp[rs][i][k];
+      }
+      __syncthreads();
+      for (int q = tid; q < kRC * 4; q += kLT) {
+        const int rr = q >> 2, k = q & 3;
+        out(rr, k, (z2w[(0 * kRC + rr) * 4 + k] + z2w[(1 * kRC + rr) * 4 + k]) +
+                       (z2w[(2 * kRC + rr) * 4 + k] + z2w[(3 * kRC + rr) * 4 + k]));
+      }
+      __syncthreads();  // z2w is rewritten by the next chunk
+    };
+
+    const bool split = a.Gj > 1;
+    if (split) {
+      // the Gj partials of a row meet in the workspace
+      for (int pc = 0; pc < NPc; ++pc) {
+        stage_piece(pc);
+        const int64_t rowbase = (int64_t)gc * a.b + (int64_t)gi * RB + (int64_t)pc * RBP;
+        for (int c0 = 0; c0 < RBP; c0 += kRC)
+          z2_chunk(c0, [&](int rr, int k, float v) { a.z2p[(rowbase + c0 + rr) * 4 + k] = v; });
       }
       barrier();
     }
 
     // ================================================================ phase 2
-    // output layer, error and delta2 for this block's rows
-    if (!split) {
-      // Gj == 1: z2 partials are complete inside this workgroup
-      for (int c0 = 0; c0 < RB; c0 += kRC) {
-        float zp[2][4][kMaxK];
-#pragma unroll
-        for (int rs = 0; rs < 2; ++rs)
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int k = 0; k < kMaxK; ++k) zp[rs][i][k] = 0.0f;
-        f32x4 zt[4][2];
-        z1_tiles(c0, zt);
-#pragma unroll
-        for (int hb = 0; hb < 4; ++hb) {
-          if (hb >= NHB) continue;
-          const int hl = wave * HW + hb * 16 + l16;
-          const float bias = b1s[hl];
-          float w2v[kMaxK];
-#pragma unroll
-          for (int k = 0; k < kMaxK; ++k) w2v[k] = w2s[k * HB + hl];
-#pragma unroll
-          for (int rs = 0; rs < 2; ++rs) {
-            const f32x4 z = zt[hb][rs];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const float av = sigmoid(z[i] + bias);
-#pragma unroll
-              for (int k = 0; k < kMaxK; ++k) zp[rs][i][k] = fmaf(av, w2v[k], zp[rs][i][k]);
-            }
-          }
-        }
-#pragma unroll
-        for (int rs = 0; rs < 2; ++rs)
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int k = 0; k < kMaxK; ++k) {
-              zp[rs][i][k] = sum16(zp[rs][i][k]);
-            }
-        if (l16 == 0) {
-#pragma unroll
-          for (int rs = 0; rs < 2; ++rs)
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-              for (int k = 0; k < kMaxK; ++k)
-                z2w[(wave * kRC + rs * 16 + 4 * lg + i) * 4 + k] = zp[rs][i][k];
-        }
-        __syncthreads();
-        for (int q = tid; q < kRC * 4; q += kLT) {
-          const int rr = q >> 2, k = q & 3;
-          d2s[(c0 + rr) * 4 + k] = (z2w[(0 * kRC + rr) * 4 + k] + z2w[(1 * kRC + rr) * 4 + k]) +
-                                   (z2w[(2 * kRC + rr) * 4 + k] + z2w[(3 * kRC + rr) * 4 + k]);
-        }
-        __syncthreads();  // z2w is rewritten by the next chunk
-      }
-      __syncthreads();
-    }
-    float sq = 0.0f;
-    {
-      // entries (row, output) of this block, kIt per thread at the largest
-      // row block; every load (b2, targets, the Gj partials) is issued before
-      // the first use
-      constexpr int kIt = 512 * 4 / kLT;
-      float zv[kIt], tv[kIt];
-#pragma unroll
-      for (int it = 0; it < kIt; ++it) {
-        const int q = tid + it * kLT, rr = q >> 2, k = q & 3;
-        const bool on = q < RB * 4 && k < K && rr < rows_here;
-        zv[it] = on ? a.theta[oB2 + k] : 0.0f;
-        tv[it] = on ? a.T[(rb0 + rr) * K + k] : 0.0f;
-      }
-      if (split) {
-        const float *zb = a.z2p + (int64_t)gi * RB * 4;
-#pragma unroll 4
-        for (int g = 0; g < a.Gj; ++g) {
-#pragma unroll
-          for (int it = 0; it < kIt; ++it) {
-            const int q = tid + it * kLT, rr = q >> 2, k = q & 3;
-            if (q < RB * 4 && k < K && rr < rows_here) zv[it] += zb[(int64_t)g * a.b * 4 + q];
-          }
-        }
-      } else {
-#pragma unroll
-        for (int it = 0; it < kIt; ++it) {
-          const int q = tid + it * kLT, rr = q >> 2, k = q & 3;
-          if (q < RB * 4 && k < K && rr < rows_here) zv[it] += d2s[q];
-        }
-      }
-#pragma unroll
-      for (int it = 0; it < kIt; ++it) {
-        const int q = tid + it * kLT, rr = q >> 2, k = q & 3;
-        if (q < RB * 4) {
-          float d = 0.0f;
-          if (k < K && rr < rows_here) {
-            const float y = sigmoid(zv[it]);
-            const float err = y - tv[it];
-            sq = fmaf(err, err, sq);
-            d = dscale * err * y * (1.0f - y);
-          }
-          d2s[q] = d;  // each entry is read and rewritten by the same thread
-        }
-      }
-    }
-    __syncthreads();
-    // loss and gb2 partials (hidden block 0 only; other blocks hold copies)
-    if (gj == 0) {
-      for (int off = 32; off >= 1; off >>= 1) sq += __shfl_xor(sq, off, kWave);
-      if (lane == 0) red[wave] = sq;
-      float gb2 = 0.0f;
-      if (tid < 4 * 64) {
-        // wave w sums output w over the block's rows
-        const int k = wave;
-        for (int rr = lane; rr < RB; rr += 64) gb2 += d2s[rr * 4 + k];
-        for (int off = 32; off >= 1; off >>= 1) gb2 += __shfl_xor(gb2, off, kWave);
-      }
-      __syncthreads();
-      if (tid == 0) a.lossp[gi] = (red[0] + red[1]) + (red[2] + red[3]);
-      if (lane == 0 && wave < K) a.gp[(int64_t)gi * P + oB2 + wave] = gb2;
-    }
-
-    // recompute a, form delta1, accumulate gW1 (MFMA), gb1, gW2
+    // Per piece of the row block (the split case walks the pieces backwards,
+    // starting from the one phase 1 left in LDS): output layer, error and
+    // delta2 of its rows, then delta1 and the gradient contributions.
+    float sq = 0.0f, gb2 = 0.0f;
     f32x4 gacc[4][4];
 #pragma unroll
     for (int hb = 0; hb < 4; ++hb)
@@ -762,7 +671,69 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
       for (int k = 0; k < kMaxK; ++k) gw2[hb][k] = 0.0f;
     float d1max = 0.0f;
 
-    for (int c0 = 0; c0 < RB; c0 += kRC) {
+    for (int t = 0; t < NPc; ++t) {
+      const int pc = split ? NPc - 1 - t : t;
+      stage_piece(pc);
+      const int prow0 = pc * RBP;                                // first row of the piece in the block
+      const int prows = max(0, min(RBP, rows_here - prow0));     // real rows of the piece
+      if (!split) {
+        // Gj == 1: z2 partials are complete inside this workgroup
+        for (int c0 = 0; c0 < RBP; c0 += kRC)
+          z2_chunk(c0, [&](int rr, int k, float v) { d2s[(c0 + rr) * 4 + k] = v; });
+      }
+      {
+        // entries (row, output) of this piece, kIt per thread at the largest
+        // piece; every load (b2, targets, the Gj partials) is issued before
+        // the first use
+        constexpr int kIt = 512 * 4 / kLT;
+        float zv[kIt], tv[kIt];
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+          const int q = tid + it * kLT, rr = q >> 2, k = q & 3;
+          const bool on = q < RBP * 4 && k < K && rr < prows;
+          zv[it] = on ? th[oB2 + k] : 0.0f;
+          tv[it] = on ? a.T[(rb0 + prow0 + rr) * K + k] : 0.0f;
+        }
+        if (split) {
+          const float *zb = a.z2p + ((int64_t)(net * a.Gj) * a.b + (int64_t)gi * RB + prow0) * 4;
+#pragma unroll 4
+          for (int g = 0; g < a.Gj; ++g) {
+#pragma unroll
+            for (int it = 0; it < kIt; ++it) {
+              const int q = tid + it * kLT, rr = q >> 2, k = q & 3;
+              if (q < RBP * 4 && k < K && rr < prows) zv[it] += zb[(int64_t)g * a.b * 4 + q];
+            }
+          }
+        } else {
+#pragma unroll
+          for (int it = 0; it < kIt; ++it) {
+            const int q = tid + it * kLT, rr = q >> 2, k = q & 3;
+            if (q < RBP * 4 && k < K && rr < prows) zv[it] += d2s[q];
+          }
+        }
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+          const int q = tid + it * kLT, rr = q >> 2, k = q & 3;
+          if (q < RBP * 4) {
+            float d = 0.0f;
+            if (k < K && rr < prows) {
+              const float y = sigmoid(zv[it]);
+              const float err = y - tv[it];
+              sq = fmaf(err, err, sq);
+              d = dscale * err * y * (1.0f - y);
+            }
+            d2s[q] = d;  // each entry is read and rewritten by the same thread
+          }
+        }
+      }
+      __syncthreads();
+      // gb2 (hidden block 0 only; other blocks hold copies): wave k sums
+      // output k over the piece's rows, lane-strided
+      if (gj == 0)
+        for (int rr = lane; rr < RBP; rr += 64) gb2 += d2s[rr * 4 + wave];
+
+      // recompute a, form delta1, accumulate gW1 (MFMA), gb1, gW2
+      for (int c0 = 0; c0 < RBP; c0 += kRC) {
       f32x4 zt[4][2];
       z1_tiles(c0, zt);
 #pragma unroll
@@ -843,10 +814,21 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
         }
       }
     }
+    }  // pieces
+
+    // loss and gb2 partials of this net's row block (hidden block 0 only)
+    if (gj == 0) {
+      for (int off = 32; off >= 1; off >>= 1) sq += __shfl_xor(sq, off, kWave);
+      for (int off = 32; off >= 1; off >>= 1) gb2 += __shfl_xor(gb2, off, kWave);
+      if (lane == 0) red[wave] = sq;
+      __syncthreads();
+      if (tid == 0) a.lossp[(int64_t)gi * a.M + net] = (red[0] + red[1]) + (red[2] + red[3]);
+      if (lane == 0 && wave < K) a.gp[(int64_t)gi * PT + (int64_t)net * P + oB2 + wave] = gb2;
+    }
 
     // write this workgroup's partial gradients
     {
-      float *gpi = a.gp + (int64_t)gi * P;
+      float *gpi = a.gp + (int64_t)gi * PT + (int64_t)net * P;
       const float gscale = PREC == 2 ? isd * isx : 1.0f;
 #pragma unroll
       for (int hb = 0; hb < 4; ++hb) {
@@ -894,19 +876,20 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
     barrier();
 
     // ================================================================ phase 3
-    // Sum the Gi partials of this workgroup's slice of the parameters in a
-    // fixed order and update the master copy.  Lanes run over parameters
-    // (coalesced reads of each partial row); with few parameters per
-    // workgroup the four waves split the partials and meet in LDS.
+    // Sum the Gi partials of this workgroup's slice of the parameters (of all
+    // nets) in a fixed order and update the master copy.  Lanes run over
+    // parameters (coalesced reads of each partial row); with few parameters
+    // per workgroup the four waves split the partials and meet in LDS.
     // next step's X rows: loads in flight while the partials are summed
     if (step + 1 < total_steps) load_x(step + 1, xpre);
     {
-      const int64_t per = (P + G - 1) / G;
+      const int64_t per = (PT + G - 1) / G;
       const int64_t p0 = (int64_t)bid * per;
-      const int np = (int)max((int64_t)0, min(P, p0 + per) - p0);
+      const int np = (int)max((int64_t)0, min(PT, p0 + per) - p0);
       float wmax = 0.0f;
       auto update = [&](int64_t p, float w, float c, float gsum) {
-        gd_update(w, c, a.lr, gsum, a.comp != nullptr);
+        const float lr = a.M == 1 ? a.lr[0] : a.lr[(int)(p / P)];
+        gd_update(w, c, lr, gsum, a.comp != nullptr);
         a.theta[p] = w;
         if (a.comp) a.comp[p] = c;
         if (p < oB1) wmax = fmaxf(wmax, fabsf(w));
@@ -919,7 +902,7 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
         for (int gb = g0; gb < g1; gb += kRedU) {
           float v[kRedU];
 #pragma unroll
-          for (int u = 0; u < kRedU; ++u) v[u] = (gb + u < g1) ? src[(int64_t)(gb + u) * P] : 0.0f;
+          for (int u = 0; u < kRedU; ++u) v[u] = (gb + u < g1) ? src[(int64_t)(gb + u) * PT] : 0.0f;
 #pragma unroll
           for (int u = 0; u < kRedU; ++u)
             if (gb + u < g1) sum += v[u];
@@ -953,17 +936,18 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
         if (tid == 0)
           a.amax[((step + 1) & 1) * G + bid] = fmaxf(fmaxf(red[16], red[17]), fmaxf(red[18], red[19]));
       }
-      if (bid == 0 && wave == 0) {
-        // lanes take every 64th row block, then a fixed butterfly
+      if (bid < a.M && wave == 0) {
+        // workgroup n keeps net n's loss: lanes take every 64th row block,
+        // then a fixed butterfly
         float sl = 0.0f;
-        for (int g = lane; g < a.Gi; g += kWave) sl += a.lossp[g];
+        for (int g = lane; g < a.Gi; g += kWave) sl += a.lossp[(int64_t)g * a.M + bid];
         sl = wave_sum(sl);
         if (lane == 0) {
           const float lstep = sl / ((float)m * (float)K);
-          const float accum = (sidx == 0 ? 0.0f : a.acc[0]) + lstep;
-          a.acc[0] = accum;
+          const float accum = (sidx == 0 ? 0.0f : a.acc[bid]) + lstep;
+          a.acc[bid] = accum;
           if (sidx == a.steps_per_epoch - 1 && a.loss_hist)
-            a.loss_hist[e] = accum / (float)a.steps_per_epoch;
+            a.loss_hist[(int64_t)bid * a.epochs + e] = accum / (float)a.steps_per_epoch;
         }
       }
     }
@@ -982,10 +966,11 @@ namespace mlph {
 namespace {
 
 constexpr int kMaxRowBlocks = 256, kMaxHiddenBlocks = 16;
+constexpr size_t kLdsLimit = 160 * 1024;
 int g_grid_rows = 0, g_grid_hidden = 0;  // launch hint (0: automatic)
 
 struct Plan {
-  int Gi, Gj, Hp;
+  int Gi, Gj, Hp, RBP;
   size_t lds;
 };
 
@@ -1000,59 +985,82 @@ size_t lds_for(int prec, int HB, int RB) {
   return lds_bytes<2>(HB, RB);
 }
 
+// Rows staged in LDS at a time: the largest multiple of 32 that divides the
+// row block, is at most 512 and fits the LDS with the hidden block (0: none).
+int piece_rows(int prec, int HB, int RB) {
+  for (int r = std::min(RB, 512) / 32 * 32; r >= 32; r -= 32)
+    if (RB % r == 0 && lds_for(prec, HB, r) <= kLdsLimit) return r;
+  return 0;
+}
+
 int64_t batch_of(const mlp_config &c) { return (c.batch <= 0 || c.batch >= c.n_rows) ? c.n_rows : c.batch; }
+
+int min_hidden_blocks(int H) {
+  int Gj = 1;   // hidden blocks: at most 256 units each (4 waves x 64)
+  while ((H + 64 * Gj - 1) / (64 * Gj) * 64 > 256) Gj *= 2;
+  return Gj;
+}
 
 // Workspace layout (bytes, 256-aligned pieces).
 struct WsLayout {
   size_t z2p, gp, lossp, amax, acc, bar, total;
 };
 
-WsLayout ws_layout(const mlp_config &c, int Gi, int Gj) {
+WsLayout ws_layout(const mlp_config &c, int M, int Gi, int Gj) {
   const int64_t b = batch_of(c);
   const int64_t P = (int64_t)c.n_in * c.n_hidden + c.n_hidden + (int64_t)c.n_hidden * c.n_out + c.n_out;
   const int64_t bp = (b + 31) / 32 * 32 * 2;   // rows padded for any Gi that divides the block
   auto up = [](size_t v) { return (v + 255) / 256 * 256; };
   WsLayout w{};
   size_t o = 0;
-  w.z2p = o; o += up(sizeof(float) * (size_t)Gj * bp * 4);
-  w.gp = o; o += up(sizeof(float) * (size_t)Gi * P);
-  w.lossp = o; o += up(sizeof(float) * (size_t)Gi);
-  w.amax = o; o += up(sizeof(float) * (size_t)5 * Gi * Gj);
-  w.acc = o; o += up(sizeof(float) * 4);
+  w.z2p = o; o += up(sizeof(float) * (size_t)M * Gj * bp * 4);
+  w.gp = o; o += up(sizeof(float) * (size_t)Gi * M * P);
+  w.lossp = o; o += up(sizeof(float) * (size_t)Gi * M);
+  w.amax = o; o += up(sizeof(float) * (size_t)5 * Gi * M * Gj);
+  w.acc = o; o += up(sizeof(float) * (size_t)(M + 4));
   w.bar = o; o += up(sizeof(unsigned) * mlpk::kBarWords);
   w.total = o;
   return w;
 }
 
+// Largest row-block count a plan for M nets may use (one workgroup per CU on
+// devices of up to 256 CUs; M > 1 never splits the hidden layer beyond the
+// minimum).
+int max_row_blocks(int M, int Gj) { return M == 1 ? kMaxRowBlocks : std::max(1, kMaxRowBlocks / (M * Gj)); }
+
 }  // namespace
 
-// Grid shape: Gj hidden blocks of <= 256 units (a multiple of 64), Gi row
-// blocks of >= 32 rows; Gi*Gj workgroups, at most one per CU, and an
-// environment override for the autotuner.
-static bool plan_for(const mlp_config &c, int n_cu, Plan *pl, std::string *why) {
+// Grid shape.  One net: Gj hidden blocks of <= 256 units (a multiple of 64)
+// and Gi row blocks of >= 32 rows, Gi*Gj workgroups filling the CUs, with a
+// launch-hint override for the autotuner.  M > 1 nets sharing X: each net
+// takes the minimum number of hidden blocks, and row blocks are added while
+// Gi*M*Gj workgroups still fit one per CU.  Rows of a block are staged in
+// LDS in pieces (all of them at once when they fit).
+static bool plan_for(const mlp_config &c, int M, int n_cu, Plan *pl, std::string *why) {
   const int64_t b = batch_of(c);
   const int H = c.n_hidden;
-  int Gj = 1;   // hidden blocks: at most 256 units each (4 waves x 64)
-  while ((H + 64 * Gj - 1) / (64 * Gj) * 64 > 256) Gj *= 2;
-  int Gi = 1;   // row blocks: at least 32 rows each, at most one workgroup per CU
-  while (Gi * 2 * Gj <= n_cu && b % (Gi * 2 * 32) == 0) Gi *= 2;
-  // fill the remaining CUs by splitting the hidden layer further
-  while (Gi * Gj * 2 <= n_cu && (H + 64 * Gj * 2 - 1) / (64 * Gj * 2) * 64 >= 64 &&
-         H > 64 * Gj)
-    Gj *= 2;
-  if (g_grid_rows > 0 && g_grid_hidden > 0) {
-    Gi = g_grid_rows;
-    Gj = g_grid_hidden;
+  int Gj = min_hidden_blocks(H);
+  int Gi = 1;   // row blocks: at least 32 rows each
+  while (Gi * 2 * M * Gj <= n_cu && b % (Gi * 2 * 32) == 0 && Gi * 2 <= max_row_blocks(M, Gj)) Gi *= 2;
+  if (M == 1) {
+    // fill the remaining CUs by splitting the hidden layer further
+    while (Gi * Gj * 2 <= n_cu && (H + 64 * Gj * 2 - 1) / (64 * Gj * 2) * 64 >= 64 && H > 64 * Gj)
+      Gj *= 2;
+    if (g_grid_rows > 0 && g_grid_hidden > 0) {
+      Gi = g_grid_rows;
+      Gj = g_grid_hidden;
+    }
   }
   const int Hp = (H + 64 * Gj - 1) / (64 * Gj) * 64 * Gj;
   if (Hp / Gj > 256) { *why = "hidden block above 256 units"; return false; }
-  if (Gi > kMaxRowBlocks || Gj > kMaxHiddenBlocks) { *why = "grid above the workspace plan"; return false; }
+  if (Gi > max_row_blocks(M, Gj) || Gj > kMaxHiddenBlocks) { *why = "grid above the workspace plan"; return false; }
   if (b % Gi != 0 || (b / Gi) % 32 != 0) { *why = "rows per block must be a multiple of 32"; return false; }
   pl->Gi = Gi;
   pl->Gj = Gj;
   pl->Hp = Hp;
-  pl->lds = lds_for(c.prec, Hp / Gj, (int)(b / Gi));
-  if (pl->lds > 160 * 1024) { *why = "row block too large for LDS (use more row blocks)"; return false; }
+  pl->RBP = piece_rows(c.prec, Hp / Gj, (int)(b / Gi));
+  if (pl->RBP == 0) { *why = "no row piece of the block fits the LDS"; return false; }
+  pl->lds = lds_for(c.prec, Hp / Gj, pl->RBP);
   return true;
 }
 
@@ -1061,23 +1069,38 @@ void set_large_grid_hint(int row_blocks, int hidden_blocks) {
   g_grid_hidden = hidden_blocks;
 }
 
-mlp_status large_workspace_bytes(const mlp_config &c, size_t *bytes) {
+mlp_status large_workspace_bytes(const mlp_config &c, int n_nets, size_t *bytes) {
   if (c.n_in > mlpk::kMaxD || c.n_out > mlpk::kMaxK) return MLP_ERR_UNSUPPORTED;
+  if (n_nets < 1 || n_nets > mlpk::kMaxNets) return MLP_ERR_UNSUPPORTED;
   const int64_t b = batch_of(c);
   if (b % 32 != 0) return MLP_ERR_UNSUPPORTED;
   // Size for the largest grid any plan may use.
   size_t best = 0;
-  for (int gj = 1; gj <= kMaxHiddenBlocks; gj *= 2)
-    for (int gi = 1; gi <= kMaxRowBlocks; gi *= 2) best = std::max(best, ws_layout(c, gi, gj).total);
+  if (n_nets == 1) {
+    for (int gj = 1; gj <= kMaxHiddenBlocks; gj *= 2)
+      for (int gi = 1; gi <= kMaxRowBlocks; gi *= 2) best = std::max(best, ws_layout(c, 1, gi, gj).total);
+  } else {
+    const int gj = min_hidden_blocks(c.n_hidden);
+    for (int gi = 1; gi <= max_row_blocks(n_nets, gj); gi *= 2)
+      best = std::max(best, ws_layout(c, n_nets, gi, gj).total);
+  }
   *bytes = best;
   return MLP_OK;
 }
 
-mlp_status large_train(const mlp_config &c, const mlp_params &theta, float *comp, void *ws,
-                       size_t ws_bytes, int n_cu, const float *X, const float *T, int epochs,
-                       float *loss_hist, hipStream_t s, std::string *err) {
+mlp_status large_train(const mlp_config &c, int n_nets, const float *lrs, const mlp_params &theta,
+                       float *comp, void *ws, size_t ws_bytes, int n_cu, const float *X, const float *T,
+                       int epochs, float *loss_hist, hipStream_t s, std::string *err) {
   if (c.n_in > mlpk::kMaxD || c.n_out > mlpk::kMaxK) {
     *err = "large-N trainer supports n_in <= 64 and n_out <= 4";
+    return MLP_ERR_UNSUPPORTED;
+  }
+  if (n_nets < 1 || n_nets > mlpk::kMaxNets) {
+    *err = "between 1 and " + std::to_string(mlpk::kMaxNets) + " nets may share X";
+    return MLP_ERR_UNSUPPORTED;
+  }
+  if (n_nets > 1 && c.prec == MLP_FP8_E4M3) {
+    *err = "nets sharing X train in float32 or bf16 operands (e4m3 scales are per net)";
     return MLP_ERR_UNSUPPORTED;
   }
   const int64_t D = c.n_in, H = c.n_hidden, K = c.n_out;
@@ -1092,11 +1115,11 @@ mlp_status large_train(const mlp_config &c, const mlp_params &theta, float *comp
   }
   Plan pl;
   std::string why;
-  if (!plan_for(c, n_cu, &pl, &why)) {
+  if (!plan_for(c, n_nets, n_cu, &pl, &why)) {
     *err = "no grid for this shape: " + why;
     return MLP_ERR_UNSUPPORTED;
   }
-  const WsLayout wl = ws_layout(c, pl.Gi, pl.Gj);
+  const WsLayout wl = ws_layout(c, n_nets, pl.Gi, pl.Gj);
   if (!ws || ws_bytes < wl.total) {
     *err = "workspace too small for the large-N trainer";
     return MLP_ERR_WORKSPACE;
@@ -1122,9 +1145,11 @@ mlp_status large_train(const mlp_config &c, const mlp_params &theta, float *comp
   a.K = (int)K;
   a.Gi = pl.Gi;
   a.Gj = pl.Gj;
+  a.M = n_nets;
+  a.RBP = pl.RBP;
   a.epochs = epochs;
   a.steps_per_epoch = (int)((c.n_rows + b - 1) / b);
-  a.lr = c.lr;
+  for (int i = 0; i < n_nets; ++i) a.lr[i] = lrs ? lrs[i] : c.lr;
 
   hipLaunchKernelGGL(mlpk::k_zero_u32, dim3(1), dim3(256), 0, s, a.bar, mlpk::kBarWords);
   hipError_t e = hipGetLastError();
@@ -1138,7 +1163,7 @@ mlp_status large_train(const mlp_config &c, const mlp_params &theta, float *comp
   int per_cu = 0;
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, mlpk::kLT, pl.lds);
   if (e != hipSuccess) { *err = std::string("occupancy query: ") + hipGetErrorString(e); return MLP_ERR_HIP; }
-  const int G = pl.Gi * pl.Gj;
+  const int G = pl.Gi * n_nets * pl.Gj;
   if (per_cu * n_cu < G) {
     *err = "grid of " + std::to_string(G) + " workgroups cannot be co-resident (" +
            std::to_string(per_cu) + " per CU)";

@@ -130,7 +130,7 @@ mlp_status mlp_workspace_size(const mlp_config *cfg, size_t *bytes) {
   size_t need = backward_ws_bytes(*cfg);
   if (!small_path(*cfg)) {
     size_t lw = 0;
-    s = mlph::large_workspace_bytes(*cfg, &lw);
+    s = mlph::large_workspace_bytes(*cfg, 1, &lw);
     if (s != MLP_OK && s != MLP_ERR_UNSUPPORTED) return s;
     if (s == MLP_OK) need = std::max(need, lw);
   }
@@ -253,8 +253,8 @@ mlp_status mlp_train(mlp_net *net, const float *X, const float *T, int32_t epoch
                                             (hipStream_t)stream);
     return e == hipSuccess ? MLP_OK : hip_fail(e, "mlp_train (small) launch");
   }
-  return mlph::large_train(net->cfg, net->theta, net->comp, net->ws, net->ws_bytes, net->n_cu, X, T,
-                           epochs, loss_hist, (hipStream_t)stream, &g_last_error);
+  return mlph::large_train(net->cfg, 1, nullptr, net->theta, net->comp, net->ws, net->ws_bytes, net->n_cu,
+                           X, T, epochs, loss_hist, (hipStream_t)stream, &g_last_error);
 }
 
 mlp_status mlp_train_batched(const mlp_batch_item *items_host, const mlp_batch_item *items_dev,
@@ -302,6 +302,53 @@ mlp_status mlp_train_batched(const mlp_batch_item *items_host, const mlp_batch_i
                                           mlph::small_threads(n_nets, g_hint.small_threads),
                                           (hipStream_t)stream);
   return e == hipSuccess ? MLP_OK : hip_fail(e, "mlp_train_batched launch");
+}
+
+mlp_status mlp_shared_workspace_size(const mlp_config *cfg, int32_t n_nets, size_t *bytes) {
+  mlp_status s = check_config(cfg);
+  if (s != MLP_OK) return s;
+  if (!bytes) return fail(MLP_ERR_ARG, "bytes is NULL");
+  if (n_nets < 1 || n_nets > MLP_MAX_SHARED_NETS)
+    return fail(MLP_ERR_SHAPE, "n_nets %d outside [1,%d]", n_nets, MLP_MAX_SHARED_NETS);
+  size_t need = 0;
+  s = mlph::large_workspace_bytes(*cfg, n_nets, &need);
+  if (s != MLP_OK)
+    return fail(s, "no shared-X trainer for this shape (n_in <= 64, n_out <= 4, batch a multiple of 32)");
+  *bytes = (need + 255) / 256 * 256;
+  return MLP_OK;
+}
+
+mlp_status mlp_train_shared(const mlp_config *cfg, int32_t n_nets, const float *lr, const float *X,
+                            const float *T, float *theta, float *comp, int32_t epochs, float *loss_hist,
+                            void *workspace, size_t ws_bytes, void *stream) {
+  size_t need = 0;
+  mlp_status s = mlp_shared_workspace_size(cfg, n_nets, &need);
+  if (s != MLP_OK) return s;
+  if (!X || !T || !theta) return fail(MLP_ERR_ARG, "X, T and theta must not be NULL");
+  if ((cfg->flags & MLP_F_COMPENSATED) && !comp)
+    return fail(MLP_ERR_ARG, "MLP_F_COMPENSATED needs a compensation buffer");
+  if (epochs < 0) return fail(MLP_ERR_ARG, "epochs must be >= 0");
+  if (cfg->prec == MLP_FP8_E4M3 && n_nets > 1)
+    return fail(MLP_ERR_UNSUPPORTED, "e4m3 operands need n_nets == 1 (per-tensor scales)");
+  if (lr)
+    for (int32_t i = 0; i < n_nets; ++i)
+      if (!(lr[i] >= 0.0f) || lr[i] > 1e6f) return fail(MLP_ERR_ARG, "net %d: lr must be finite and >= 0", i);
+  if (!aligned16(X) || !aligned16(T)) return fail(MLP_ERR_ALIGN, "X and T must be 16-byte aligned");
+  if (!aligned4(theta) || (comp && !aligned4(comp)) || (loss_hist && !aligned4(loss_hist)))
+    return fail(MLP_ERR_ALIGN, "theta, comp and loss_hist must be 4-byte aligned");
+  if (!workspace || ws_bytes < need)
+    return fail(MLP_ERR_WORKSPACE, "workspace of %zu bytes given, %zu needed", workspace ? ws_bytes : 0, need);
+  if (!aligned16(workspace)) return fail(MLP_ERR_ALIGN, "workspace must be 16-byte aligned");
+  if (epochs == 0) return MLP_OK;
+  int dev = 0, ncu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+  const int64_t D = cfg->n_in, H = cfg->n_hidden, K = cfg->n_out;
+  mlp_params p{theta, theta + D * H, theta + D * H + H, theta + D * H + H + H * K};
+  return mlph::large_train(*cfg, n_nets, lr, p, (cfg->flags & MLP_F_COMPENSATED) ? comp : nullptr, workspace,
+                           ws_bytes, ncu, X, T, epochs, loss_hist, (hipStream_t)stream, &g_last_error);
 }
 
 }  // extern "C"

@@ -211,6 +211,37 @@ class BatchedGraph:
         self.graph.replay()
 
 
+# ---------------------------------------------------------------- nets sharing one dataset
+def shared_workspace_size(n_in: int, n_hidden: int, n_out: int, n_rows: int, batch: int, n_nets: int,
+                          prec: str = "fp32") -> int:
+    cfg = Config(n_in, n_hidden, n_out, _lib.PREC[prec], n_rows, batch, 0.1, 0)
+    nbytes = ctypes.c_size_t(0)
+    check(lib.mlp_shared_workspace_size(ctypes.byref(cfg), int(n_nets), ctypes.byref(nbytes)))
+    return int(nbytes.value)
+
+
+def train_shared(X: torch.Tensor, T: torch.Tensor, theta: torch.Tensor, lrs, epochs: int, n_hidden: int, *,
+                 batch: int, prec: str = "fp32", comp: torch.Tensor | None = None,
+                 loss_hist: torch.Tensor | None = None, workspace: torch.Tensor | None = None, stream=None):
+    """mlp_train_shared: theta [n_nets][P] (float32, packed per net) trains in
+    place on the shared X [N][D], T [N][K]; lrs holds one learning rate per
+    net; comp (same shape as theta, or None) selects the compensated update.
+    Returns loss_hist [n_nets][epochs] if given (else None)."""
+    M = int(theta.shape[0])
+    N, D = X.shape
+    K = T.shape[1]
+    cfg = Config(int(D), int(n_hidden), int(K), _lib.PREC[prec], int(N), int(batch), float(lrs[0]),
+                 _lib.MLP_F_COMPENSATED if comp is not None else 0)
+    nbytes = ctypes.c_size_t(0)
+    check(lib.mlp_shared_workspace_size(ctypes.byref(cfg), M, ctypes.byref(nbytes)))
+    ws = workspace if workspace is not None else torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8,
+                                                             device=X.device)
+    lr_arr = (ctypes.c_float * M)(*[float(v) for v in lrs])
+    check(lib.mlp_train_shared(ctypes.byref(cfg), M, lr_arr, _ptr(X), _ptr(T), _ptr(theta), _ptr(comp),
+                               int(epochs), _ptr(loss_hist), _ptr(ws), int(ws.numel()), _stream(stream)))
+    return loss_hist
+
+
 def set_launch_hint(small_threads: int = 0, large_grid: tuple[int, int] | None = None) -> None:
     """Launch-shape override for the autotuner (0 / None: the library's choice)."""
     gi, gj = large_grid if large_grid else (0, 0)

@@ -183,3 +183,21 @@ def batched(n_nets: int = 4096, seed_workload: int = 3):
     return dict(X=np.ascontiguousarray(np.concatenate(xs)), T=np.ascontiguousarray(np.concatenate(ts)),
                 theta=np.concatenate(thetas).astype(np.float32), items=items, D=33, K=N_OUT,
                 epochs=WORKLOADS[3]["epochs"], name=WORKLOADS[3]["name"])
+
+
+# learning rates of the nets-sharing-X grid: 10^(-2 + 2j/7), j = 0..7
+SHARED_LR_GRID = tuple(float(10.0 ** (-2.0 + 2.0 * j / 7.0)) for j in range(8))
+
+
+def shared(workload: int = 5, n_nets: int = 64, n_rows: int | None = None, hidden: int | None = None):
+    """Nets that share one dataset (a hyperparameter grid): the rows of a
+    single-network workload, and for net i the learning rate
+    SHARED_LR_GRID[i % 8] with initial parameters from seed group i // 8
+    (so each group of 8 nets starts from the same weights and differs only
+    in the learning rate).  theta is [n_nets][P] float32."""
+    base = single(workload, n_rows=n_rows, hidden=hidden)
+    d, h, k = base["D"], base["H"], base["K"]
+    thetas = [theta0(d, h, k, rng(workload, 100 + i // 8, ROLE_THETA)).packed() for i in range(n_nets)]
+    lrs = [SHARED_LR_GRID[i % 8] for i in range(n_nets)]
+    return dict(X=base["X"], T=base["T"], theta=np.stack(thetas).astype(np.float32), lrs=lrs, D=d, H=h, K=k,
+                batch=base["batch"], epochs=base["epochs"], name=base["name"] + f", {n_nets} nets sharing X")

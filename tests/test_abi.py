@@ -120,3 +120,51 @@ def test_batched_shape_and_pointer_validation():
                                    None) == L.MLP_ERR_ALIGN
     assert L.lib.mlp_train_batched(it, None, 1, 33, 3, 0x2000, 0x3000, 100, 0x4000, None, 10**5, 1, None,
                                    None) == L.MLP_ERR_ARG
+
+
+def _shared_ws(cfg, n):
+    L = _lib()
+    b = ctypes.c_size_t(0)
+    st = L.lib.mlp_shared_workspace_size(ctypes.byref(cfg), n, ctypes.byref(b))
+    return st, b.value
+
+
+def test_shared_workspace_size():
+    L = _lib()
+    c5 = L.Config(64, 1024, 3, 1, 1 << 22, 16384, 0.1, 1)
+    st, n64 = _shared_ws(c5, 64)
+    assert st == L.MLP_OK and n64 % 256 == 0
+    P = 64 * 1024 + 1024 + 1024 * 3 + 3
+    assert n64 >= 64 * P * 4                       # at least one partial-gradient row per net
+    st, n1 = _shared_ws(c5, 1)
+    assert st == L.MLP_OK and n1 > 0
+    assert _shared_ws(c5, 0)[0] == L.MLP_ERR_SHAPE
+    assert _shared_ws(c5, 65)[0] == L.MLP_ERR_SHAPE
+    assert _shared_ws(L.Config(65, 1024, 3, 1, 1 << 22, 16384, 0.1, 1), 4)[0] == L.MLP_ERR_UNSUPPORTED
+    assert _shared_ws(L.Config(64, 1024, 5, 1, 1 << 22, 16384, 0.1, 1), 4)[0] == L.MLP_ERR_UNSUPPORTED
+    assert _shared_ws(L.Config(64, 1024, 3, 1, 1 << 22, 1000, 0.1, 1), 4)[0] == L.MLP_ERR_UNSUPPORTED
+
+
+def test_train_shared_rejects_before_touching_the_device():
+    L = _lib()
+    cfg = L.Config(33, 256, 3, 0, 8192, 1024, 0.1, 1)
+    st, need = _shared_ws(cfg, 4)
+    assert st == L.MLP_OK
+    lrs = (ctypes.c_float * 4)(0.1, 0.2, 0.3, 0.4)
+    args = lambda **kw: dict(dict(cfg=ctypes.byref(cfg), n=4, lr=lrs, X=0x10000, T=0x20000, th=0x30000,
+                                  comp=0x40000, ep=3, lh=None, ws=0x50000, nb=need), **kw)
+    call = lambda a: L.lib.mlp_train_shared(a["cfg"], a["n"], a["lr"], a["X"], a["T"], a["th"], a["comp"],
+                                            a["ep"], a["lh"], a["ws"], a["nb"], None)
+    assert call(args(X=None)) == L.MLP_ERR_ARG
+    assert call(args(comp=None)) == L.MLP_ERR_ARG                 # compensated without a buffer
+    assert call(args(ep=-1)) == L.MLP_ERR_ARG
+    bad = (ctypes.c_float * 4)(0.1, float("nan"), 0.3, 0.4)
+    assert call(args(lr=bad)) == L.MLP_ERR_ARG
+    assert call(args(X=0x10004)) == L.MLP_ERR_ALIGN
+    assert call(args(th=0x30002)) == L.MLP_ERR_ALIGN
+    assert call(args(nb=need - 256)) == L.MLP_ERR_WORKSPACE
+    assert call(args(ws=None)) == L.MLP_ERR_WORKSPACE
+    assert call(args(n=0)) == L.MLP_ERR_SHAPE
+    e4 = L.Config(33, 256, 3, 2, 8192, 1024, 0.1, 1)
+    assert call(args(cfg=ctypes.byref(e4))) == L.MLP_ERR_UNSUPPORTED   # e4m3 with several nets
+    assert call(args(ep=0)) == L.MLP_OK                           # nothing to do, no device work
