@@ -12,7 +12,9 @@ Workloads (all synthetic, from the seeded generator):
   w3   4096 independent nets, H~U{4..64}, 40..120 rows each    step = 1 epoch of every net
   w4   1,048,576 x 33, 33-256-3, minibatch 4096               step = 1 epoch (256 minibatches)
   w5   4,194,304 x 64, 64-1024-3, minibatch 16384             step = 1 epoch (256 minibatches)
-w4/w5 take --prec fp32|bf16|e4m3 (operand precision of the two contractions).
+  w6   64 nets of w5's shape sharing its X (grid of 8 learning rates x 8 initialisations)
+                                                               step = 1 epoch of every net
+w4/w5 take --prec fp32|bf16|e4m3, w6 fp32|bf16 (operand precision of the two contractions).
 The timed region is one training call of K steps (one kernel launch).  The
 JSON line carries the roofline of that kernel, timed with HIP events on the
 stream it runs on, and the FP64 CPU oracle's throughput on a bounded sample
@@ -242,6 +244,67 @@ def cpu_batched(ctx, budget_s: float):
                                         f"one net per thread, {cpu_info()}", "seconds": t_total}
 
 
+# ---------------------------------------------------------------- nets sharing X (w6)
+def bench_shared(args):
+    import torch
+    from paper_1908_07847_amd import mlp, synth
+
+    prec = args.prec if args.prec in ("fp32", "bf16") else "bf16"
+    w = synth.shared(5, n_nets=64)
+    D, H, K, N, batch = w["D"], w["H"], w["K"], w["X"].shape[0], w["batch"]
+    M = w["theta"].shape[0]
+    X = torch.from_numpy(w["X"]).cuda()
+    T = torch.from_numpy(w["T"]).cuda()
+    th0 = torch.from_numpy(w["theta"]).cuda()
+    ws = torch.empty(mlp.shared_workspace_size(D, H, K, N, batch, M, prec), dtype=torch.uint8, device="cuda")
+    steps = args.steps if args.steps is not None else w["epochs"]
+    warmup = args.warmup if args.warmup is not None else 1
+    if warmup:
+        mlp.train_shared(X, T, th0.clone(), w["lrs"], warmup, H, batch=batch, prec=prec,
+                         comp=torch.zeros_like(th0), workspace=ws)
+    th, comp = th0.clone(), torch.zeros_like(th0)
+    hist = torch.empty((M, max(steps, 1)), device="cuda")
+    stream = torch.cuda.current_stream()
+    wall, kern = timed(lambda: mlp.train_shared(X, T, th, w["lrs"], steps, H, batch=batch, prec=prec, comp=comp,
+                                                loss_hist=hist[:, :steps], workspace=ws), stream)
+    flops = contraction_flops_per_sample(D, H) * N * M * steps
+    achieved = flops / kern / 1e12
+    pi = {"fp32": 0, "bf16": 1}[prec]
+    res = dict(
+        metric="training samples*epochs/s", value=M * N * steps / wall, unit="samples*epochs/s",
+        ms_per_step=wall * 1e3 / steps, dtype={"fp32": "f32", "bf16": "bf16"}[prec],
+        config={"workload": "64 nets sharing X: N=4,194,304 x 64, 64-1024-3 each, minibatch 16384, lr grid "
+                            "10^(-2..0) x 8 initialisations, sigmoid both layers, MSE, GD, one launch",
+                "nets": M, "n_rows": N, "n_in": D, "n_hidden": H, "n_out": K, "batch": batch,
+                "compensated_update": True, "operand_precision": prec, "step": "one epoch of every net"},
+        roofline={"bound": "mfma", "achieved": achieved, "peak": PEAK[prec], "unit": "TFLOP/s",
+                  "frac": achieved / PEAK[prec], "traffic": measured_traffic(f"w6-{prec}-steps{steps}", "large"),
+                  "traffic_unit": "bytes per launch", "kernel": f"mlpk::k_large_train<{pi}>",
+                  "kernel_ms": kern * 1e3, "flops_per_launch": flops},
+        final_loss_mean=float(hist[:, steps - 1].mean().item()) if steps else None, steps=steps, warmup=warmup)
+    return res, dict(w=w, batch=batch)
+
+
+def cpu_shared(ctx, budget_s: float):
+    """The oracle trains net after net; one net on the first minibatch for
+    one epoch is the sample (the nets are independent, so the rate of one
+    thread on one net is the oracle's rate for the grid)."""
+    import oracle
+    from paper_1908_07847_amd import synth
+    w, batch = ctx["w"], ctx["batch"]
+    p = oracle.Params.of(synth.Theta.unpack(w["theta"][0], w["D"], w["H"], w["K"]))
+    X, T = w["X"][:batch], w["T"][:batch]
+    reps, t_total = 0, 0.0
+    while (t_total < budget_s or reps == 0) and reps < 50:
+        t0 = time.perf_counter()
+        oracle.train(X, T, p, w["lrs"][0], 1, batch=batch)
+        t_total += time.perf_counter() - t0
+        reps += 1
+    return {"value": batch * reps / t_total, "unit": "samples*epochs/s", "cores": 1, "kind": "oracle",
+            "sample": f"net 0 on the first {batch} rows (one minibatch) for 1 epoch, run {reps} time(s), "
+                      f"float64, single thread, {cpu_info()}", "seconds": t_total}
+
+
 def copy_probe(n_bytes: int = 1 << 30):
     """A plain device-to-device copy of known size, used to scale the HBM
     byte counters (FETCH_SIZE / WRITE_SIZE) of the profiler."""
@@ -258,7 +321,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the workload's epochs)")
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="w2", choices=["w1", "w2", "w3", "w4", "w5"])
+    ap.add_argument("--workload", default="w2", choices=["w1", "w2", "w3", "w4", "w5", "w6"])
     ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16", "e4m3"])
     ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true")
@@ -274,6 +337,9 @@ def main():
     if args.workload == "w3":
         res, ctx = bench_batched(args)
         cpu = None if args.no_cpu else cpu_batched(ctx, args.cpu_budget)
+    elif args.workload == "w6":
+        res, ctx = bench_shared(args)
+        cpu = None if args.no_cpu else cpu_shared(ctx, args.cpu_budget)
     else:
         res, ctx = bench_single(args)
         cpu = None if args.no_cpu else cpu_single(ctx, args.cpu_budget)

@@ -330,62 +330,77 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
     rb0_ = r0_ + first;
     rows_ = (int)max((int64_t)0, min((int64_t)RBP, m_ - first));
   };
-  auto put_x = [&](int q, float v) {
-    const int rr = div_by(q, mdD), c = q - rr * D;
+  // A staging unit is 8 consecutive rows of one feature: unit u holds rows
+  // 8 (u / D) .. +7 and feature u % D.  Lanes run over features, so each of
+  // the unit's 8 loads is a coalesced run of an X row; the 8 values land in
+  // the row-major copy one by one and in the transposed copy (operand of
+  // gW1 = delta1^T X) as one 16-byte (bf16) or 8-byte (e4m3) store.
+  constexpr int kUnitsPre = kPre / 8;      // units per thread held in xpre
+  constexpr int kUnitsBatch = kStageU / 8;  // units per thread per direct batch
+  const int n_units = RBP / 8 * D;
+  auto put_unit = [&](int u, const float *v) {
+    const int r8 = div_by(u, mdD), c = u - r8 * D, rr = r8 * 8;
     if (PREC == 0) {
-      reinterpret_cast<float *>(xr)[rr * XROW + c] = v;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) reinterpret_cast<float *>(xr)[(rr + j) * XROW + c] = v[j];
     } else if (PREC == 1) {
-      const __bf16 bv = (__bf16)v;
-      reinterpret_cast<__bf16 *>(xr)[rr * XROW + c] = bv;
-      reinterpret_cast<__bf16 *>(xt)[c * XTS + rr] = bv;
+      bf16x8 t;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        t[j] = (__bf16)v[j];
+        reinterpret_cast<__bf16 *>(xr)[(rr + j) * XROW + c] = t[j];
+      }
+      *reinterpret_cast<bf16x8 *>(reinterpret_cast<__bf16 *>(xt) + c * XTS + rr) = t;
     } else {
-      const uint8_t bv = e4m3_byte(v * sx);
-      reinterpret_cast<uint8_t *>(xr)[rr * XROW + c] = bv;
-      reinterpret_cast<uint8_t *>(xt)[c * XTS + rr] = bv;
+      uint64_t t = 0;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const uint8_t bv = e4m3_byte(v[j] * sx);
+        reinterpret_cast<uint8_t *>(xr)[(rr + j) * XROW + c] = bv;
+        t |= (uint64_t)bv << (8 * j);
+      }
+      *reinterpret_cast<uint64_t *>(reinterpret_cast<uint8_t *>(xt) + c * XTS + rr) = t;
     }
+  };
+  // the 8 values of unit u (zero past the real rows of the piece)
+  auto load_unit = [&](const float *src, int rows_, int u, float *v) {
+    const int r8 = div_by(u, mdD), c = u - r8 * D, rr = r8 * 8;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = (u < n_units && rr + j < rows_) ? src[(int64_t)(rr + j) * D + c] : 0.0f;
   };
   auto load_x = [&](int st, float (&v)[kPre]) {
     int64_t rb0_;
     int rows_;
     block_rows(st, 0, rb0_, rows_);
     const float *src = a.X + rb0_ * D;
-    const int nv = rows_ * D;
 #pragma unroll
-    for (int u = 0; u < kPre; ++u) {
-      const int q = u * kLT + tid;
-      v[u] = q < nv ? src[q] : 0.0f;
-    }
+    for (int k = 0; k < kUnitsPre; ++k) load_unit(src, rows_, k * kLT + tid, v + 8 * k);
   };
-  // stage piece pc of step st; with v (piece 0 only) its first kPre * kLT
-  // elements come from the registers
+  // stage piece pc of step st; with v (piece 0 only) its first
+  // kUnitsPre * kLT units come from the registers
   auto store_x = [&](int st, int pc, const float (*v)[kPre]) {
-    const int n = RBP * D;
     int from = 0;
     if (v) {
 #pragma unroll
-      for (int u = 0; u < kPre; ++u) {
-        const int q = u * kLT + tid;
-        if (q < n) put_x(q, (*v)[u]);
+      for (int k = 0; k < kUnitsPre; ++k) {
+        const int u = k * kLT + tid;
+        if (u < n_units) put_unit(u, *v + 8 * k);
       }
-      from = kPre * kLT;
+      from = kUnitsPre * kLT;
     }
-    if (n > from) {
+    if (n_units > from) {
       int64_t rb0_;
       int rows_;
       block_rows(st, pc, rb0_, rows_);
-      const int nv = rows_ * D;
       const float *src = a.X + rb0_ * D;
-      for (int base = from; base < n; base += kStageU * kLT) {
+      for (int base = from; base < n_units; base += kUnitsBatch * kLT) {
         float w[kStageU];
 #pragma unroll
-        for (int u = 0; u < kStageU; ++u) {
-          const int q = base + u * kLT + tid;
-          w[u] = q < nv ? src[q] : 0.0f;
-        }
+        for (int k = 0; k < kUnitsBatch; ++k) load_unit(src, rows_, base + k * kLT + tid, w + 8 * k);
 #pragma unroll
-        for (int u = 0; u < kStageU; ++u) {
-          const int q = base + u * kLT + tid;
-          if (q < n) put_x(q, w[u]);
+        for (int k = 0; k < kUnitsBatch; ++k) {
+          const int u = base + k * kLT + tid;
+          if (u < n_units) put_unit(u, w + 8 * k);
         }
       }
     }

@@ -107,6 +107,7 @@ const char *mlp_last_error(void) { return g_last_error.c_str(); }
 mlp_status mlp_set_launch_hint(const mlp_launch_hint *hint) {
   if (!hint) {
     g_hint = mlp_launch_hint{};
+    mlph::set_large_grid_hint(0, 0);
     return MLP_OK;
   }
   const int t = hint->small_threads;
