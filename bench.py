@@ -170,7 +170,7 @@ def cpu_single(ctx, budget_s: float):
         X, T, epochs = w["X"][:rows], w["T"][:rows], 1
         sample = f"the first {rows} rows ({rows // batch} minibatch(es) of {batch}) for 1 epoch"
     reps, t_total = 0, 0.0
-    while (t_total < budget_s or reps == 0) and reps < 50:
+    while (t_total < budget_s or reps == 0) and reps < 100000:
         t0 = time.perf_counter()
         oracle.train(X, T, p, w["lr"], epochs, batch=0 if wl in (1, 2) else batch)
         t_total += time.perf_counter() - t0
@@ -233,7 +233,7 @@ def cpu_batched(ctx, budget_s: float):
     epochs = 100
     threads = oracle.max_threads()
     reps, t_total = 0, 0.0
-    while (t_total < budget_s or reps == 0) and reps < 50:
+    while (t_total < budget_s or reps == 0) and reps < 100000:
         t0 = time.perf_counter()
         oracle.train_many(items, w["X"], w["T"], w["theta"], 33, 3, epochs, threads=threads)
         t_total += time.perf_counter() - t0
@@ -295,7 +295,7 @@ def cpu_shared(ctx, budget_s: float):
     p = oracle.Params.of(synth.Theta.unpack(w["theta"][0], w["D"], w["H"], w["K"]))
     X, T = w["X"][:batch], w["T"][:batch]
     reps, t_total = 0, 0.0
-    while (t_total < budget_s or reps == 0) and reps < 50:
+    while (t_total < budget_s or reps == 0) and reps < 100000:
         t0 = time.perf_counter()
         oracle.train(X, T, p, w["lrs"][0], 1, batch=batch)
         t_total += time.perf_counter() - t0
