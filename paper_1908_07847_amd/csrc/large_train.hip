@@ -166,6 +166,15 @@ __device__ __forceinline__ int div_by(int q, uint32_t md) {
   return (int)(((uint64_t)(uint32_t)q * md) >> 22);
 }
 
+// *p if ok, else 0, with the load itself unconditional (it reads *safe
+// when !ok): a predicated load becomes a branch around it, and the compiler
+// then waits for the load inside that branch, which serialises a batch of
+// loads that should be in flight together.
+__device__ __forceinline__ float load_if(const float *p, const float *safe, bool ok) {
+  const float v = *(ok ? p : safe);
+  return ok ? v : 0.0f;
+}
+
 // Copy n contiguous floats src[0..n) through registers: each thread loads
 // U elements (stride kLT) before storing any, so a batch costs one memory
 // round trip.  store(q, v) places element q.
@@ -176,7 +185,7 @@ __device__ __forceinline__ void stage_flat(const float *src, int n, int tid, F &
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int q = base + u * kLT + tid;
-      v[u] = q < n ? src[q] : 0.0f;
+      v[u] = load_if(src + q, src, q < n);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -231,7 +240,7 @@ struct LLayout {
   __host__ __device__ int w2() const { return b1() + HB * 4; }
   __host__ __device__ int d2() const { return w2() + kMaxK * HB * 4; }
   __host__ __device__ int z2w() const { return d2() + RB * 16; }
-  __host__ __device__ int dst() const { return z2w() + 4 * kRC * 16; }
+  __host__ __device__ int dst() const { return z2w() + 2 * 4 * kRC * 16; }   // two chunk buffers
   __host__ __device__ int red() const {
     return dst() + 4 * (PREC == 0 ? kRC * 16 * 4 : 16 * Ops<(PREC == 0 ? 1 : PREC)>::DST * esz);
   }
@@ -366,7 +375,7 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
   auto load_unit = [&](const float *src, int rows_, int u, float *v) {
     const int r8 = div_by(u, mdD), c = u - r8 * D, rr = r8 * 8;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = (u < n_units && rr + j < rows_) ? src[(int64_t)(rr + j) * D + c] : 0.0f;
+    for (int j = 0; j < 8; ++j) v[j] = load_if(src + (int64_t)(rr + j) * D + c, a.X, u < n_units && rr + j < rows_);
   };
   auto load_x = [&](int st, float (&v)[kPre]) {
     int64_t rb0_;
@@ -478,11 +487,8 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
       for (int u = 0; u < kBW; ++u) {
         const int q = tid + u * kLT;             // q < HB: b1, else W2 row k = q / HB - 1
         const int k = q / HB - 1, hl = q - (k + 1) * HB, h = gj * HB + hl;
-        bw[u] = 0.0f;
-        if (q < (1 + kMaxK) * HB && h < H) {
-          if (k < 0) bw[u] = th[oB1 + h];
-          else if (k < K) bw[u] = th[oW2 + (int64_t)k * H + h];
-        }
+        const bool ok = q < (1 + kMaxK) * HB && h < H && k < K;
+        bw[u] = load_if(th + (k < 0 ? oB1 + h : oW2 + (int64_t)k * H + h), th, ok);
       }
       const int hv = max(0, min(HB, H - gj * HB));          // real hidden units here
       const float *w1src = th + (int64_t)gj * HB * D;
@@ -518,6 +524,28 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
     // of this wave: zt[hb][rs] holds rows c0 + 16 rs + 4 lg + i, hidden unit
     // 16 hb + l16.  The X operands of the 32 rows are loaded once and reused
     // across hidden blocks; all MFMAs are issued before any result is used.
+    // bf16 / e4m3 W1 operands of this wave's hidden tiles are the same for
+    // every row chunk of the step: read them from LDS once, keep them in
+    // registers (float32 operands would take 64 registers and stay in LDS)
+    bf16x8 w1b[4][2];
+    long w1e[4][2];
+    if (PREC != 0) {
+#pragma unroll
+      for (int hb = 0; hb < 4; ++hb)
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+          const bool on = hb < NHB && 32 * ks < DK;
+          const int o = on ? (wave * HW + hb * 16 + l16) * XROW + 8 * lg + 32 * ks : 0;
+          if (PREC == 1) {
+            const bf16x8 v = *reinterpret_cast<const bf16x8 *>(reinterpret_cast<const __bf16 *>(w1s) + o);
+            const bf16x8 zero = {};
+            w1b[hb][ks] = on ? v : zero;
+          } else {
+            const long v = *reinterpret_cast<const long *>(reinterpret_cast<const uint8_t *>(w1s) + o);
+            w1e[hb][ks] = on ? v : 0l;
+          }
+        }
+    }
     auto z1_tiles = [&](int c0, f32x4 (&zt)[4][2]) {
       if (PREC == 0) {
         float xa[2][16];
@@ -558,13 +586,11 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
         for (int hb = 0; hb < 4; ++hb) {
           f32x4 z0 = {0.f, 0.f, 0.f, 0.f}, z1v = {0.f, 0.f, 0.f, 0.f};
           if (hb < NHB) {
-            const __bf16 *wb = reinterpret_cast<const __bf16 *>(w1s) + (wave * HW + hb * 16 + l16) * XROW + 8 * lg;
 #pragma unroll
             for (int ks = 0; ks < 2; ++ks) {
               if (32 * ks < DK) {
-                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(wb + 32 * ks);
-                z0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[0][ks], bv, z0, 0, 0, 0);
-                z1v = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[1][ks], bv, z1v, 0, 0, 0);
+                z0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[0][ks], w1b[hb][ks], z0, 0, 0, 0);
+                z1v = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[1][ks], w1b[hb][ks], z1v, 0, 0, 0);
               }
             }
           }
@@ -584,13 +610,11 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
         for (int hb = 0; hb < 4; ++hb) {
           f32x4 z0 = {0.f, 0.f, 0.f, 0.f}, z1v = {0.f, 0.f, 0.f, 0.f};
           if (hb < NHB) {
-            const uint8_t *wb = reinterpret_cast<const uint8_t *>(w1s) + (wave * HW + hb * 16 + l16) * XROW + 8 * lg;
 #pragma unroll
             for (int ks = 0; ks < 2; ++ks) {
               if (32 * ks < DK) {
-                const long bv = *reinterpret_cast<const long *>(wb + 32 * ks);
-                z0 = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(xa[0][ks], bv, z0, 0, 0, 0);
-                z1v = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(xa[1][ks], bv, z1v, 0, 0, 0);
+                z0 = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(xa[0][ks], w1e[hb][ks], z0, 0, 0, 0);
+                z1v = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(xa[1][ks], w1e[hb][ks], z1v, 0, 0, 0);
               }
             }
           }
@@ -639,21 +663,24 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
         for (int i = 0; i < 4; ++i)
 #pragma unroll
           for (int k = 0; k < kMaxK; ++k) zp[rs][i][k] = sum16(zp[rs][i][k]);
+      // consecutive chunks alternate between two buffers, so one barrier per
+      // chunk separates the writes of a buffer from the reads of its
+      // previous contents (two chunks back)
+      float *zw = z2w + ((c0 / kRC) & 1) * (4 * kRC * 4);
       if (l16 == 0) {
 #pragma unroll
         for (int rs = 0; rs < 2; ++rs)
 #pragma unroll
           for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int k = 0; k < kMaxK; ++k) z2w[(wave * kRC + rs * 16 + 4 * lg + i) * 4 + k] = zp[rs][i][k];
+            for (int k = 0; k < kMaxK; ++k) zw[(wave * kRC + rs * 16 + 4 * lg + i) * 4 + k] = zp[rs][i][k];
       }
       __syncthreads();
       for (int q = tid; q < kRC * 4; q += kLT) {
         const int rr = q >> 2, k = q & 3;
-        out(rr, k, (z2w[(0 * kRC + rr) * 4 + k] + z2w[(1 * kRC + rr) * 4 + k]) +
-                       (z2w[(2 * kRC + rr) * 4 + k] + z2w[(3 * kRC + rr) * 4 + k]));
+        out(rr, k, (zw[(0 * kRC + rr) * 4 + k] + zw[(1 * kRC + rr) * 4 + k]) +
+                       (zw[(2 * kRC + rr) * 4 + k] + zw[(3 * kRC + rr) * 4 + k]));
       }
-      __syncthreads();  // z2w is rewritten by the next chunk
     };
 
     const bool split = a.Gj > 1;
@@ -695,6 +722,7 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
         // Gj == 1: z2 partials are complete inside this workgroup
         for (int c0 = 0; c0 < RBP; c0 += kRC)
           z2_chunk(c0, [&](int rr, int k, float v) { d2s[(c0 + rr) * 4 + k] = v; });
+        __syncthreads();   // d2s entries are read below by other threads
       }
       {
         // entries (row, output) of this piece, kIt per thread at the largest
@@ -706,8 +734,8 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
         for (int it = 0; it < kIt; ++it) {
           const int q = tid + it * kLT, rr = q >> 2, k = q & 3;
           const bool on = q < RBP * 4 && k < K && rr < prows;
-          zv[it] = on ? th[oB2 + k] : 0.0f;
-          tv[it] = on ? a.T[(rb0 + prow0 + rr) * K + k] : 0.0f;
+          zv[it] = load_if(th + oB2 + k, th, on);
+          tv[it] = load_if(a.T + (rb0 + prow0 + rr) * K + k, a.T, on);
         }
         if (split) {
           const float *zb = a.z2p + ((int64_t)(net * a.Gj) * a.b + (int64_t)gi * RB + prow0) * 4;
@@ -716,7 +744,7 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
 #pragma unroll
             for (int it = 0; it < kIt; ++it) {
               const int q = tid + it * kLT, rr = q >> 2, k = q & 3;
-              if (q < RBP * 4 && k < K && rr < prows) zv[it] += zb[(int64_t)g * a.b * 4 + q];
+              zv[it] += load_if(zb + (int64_t)g * a.b * 4 + q, a.z2p, q < RBP * 4 && k < K && rr < prows);
             }
           }
         } else {
