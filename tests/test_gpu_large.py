@@ -243,3 +243,18 @@ def test_tuned_grid_keeps_parity(M, tmp_path, monkeypatch):
     q, ref_hist = oracle.train(w["X"], w["T"], Params.of(w["theta"]), 0.1, 2, batch=4096)
     for name, e in errors(flat, q).items():
         assert e <= TOL, name
+
+
+def test_wide_workload_65536_row_subset_error_vs_exact_oracle(M):
+    """The wide 64-1024-3 net on the first 65,536 rows (4 minibatches of
+    16384) for one epoch in each operand type, against the exact FP64 oracle:
+    float32 within the float32 tolerance, bf16 / e4m3 within the sanity
+    gates (their errors are printed)."""
+    w = synth.single(5, n_rows=65536)
+    q, ref_hist = oracle.train(w["X"], w["T"], Params.of(w["theta"]), 0.1, 1, batch=16384)
+    for prec, w_tol, l_tol in (("fp32", TOL, TOL), ("bf16", 1e-2, 1e-3), ("e4m3", 1e-1, 5e-2)):
+        _, flat, hist = gpu_train(M, w["X"], w["T"], w["theta"], 1, 16384, prec=prec)
+        errs = errors(flat, q)
+        lerr = float(abs(hist[0] - ref_hist[0]) / ref_hist[0])
+        say(f"  wide net, 65,536 rows, {prec}: params {errs} loss {lerr:.2e}")
+        assert lerr <= l_tol and max(errs.values()) <= w_tol, (prec, errs, lerr)
