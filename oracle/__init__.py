@@ -139,6 +139,15 @@ def forward(X, p: Params):
     return A, Y
 
 
+def predict(X, p: Params):
+    """(Y, labels): the outputs of the forward pass and, per row, the index of
+    the largest output with the lowest index on ties -- the trained network's
+    class (section 2.2's network read as a classifier; np.argmax returns the
+    first maximum)."""
+    _, Y = forward(X, p)
+    return Y, np.argmax(Y, axis=1).astype(np.int32)
+
+
 def mse(Y, T) -> float:
     Y, T = _d(Y), _d(T)
     return float(_load().ora_mse(Y.shape[0], Y.shape[1], _p(Y), _p(T)))

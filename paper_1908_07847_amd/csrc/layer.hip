@@ -13,6 +13,11 @@
 //                  its gradient over all rows in row order, so the result
 //                  is bitwise repeatable.
 //  k_step          theta <- theta - lr g, optionally Kahan-compensated.
+//  k_argmax        one thread per row: the class is the index of the largest
+//                  output (lowest index on ties); with one-hot targets, the
+//                  count of rows whose class matches the target's, summed
+//                  per block and added once per block (integer adds, so the
+//                  count does not depend on their order).
 #include <algorithm>
 
 #include "mlp_device.hpp"
@@ -128,6 +133,39 @@ __global__ __launch_bounds__(256) void k_step(int D, int H, int K, mlp_params p,
 
 }  // namespace mlpk
 
+namespace mlpk {
+
+__global__ void k_fill_i32(int32_t *p, int32_t v) { *p = v; }
+
+__device__ __forceinline__ int argmax_row(const float *v, int K) {
+  int best = 0;
+  for (int k = 1; k < K; ++k)
+    if (v[k] > v[best]) best = k;   // strict: the lowest index wins ties
+  return best;
+}
+
+__global__ __launch_bounds__(256) void k_argmax(int64_t n, int K, const float *__restrict__ Y,
+                                                const float *__restrict__ T, int32_t *__restrict__ labels,
+                                                int32_t *__restrict__ correct) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int hit = 0;
+  if (r < n) {
+    const int c = argmax_row(Y + r * K, K);
+    labels[r] = c;
+    if (T) hit = c == argmax_row(T + r * K, K);
+  }
+  if (T) {
+    __shared__ int part[4];
+    int v = hit;
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(correct, (part[0] + part[1]) + (part[2] + part[3]));
+  }
+}
+
+}  // namespace mlpk
+
 namespace mlph {
 
 static dim3 grid_for(int64_t n, int b) { return dim3((unsigned)((n + b - 1) / b)); }
@@ -135,6 +173,18 @@ static dim3 grid_for(int64_t n, int b) { return dim3((unsigned)((n + b - 1) / b)
 hipError_t launch_forward(int64_t n, int D, int H, int K, const float *X, mlp_params p, float *A,
                           float *Y, hipStream_t s) {
   hipLaunchKernelGGL(mlpk::k_forward, grid_for(n, 256), dim3(256), 0, s, n, D, H, K, X, p, A, Y);
+  return hipGetLastError();
+}
+
+hipError_t launch_predict(int64_t n, int D, int H, int K, const float *X, mlp_params p, float *Y,
+                          int32_t *labels, const float *T, int32_t *correct, hipStream_t s) {
+  hipError_t e = launch_forward(n, D, H, K, X, p, nullptr, Y, s);
+  if (e != hipSuccess) return e;
+  if (T) {
+    hipLaunchKernelGGL(mlpk::k_fill_i32, dim3(1), dim3(1), 0, s, correct, 0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(mlpk::k_argmax, grid_for(n, 256), dim3(256), 0, s, n, K, Y, T, labels, correct);
   return hipGetLastError();
 }
 

@@ -190,6 +190,20 @@ mlp_status mlp_forward(mlp_net *net, const float *X, int64_t n, float *A, float 
   return e == hipSuccess ? MLP_OK : hip_fail(e, "mlp_forward launch");
 }
 
+mlp_status mlp_predict(mlp_net *net, const float *X, int64_t n, float *Y, int32_t *labels, const float *T,
+                       int32_t *correct, void *stream) {
+  if (!net) return fail(MLP_ERR_ARG, "net is NULL");
+  if (!X || !Y || !labels) return fail(MLP_ERR_ARG, "X, Y and labels must not be NULL");
+  if ((T == nullptr) != (correct == nullptr)) return fail(MLP_ERR_ARG, "give T and correct together");
+  if (n <= 0) return fail(MLP_ERR_SHAPE, "n must be positive");
+  if (!aligned16(X) || !aligned4(Y) || !aligned4(labels) || (T && !aligned4(T)) || (correct && !aligned4(correct)))
+    return fail(MLP_ERR_ALIGN, "X must be 16-byte and Y, labels, T, correct 4-byte aligned");
+  const mlp_config &c = net->cfg;
+  hipError_t e = mlph::launch_predict(n, c.n_in, c.n_hidden, c.n_out, X, net->theta, Y, labels, T, correct,
+                                      (hipStream_t)stream);
+  return e == hipSuccess ? MLP_OK : hip_fail(e, "mlp_predict launch");
+}
+
 mlp_status mlp_backward(mlp_net *net, const float *X, const float *A, const float *Y,
                         const float *dY, const float *T, int64_t n, mlp_params grads, float *dX,
                         float *loss, void *stream) {

@@ -119,5 +119,7 @@ hipError_t launch_backward(int64_t n, int64_t ws_rows, int D, int H, int K, cons
                            hipStream_t s);
 hipError_t launch_step(int D, int H, int K, mlp_params p, mlp_params g, float *comp, float lr,
                        hipStream_t s);
+hipError_t launch_predict(int64_t n, int D, int H, int K, const float *X, mlp_params p, float *Y,
+                          int32_t *labels, const float *T, int32_t *correct, hipStream_t s);
 
 }  // namespace mlph

@@ -130,6 +130,16 @@ class Net:
     def step(self, grads: Grads, lr: float | None = None, stream=None) -> None:
         check(lib.mlp_step(self._h, grads.c(), float(self.lr if lr is None else lr), _stream(stream)))
 
+    def predict(self, X: torch.Tensor, T: torch.Tensor | None = None, stream=None):
+        """(Y [n][K], labels [n] int32, number correct or None) -- mlp_predict."""
+        n = X.shape[0]
+        Y = torch.empty((n, self.K), dtype=torch.float32, device=self.device)
+        labels = torch.empty(max(n, 4), dtype=torch.int32, device=self.device)[:n]
+        correct = torch.empty(4, dtype=torch.int32, device=self.device)[:1] if T is not None else None
+        check(lib.mlp_predict(self._h, _ptr(X), n, _ptr(Y), _ptr(labels), _ptr(T), _ptr(correct),
+                              _stream(stream)))
+        return Y, labels, correct
+
     def train(self, X: torch.Tensor, T: torch.Tensor, epochs: int, record_loss: bool = True,
               loss_hist: torch.Tensor | None = None, stream=None):
         if record_loss and loss_hist is None:

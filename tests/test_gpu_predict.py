@@ -1,0 +1,91 @@
+"""mlp_predict against the FP64 oracle: outputs within float32 rounding,
+classes equal wherever the decision is unique (near-ties may go either way
+and are checked to be near-ties), ties to the lowest index, and the correct
+count equal to a count over the returned labels."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import Params
+from paper_1908_07847_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def M():
+    from paper_1908_07847_amd import mlp
+    return mlp
+
+
+def net_for(M, th: synth.Theta, n_rows):
+    return M.Net(th.W1.shape[1], th.W1.shape[0], th.W2.shape[0], n_rows, theta=th)
+
+
+def check_predict(M, net, X, T, th_flat):
+    d, h, k = net.D, net.H, net.K
+    Xd, Td = torch.from_numpy(np.ascontiguousarray(X)).cuda(), torch.from_numpy(np.ascontiguousarray(T)).cuda()
+    Y, lab, cor = net.predict(Xd, Td)
+    torch.cuda.synchronize()
+    Y, lab, cor = Y.cpu().numpy(), lab.cpu().numpy(), int(cor.cpu().numpy()[0])
+    # the decision on the kernel's own float32 outputs is exact
+    assert np.array_equal(lab, np.argmax(Y, axis=1))
+    assert cor == int(np.sum(lab == np.argmax(T, axis=1)))
+    p = Params.of(synth.Theta.unpack(th_flat, d, h, k))
+    Yr, labr = oracle.predict(X, p)
+    err = float(np.max(np.abs(Y - Yr)))
+    assert err <= 1e-6, err
+    # where the oracle's class differs, its top two outputs are within the output error
+    diff = np.nonzero(lab != labr)[0]
+    for r in diff:
+        top = np.sort(Yr[r])[-2:]
+        assert top[1] - top[0] <= 4 * err + 1e-7, (r, Yr[r])
+    return cor, len(diff), err
+
+
+def test_predict_after_training_matches_oracle(M):
+    w = synth.single(2)
+    net = net_for(M, w["theta"], 120)
+    net.train(torch.from_numpy(w["X"]).cuda(), torch.from_numpy(w["T"]).cuda(), 2000)
+    torch.cuda.synchronize()
+    cor, nd, err = check_predict(M, net, w["X"], w["T"], net.flat.cpu().numpy())
+    say(f"  workload 2 after 2000 epochs: {cor}/120 correct, {nd} near-tie differences, output error {err:.1e}")
+
+
+@pytest.mark.parametrize("n", [1, 257, 100_000])
+def test_predict_sizes(M, n):
+    w = synth.single(4, n_rows=max(n, 1))
+    net = net_for(M, w["theta"], n)
+    cor, nd, err = check_predict(M, net, w["X"][:n], w["T"][:n], w["theta"].packed())
+    say(f"  n={n}: {cor} correct, {nd} near-tie differences, output error {err:.1e}")
+
+
+def test_predict_ties_go_to_the_lowest_index(M):
+    w = synth.single(2)
+    th = w["theta"].copy()
+    th.W2[:] = 0.0
+    th.b2[:] = np.array([0.1, 0.5, 0.5], np.float32)
+    net = net_for(M, th, 120)
+    Y, lab, _ = net.predict(torch.from_numpy(w["X"]).cuda())
+    assert np.all(lab.cpu().numpy() == 1)
+    th.b2[:] = 0.25
+    net = net_for(M, th, 120)
+    Y, lab, _ = net.predict(torch.from_numpy(w["X"]).cuda())
+    assert np.all(lab.cpu().numpy() == 0)
+
+
+def test_predict_single_output(M):
+    w = synth.single(2)
+    th = synth.Theta(w["theta"].W1, w["theta"].b1, w["theta"].W2[:1].copy(), w["theta"].b2[:1].copy())
+    net = net_for(M, th, 120)
+    T = np.ascontiguousarray(w["T"][:, :1])
+    cor, _, _ = check_predict(M, net, w["X"], T, th.packed())
+    assert cor == 120

@@ -327,3 +327,23 @@ def test_lowp_step_is_close_to_exact_and_rounds_operands(prec, tol):
     if prec == "e4m3":
         assert slog[0, 0] == oracle.e4m3_scale_exp(np.max(np.abs(w["X"])))
         assert slog[0, 1] == oracle.e4m3_scale_exp(np.max(np.abs(w["theta"].W1)))
+
+
+def test_predict_is_the_first_maximum_of_the_outputs():
+    """Ties go to the lowest index; equal outputs give class 0; the labels
+    equal a plain loop over the rows."""
+    g = np.random.default_rng(3)
+    X = g.standard_normal((50, 4))
+    p = Params(g.uniform(-1, 1, (5, 4)), g.uniform(-1, 1, 5), g.uniform(-1, 1, (3, 5)), g.uniform(-1, 1, 3))
+    Y, lab = oracle.predict(X, p)
+    for r in range(50):
+        best = 0
+        for k in range(1, 3):
+            if Y[r, k] > Y[r, best]:
+                best = k
+        assert lab[r] == best
+    tie = Params(p.W1, p.b1, np.zeros((3, 5)), np.array([0.2, 0.7, 0.7]))
+    _, lab = oracle.predict(X, tie)
+    assert np.all(lab == 1)
+    one = Params(p.W1, p.b1, p.W2[:1], p.b2[:1])
+    assert np.all(oracle.predict(X, one)[1] == 0)
