@@ -14,6 +14,8 @@ Workloads (all synthetic, from the seeded generator):
   w5   4,194,304 x 64, 64-1024-3, minibatch 16384             step = 1 epoch (256 minibatches)
   w6   64 nets of w5's shape sharing its X (grid of 8 learning rates x 8 initialisations)
                                                                step = 1 epoch of every net
+  p4   class predictions (mlp_predict: forward pass + argmax + correct count) on
+       w4's 1,048,576 rows with its 33-256-3 net     metric: predicted rows/s
 w4/w5 take --prec fp32|bf16|e4m3, w6 fp32|bf16 (operand precision of the two contractions).
 The timed region is one training call of K steps (one kernel launch).  The
 JSON line carries the roofline of that kernel, timed with HIP events on the
@@ -135,7 +137,7 @@ def bench_single(args):
     if wl in (4, 5):
         flops = contraction_flops_per_sample(D, H) * N * steps
         pi = {"fp32": 0, "bf16": 1, "e4m3": 2}[prec]
-        bound, peak, unit, kname, kind = "mfma", PEAK[prec], "TFLOP/s", f"mlpk::k_large_train<{pi}>", "large"
+        bound, peak, unit, kname, kind = "mfma", PEAK[prec], "TFLOP/s", f"mlpk::k_large_train<{pi}, {3 if K <= 3 else 4}>", "large"
     else:
         flops = flops_per_sample_epoch(D, H, K) * N * steps + 2 * P * n_updates
         bound, peak, unit, kname, kind = "alu", PEAK["fp32"], "TFLOP/s", "mlpk::k_small_train", "small"
@@ -279,7 +281,7 @@ def bench_shared(args):
                 "compensated_update": True, "operand_precision": prec, "step": "one epoch of every net"},
         roofline={"bound": "mfma", "achieved": achieved, "peak": PEAK[prec], "unit": "TFLOP/s",
                   "frac": achieved / PEAK[prec], "traffic": measured_traffic(f"w6-{prec}-steps{steps}", "large"),
-                  "traffic_unit": "bytes per launch", "kernel": f"mlpk::k_large_train<{pi}>",
+                  "traffic_unit": "bytes per launch", "kernel": f"mlpk::k_large_train<{pi}, 3>",
                   "kernel_ms": kern * 1e3, "flops_per_launch": flops},
         final_loss_mean=float(hist[:, steps - 1].mean().item()) if steps else None, steps=steps, warmup=warmup)
     return res, dict(w=w, batch=batch)
@@ -305,6 +307,57 @@ def cpu_shared(ctx, budget_s: float):
                       f"float64, single thread, {cpu_info()}", "seconds": t_total}
 
 
+# ---------------------------------------------------------------- predictions (p4)
+def bench_predict(args):
+    import torch
+    from paper_1908_07847_amd import mlp, synth
+
+    w = synth.single(4)
+    D, H, K, N = w["D"], w["H"], w["K"], w["X"].shape[0]
+    net = mlp.Net(D, H, K, N, batch=w["batch"], theta=w["theta"])
+    X = torch.from_numpy(w["X"]).cuda()
+    T = torch.from_numpy(w["T"]).cuda()
+    steps = args.steps if args.steps is not None else 10
+    warmup = args.warmup if args.warmup is not None else 2
+    for _ in range(warmup):
+        net.predict(X, T)
+    stream = torch.cuda.current_stream()
+
+    def run():
+        for _ in range(steps):
+            net.predict(X, T)
+    wall, kern = timed(run, stream)
+    flops = (2 * D * H + 4 * H + 2 * H * K + 4 * K) * N * steps    # z1, sigma, z2, sigma per row
+    achieved = flops / kern / 1e12
+    res = dict(
+        metric="predicted rows/s", value=N * steps / wall, unit="rows/s", ms_per_step=wall * 1e3 / steps,
+        dtype="f32",
+        config={"workload": "class predictions of the 33-256-3 net on N=1,048,576 x 33 (forward, argmax, "
+                            "correct count)", "n_rows": N, "n_in": D, "n_hidden": H, "n_out": K,
+                "step": "one mlp_predict call over all rows"},
+        roofline={"bound": "alu", "achieved": achieved, "peak": PEAK["fp32"], "unit": "TFLOP/s",
+                  "frac": achieved / PEAK["fp32"], "traffic": None, "traffic_unit": "bytes per launch",
+                  "kernel": "mlpk::k_forward", "kernel_ms": kern * 1e3 / steps, "flops_per_launch": flops // steps},
+        steps=steps, warmup=warmup)
+    return res, dict(w=w)
+
+
+def cpu_predict(ctx, budget_s: float):
+    import oracle
+    w = ctx["w"]
+    p = oracle.Params.of(w["theta"])
+    rows = 65536
+    reps, t_total = 0, 0.0
+    while (t_total < budget_s or reps == 0) and reps < 100000:
+        t0 = time.perf_counter()
+        oracle.predict(w["X"][:rows], p)
+        t_total += time.perf_counter() - t0
+        reps += 1
+    return {"value": rows * reps / t_total, "unit": "rows/s", "cores": 1, "kind": "oracle",
+            "sample": f"the first {rows} rows, run {reps} time(s), float64, single thread, {cpu_info()}",
+            "seconds": t_total}
+
+
 def copy_probe(n_bytes: int = 1 << 30):
     """A plain device-to-device copy of known size, used to scale the HBM
     byte counters (FETCH_SIZE / WRITE_SIZE) of the profiler."""
@@ -321,7 +374,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the workload's epochs)")
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="w2", choices=["w1", "w2", "w3", "w4", "w5", "w6"])
+    ap.add_argument("--workload", default="w2", choices=["w1", "w2", "w3", "w4", "w5", "w6", "p4"])
     ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16", "e4m3"])
     ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true")
@@ -337,6 +390,9 @@ def main():
     if args.workload == "w3":
         res, ctx = bench_batched(args)
         cpu = None if args.no_cpu else cpu_batched(ctx, args.cpu_budget)
+    elif args.workload == "p4":
+        res, ctx = bench_predict(args)
+        cpu = None if args.no_cpu else cpu_predict(ctx, args.cpu_budget)
     elif args.workload == "w6":
         res, ctx = bench_shared(args)
         cpu = None if args.no_cpu else cpu_shared(ctx, args.cpu_budget)

@@ -247,7 +247,8 @@ struct LLayout {
   __host__ __device__ int total() const { return red() + 64 * 4; }
 };
 
-template <int PREC>
+// KO: outputs the loops run over (K <= KO <= kMaxK; 3 for the usual K = 3).
+template <int PREC, int KO>
 __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
   using O = Ops<PREC>;
   using E = typename O::elem;
@@ -628,13 +629,13 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
     // z2 partial over this workgroup's hidden block for the 32 rows of chunk
     // c0 of the piece in LDS; out(rr, k, v) receives row rr's sum for output k
     auto z2_chunk = [&](int c0, auto &&out) {
-      float zp[2][4][kMaxK];
+      float zp[2][4][KO];
 #pragma unroll
       for (int rs = 0; rs < 2; ++rs)
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-          for (int k = 0; k < kMaxK; ++k) zp[rs][i][k] = 0.0f;
+          for (int k = 0; k < KO; ++k) zp[rs][i][k] = 0.0f;
       f32x4 zt[4][2];
       z1_tiles(c0, zt);
 #pragma unroll
@@ -642,9 +643,9 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
         if (hb >= NHB) continue;
         const int hl = wave * HW + hb * 16 + l16;
         const float bias = b1s[hl];
-        float w2v[kMaxK];
+        float w2v[KO];
 #pragma unroll
-        for (int k = 0; k < kMaxK; ++k) w2v[k] = w2s[k * HB + hl];
+        for (int k = 0; k < KO; ++k) w2v[k] = w2s[k * HB + hl];
 #pragma unroll
         for (int rs = 0; rs < 2; ++rs) {
           const f32x4 z = zt[hb][rs];
@@ -652,7 +653,7 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
           for (int i = 0; i < 4; ++i) {
             const float av = sigmoid(z[i] + bias);
 #pragma unroll
-            for (int k = 0; k < kMaxK; ++k) zp[rs][i][k] = fmaf(av, w2v[k], zp[rs][i][k]);
+            for (int k = 0; k < KO; ++k) zp[rs][i][k] = fmaf(av, w2v[k], zp[rs][i][k]);
           }
         }
       }
@@ -662,7 +663,7 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-          for (int k = 0; k < kMaxK; ++k) zp[rs][i][k] = sum16(zp[rs][i][k]);
+          for (int k = 0; k < KO; ++k) zp[rs][i][k] = sum16(zp[rs][i][k]);
       // consecutive chunks alternate between two buffers, so one barrier per
       // chunk separates the writes of a buffer from the reads of its
       // previous contents (two chunks back)
@@ -673,7 +674,7 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
 #pragma unroll
           for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int k = 0; k < kMaxK; ++k) zw[(wave * kRC + rs * 16 + 4 * lg + i) * 4 + k] = zp[rs][i][k];
+            for (int k = 0; k < 4; ++k) zw[(wave * kRC + rs * 16 + 4 * lg + i) * 4 + k] = k < KO ? zp[rs][i][k] : 0.0f;
       }
       __syncthreads();
       for (int q = tid; q < kRC * 4; q += kLT) {
@@ -706,11 +707,11 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
 #pragma unroll
       for (int fb = 0; fb < 4; ++fb) gacc[hb][fb] = f32x4{0.f, 0.f, 0.f, 0.f};
     float gb1[4] = {0.f, 0.f, 0.f, 0.f};
-    float gw2[4][kMaxK];
+    float gw2[4][KO];
 #pragma unroll
     for (int hb = 0; hb < 4; ++hb)
 #pragma unroll
-      for (int k = 0; k < kMaxK; ++k) gw2[hb][k] = 0.0f;
+      for (int k = 0; k < KO; ++k) gw2[hb][k] = 0.0f;
     float d1max = 0.0f;
 
     for (int t = 0; t < NPc; ++t) {
@@ -784,9 +785,9 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
         if (hb < NHB) {
           const int hl = wave * HW + hb * 16 + l16;
           const float bias = b1s[hl];
-          float w2v[kMaxK];
+          float w2v[KO];
 #pragma unroll
-          for (int k = 0; k < kMaxK; ++k) w2v[k] = w2s[k * HB + hl];
+          for (int k = 0; k < KO; ++k) w2v[k] = w2s[k * HB + hl];
 #pragma unroll
           for (int rs = 0; rs < 2; ++rs) {
             const f32x4 z = zt[hb][rs];
@@ -799,7 +800,7 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
               const float dd[4] = {dv.x, dv.y, dv.z, dv.w};
               float bp = 0.0f;
 #pragma unroll
-              for (int k = 0; k < kMaxK; ++k) {
+              for (int k = 0; k < KO; ++k) {
                 bp = fmaf(dd[k], w2v[k], bp);
                 gw2[hb][k] = fmaf(dd[k], av, gw2[hb][k]);
               }
@@ -889,9 +890,9 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
           float v = gb1[hb];
           v += __shfl_xor(v, 16, kWave);
           v += __shfl_xor(v, 32, kWave);
-          float w[kMaxK];
+          float w[KO];
 #pragma unroll
-          for (int k = 0; k < kMaxK; ++k) {
+          for (int k = 0; k < KO; ++k) {
             float t = gw2[hb][k];
             t += __shfl_xor(t, 16, kWave);
             t += __shfl_xor(t, 32, kWave);
@@ -901,7 +902,7 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
           if (lg == 0 && h < H) {
             gpi[oB1 + h] = v;
 #pragma unroll
-            for (int k = 0; k < kMaxK; ++k)
+            for (int k = 0; k < KO; ++k)
               if (k < K) gpi[oW2 + (int64_t)k * H + h] = w[k];
           }
         }
@@ -1198,9 +1199,10 @@ mlp_status large_train(const mlp_config &c, int n_nets, const float *lrs, const 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) { *err = hipGetErrorString(e); return MLP_ERR_HIP; }
 
-  const void *kern = c.prec == MLP_FP32 ? (const void *)mlpk::k_large_train<0>
-                   : c.prec == MLP_BF16 ? (const void *)mlpk::k_large_train<1>
-                                        : (const void *)mlpk::k_large_train<2>;
+  const bool k3 = c.n_out <= 3;
+  const void *kern = c.prec == MLP_FP32 ? (k3 ? (const void *)mlpk::k_large_train<0, 3> : (const void *)mlpk::k_large_train<0, 4>)
+                   : c.prec == MLP_BF16 ? (k3 ? (const void *)mlpk::k_large_train<1, 3> : (const void *)mlpk::k_large_train<1, 4>)
+                                        : (k3 ? (const void *)mlpk::k_large_train<2, 3> : (const void *)mlpk::k_large_train<2, 4>);
   e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.lds);
   if (e != hipSuccess) { *err = std::string("hipFuncSetAttribute: ") + hipGetErrorString(e); return MLP_ERR_HIP; }
   int per_cu = 0;
