@@ -2,9 +2,13 @@
 // section 2.2), for callers that drive the steps themselves -- e.g. a
 // torch.autograd.Function whose backward is this hand-written adjoint.
 //
-//  k_forward       one thread per row: z1 = X W1^T + b1, A = sigma(z1),
-//                  Y = sigma(A W2^T + b2).  W1/W2 reads are uniform across
-//                  the wave (broadcast); each thread streams its own row.
+//  k_forward_tiled 64 rows per workgroup, 16 per wave: the row tile of X and
+//                  a 64-unit block of W1 at a time in LDS, z1 on
+//                  v_mfma_f32_16x16x4_f32, sigma in the accumulator layout,
+//                  the output layer as lane partials summed across the 16
+//                  lanes of a row (n_in <= 256, n_out <= 16)
+//  k_forward       one thread per row (any n_in): z1 = X W1^T + b1,
+//                  A = sigma(z1), Y = sigma(A W2^T + b2).
 //  k_backward_rows one thread per row: delta2 = dY . Y (1 - Y) (dY from the
 //                  caller, or the MSE reading 2 (Y - T) / (n K)),
 //                  delta1 = (delta2 W2) . A (1 - A); optional dX = delta1 W1;
@@ -41,6 +45,76 @@ __global__ __launch_bounds__(256) void k_forward(int64_t n, int D, int H, int K,
     for (int k = 0; k < K && k < kLayerMaxOut; ++k) z2[k] += a * p.W2[(int64_t)k * H + h];
   }
   for (int k = 0; k < K && k < kLayerMaxOut; ++k) Y[r * K + k] = sigmoid(z2[k]);
+}
+
+constexpr int kFwdRows = 64, kFwdHB = 64, kFwdMaxD = 256;
+
+typedef float f32x4_l __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_forward_tiled(int64_t n, int D, int H, int K,
+                                                       const float *__restrict__ X, mlp_params p,
+                                                       float *__restrict__ A, float *__restrict__ Y) {
+  extern __shared__ float4 fsm4[];
+  float *sm = reinterpret_cast<float *>(fsm4);
+  const int DK = (D + 3) / 4 * 4, XS = DK + 1;     // contraction length; odd row stride
+  float *xs = sm;                                   // [64][XS]
+  float *ws = xs + kFwdRows * XS;                   // [64][XS] W1 block
+  float *w2 = ws + kFwdHB * XS;                     // [16][64] W2 block
+  float *b1 = w2 + kLayerMaxOut * kFwdHB;           // [64]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, lg = lane >> 4;
+  const int64_t r0 = (int64_t)blockIdx.x * kFwdRows;
+  const int rows = (int)min((int64_t)kFwdRows, n - r0);
+  for (int q = tid; q < kFwdRows * XS; q += 256) {
+    const int r = q / XS, c = q - r * XS;
+    xs[q] = (r < rows && c < D) ? X[(r0 + r) * D + c] : 0.0f;
+  }
+  float zp[4][kLayerMaxOut];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int k = 0; k < kLayerMaxOut; ++k) zp[i][k] = 0.0f;
+  for (int h0 = 0; h0 < H; h0 += kFwdHB) {
+    __syncthreads();   // the previous block's W1 / W2 are no longer read
+    for (int q = tid; q < kFwdHB * XS; q += 256) {
+      const int h = q / XS, c = q - h * XS;
+      ws[q] = (h0 + h < H && c < D) ? p.W1[(int64_t)(h0 + h) * D + c] : 0.0f;
+    }
+    for (int q = tid; q < kLayerMaxOut * kFwdHB; q += 256) {
+      const int k = q / kFwdHB, h = q - k * kFwdHB;
+      w2[q] = (k < K && h0 + h < H) ? p.W2[(int64_t)k * H + h0 + h] : 0.0f;
+    }
+    if (tid < kFwdHB) b1[tid] = h0 + tid < H ? p.b1[h0 + tid] : 0.0f;
+    __syncthreads();
+    for (int ht = 0; ht < kFwdHB / 16; ++ht) {
+      if (h0 + ht * 16 >= H) break;
+      f32x4_l z = {0.f, 0.f, 0.f, 0.f};
+      const float *xa = xs + (wave * 16 + l16) * XS + lg;
+      const float *wb = ws + (ht * 16 + l16) * XS + lg;
+      for (int k0 = 0; k0 < DK; k0 += 4) z = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[k0], wb[k0], z, 0, 0, 0);
+      const int hl = ht * 16 + l16, h = h0 + hl;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = wave * 16 + 4 * lg + i;
+        const float a = h < H ? sigmoid(z[i] + b1[hl]) : 0.0f;
+        if (A && r < rows && h < H) A[(r0 + r) * H + h] = a;
+#pragma unroll
+        for (int k = 0; k < kLayerMaxOut; ++k)
+          if (k < K) zp[i][k] = fmaf(a, w2[k * kFwdHB + hl], zp[i][k]);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = wave * 16 + 4 * lg + i;
+#pragma unroll
+    for (int k = 0; k < kLayerMaxOut; ++k) {
+      if (k < K) {
+        const float z2 = sum16(zp[i][k]);
+        if (l16 == 0 && r < rows) Y[(r0 + r) * K + k] = sigmoid(z2 + p.b2[k]);
+      }
+    }
+  }
 }
 
 __global__ __launch_bounds__(256) void k_backward_rows(
@@ -172,6 +246,17 @@ static dim3 grid_for(int64_t n, int b) { return dim3((unsigned)((n + b - 1) / b)
 
 hipError_t launch_forward(int64_t n, int D, int H, int K, const float *X, mlp_params p, float *A,
                           float *Y, hipStream_t s) {
+  if (D <= mlpk::kFwdMaxD && K <= mlpk::kLayerMaxOut) {
+    const int XS = (D + 3) / 4 * 4 + 1;
+    const size_t lds = sizeof(float) * ((size_t)(mlpk::kFwdRows + mlpk::kFwdHB) * XS +
+                                        mlpk::kLayerMaxOut * mlpk::kFwdHB + mlpk::kFwdHB);
+    hipError_t e = hipFuncSetAttribute((const void *)mlpk::k_forward_tiled,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    const int64_t blocks = (n + mlpk::kFwdRows - 1) / mlpk::kFwdRows;
+    hipLaunchKernelGGL(mlpk::k_forward_tiled, dim3((unsigned)blocks), dim3(256), lds, s, n, D, H, K, X, p, A, Y);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(mlpk::k_forward, grid_for(n, 256), dim3(256), 0, s, n, D, H, K, X, p, A, Y);
   return hipGetLastError();
 }
