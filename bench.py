@@ -14,6 +14,9 @@ Workloads (all synthetic, from the seeded generator):
   w5   4,194,304 x 64, 64-1024-3, minibatch 16384             step = 1 epoch (256 minibatches)
   w6   64 nets of w5's shape sharing its X (grid of 8 learning rates x 8 initialisations)
                                                                step = 1 epoch of every net
+  w2a  w2 through the differentiation path: per epoch MLPFunction (forward
+       kernel), torch's MSE, the hand-written adjoint (backward kernels) and
+       mlp_step, launched from Python                 step = 1 epoch
   p4   class predictions (mlp_predict: forward pass + argmax + correct count) on
        w4's 1,048,576 rows with its 33-256-3 net     metric: predicted rows/s
 w4/w5 take --prec fp32|bf16|e4m3, w6 fp32|bf16 (operand precision of the two contractions).
@@ -307,6 +310,54 @@ def cpu_shared(ctx, budget_s: float):
                       f"float64, single thread, {cpu_info()}", "seconds": t_total}
 
 
+# ---------------------------------------------------------------- differentiation path (w2a)
+def bench_autograd(args):
+    import torch
+    from paper_1908_07847_amd import mlp, synth
+
+    w = synth.single(2)
+    D, H, K, N = w["D"], w["H"], w["K"], w["X"].shape[0]
+    net = mlp.Net(D, H, K, N, lr=w["lr"], theta=w["theta"])
+    X = torch.from_numpy(w["X"]).cuda()
+    T = torch.from_numpy(w["T"]).cuda()
+    net.flat.requires_grad_(True)
+    params = list(mlp.split_packed(net.flat, D, H, K))
+    grads = net.new_grads()
+    steps = args.steps if args.steps is not None else w["epochs"]
+    warmup = args.warmup if args.warmup is not None else 20
+    hist = torch.empty(max(steps, warmup, 1), device="cuda")
+
+    def epochs(count):
+        for e in range(count):
+            Y = mlp.MLPFunction.apply(net, X, *params)
+            loss = torch.nn.functional.mse_loss(Y, T)
+            gW1, gb1, gW2, gb2 = torch.autograd.grad(loss, params)
+            grads.W1.copy_(gW1); grads.b1.copy_(gb1); grads.W2.copy_(gW2); grads.b2.copy_(gb2)
+            with torch.no_grad():
+                net.step(grads)
+            hist[e] = loss.detach()
+    epochs(warmup)
+    with torch.no_grad():
+        net.set_theta(w["theta"])
+    stream = torch.cuda.current_stream()
+    wall, kern = timed(lambda: epochs(steps), stream)
+    P = D * H + H + H * K + K
+    flops = flops_per_sample_epoch(D, H, K) * N * steps + 2 * P * steps
+    achieved = flops / kern / 1e12
+    res = dict(
+        metric="training samples*epochs/s", value=N * steps / wall, unit="samples*epochs/s",
+        ms_per_step=wall * 1e3 / steps, dtype="f32",
+        config={"workload": "differentiation: N=120 x 33, 33-16-3, full batch, MLPFunction forward + hand-written "
+                            "adjoint + mlp_step per epoch (launched from Python)", "n_rows": N, "n_in": D,
+                "n_hidden": H, "n_out": K, "lr": w["lr"], "step": "one epoch"},
+        roofline={"bound": "alu", "achieved": achieved, "peak": PEAK["fp32"], "unit": "TFLOP/s",
+                  "frac": achieved / PEAK["fp32"], "traffic": None, "traffic_unit": "bytes per launch",
+                  "kernel": "mlpk::k_forward_tiled + k_backward_rows + k_backward_sum + k_step (per epoch)",
+                  "kernel_ms": kern * 1e3, "flops_per_launch": flops},
+        final_loss=float(hist[steps - 1].item()) if steps else None, steps=steps, warmup=warmup)
+    return res, dict(w=w, wl=2, batch=N)
+
+
 # ---------------------------------------------------------------- predictions (p4)
 def bench_predict(args):
     import torch
@@ -374,7 +425,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the workload's epochs)")
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="w2", choices=["w1", "w2", "w3", "w4", "w5", "w6", "p4"])
+    ap.add_argument("--workload", default="w2", choices=["w1", "w2", "w2a", "w3", "w4", "w5", "w6", "p4"])
     ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16", "e4m3"])
     ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true")
@@ -390,6 +441,9 @@ def main():
     if args.workload == "w3":
         res, ctx = bench_batched(args)
         cpu = None if args.no_cpu else cpu_batched(ctx, args.cpu_budget)
+    elif args.workload == "w2a":
+        res, ctx = bench_autograd(args)
+        cpu = None if args.no_cpu else cpu_single(ctx, args.cpu_budget)
     elif args.workload == "p4":
         res, ctx = bench_predict(args)
         cpu = None if args.no_cpu else cpu_predict(ctx, args.cpu_budget)
