@@ -322,7 +322,6 @@ def bench_autograd(args):
     T = torch.from_numpy(w["T"]).cuda()
     net.flat.requires_grad_(True)
     params = list(mlp.split_packed(net.flat, D, H, K))
-    grads = net.new_grads()
     steps = args.steps if args.steps is not None else w["epochs"]
     warmup = args.warmup if args.warmup is not None else 20
     hist = torch.empty(max(steps, warmup, 1), device="cuda")
@@ -332,9 +331,8 @@ def bench_autograd(args):
             Y = mlp.MLPFunction.apply(net, X, *params)
             loss = torch.nn.functional.mse_loss(Y, T)
             gW1, gb1, gW2, gb2 = torch.autograd.grad(loss, params)
-            grads.W1.copy_(gW1); grads.b1.copy_(gb1); grads.W2.copy_(gW2); grads.b2.copy_(gb2)
-            with torch.no_grad():
-                net.step(grads)
+            with torch.no_grad():   # the adjoint's own gradient buffers feed the update directly
+                net.step(mlp.Grads(gW1, gb1, gW2, gb2, None))
             hist[e] = loss.detach()
     epochs(warmup)
     with torch.no_grad():

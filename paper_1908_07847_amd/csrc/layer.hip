@@ -13,9 +13,9 @@
 //                  caller, or the MSE reading 2 (Y - T) / (n K)),
 //                  delta1 = (delta2 W2) . A (1 - A); optional dX = delta1 W1;
 //                  writes delta1, delta2 and the row's squared error.
-//  k_backward_sum  one thread per parameter (plus one for the loss): sums
-//                  its gradient over all rows in row order, so the result
-//                  is bitwise repeatable.
+//  k_backward_sum  one wave per parameter (plus one for the loss): lane
+//                  partial sums over the rows, then a fixed butterfly, so
+//                  the result is bitwise repeatable.
 //  k_step          theta <- theta - lr g, optionally Kahan-compensated.
 //  k_argmax        one thread per row: the class is the index of the largest
 //                  output (lowest index on ties); with one-hot targets, the
@@ -154,36 +154,43 @@ __global__ __launch_bounds__(256) void k_backward_rows(
   }
 }
 
-// Parameter index q in packed order [W1 | b1 | W2 | b2], plus q == P for the loss.
+// One wave per parameter q in packed order [W1 | b1 | W2 | b2], plus q == P
+// for the loss: lane l sums rows l, l + 64, ... in order, then a fixed
+// butterfly adds the 64 lane sums, so the result is bitwise repeatable.
 __global__ __launch_bounds__(256) void k_backward_sum(
     int64_t n, int64_t n_total, int accumulate, int D, int H, int K, const float *__restrict__ X,
     const float *__restrict__ A, const float *__restrict__ d1, const float *__restrict__ d2,
     const float *__restrict__ sq, mlp_params g, float *__restrict__ loss) {
   const int64_t P = (int64_t)D * H + H + (int64_t)H * K + K;
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q > P) return;
+  const int64_t q = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+  const int lane = threadIdx.x & (kWave - 1);
+  if (q > P) return;   // whole waves leave together
   float s = 0.0f;
   if (q < (int64_t)D * H) {
     const int h = (int)(q / D), d = (int)(q - (int64_t)h * D);
-    for (int64_t r = 0; r < n; ++r) s += d1[r * H + h] * X[r * D + d];
-    g.W1[q] = accumulate ? g.W1[q] + s : s;
+    for (int64_t r = lane; r < n; r += kWave) s += d1[r * H + h] * X[r * D + d];
+    s = wave_sum(s);
+    if (lane == 0) g.W1[q] = accumulate ? g.W1[q] + s : s;
   } else if (q < (int64_t)D * H + H) {
     const int h = (int)(q - (int64_t)D * H);
-    for (int64_t r = 0; r < n; ++r) s += d1[r * H + h];
-    g.b1[h] = accumulate ? g.b1[h] + s : s;
+    for (int64_t r = lane; r < n; r += kWave) s += d1[r * H + h];
+    s = wave_sum(s);
+    if (lane == 0) g.b1[h] = accumulate ? g.b1[h] + s : s;
   } else if (q < (int64_t)D * H + H + (int64_t)H * K) {
     const int64_t o = q - ((int64_t)D * H + H);
     const int k = (int)(o / H), h = (int)(o - (int64_t)k * H);
-    for (int64_t r = 0; r < n; ++r) s += d2[r * K + k] * A[r * H + h];
-    g.W2[o] = accumulate ? g.W2[o] + s : s;
+    for (int64_t r = lane; r < n; r += kWave) s += d2[r * K + k] * A[r * H + h];
+    s = wave_sum(s);
+    if (lane == 0) g.W2[o] = accumulate ? g.W2[o] + s : s;
   } else if (q < P) {
     const int k = (int)(q - ((int64_t)D * H + H + (int64_t)H * K));
-    for (int64_t r = 0; r < n; ++r) s += d2[r * K + k];
-    g.b2[k] = accumulate ? g.b2[k] + s : s;
+    for (int64_t r = lane; r < n; r += kWave) s += d2[r * K + k];
+    s = wave_sum(s);
+    if (lane == 0) g.b2[k] = accumulate ? g.b2[k] + s : s;
   } else if (loss) {
-    for (int64_t r = 0; r < n; ++r) s += sq[r];
-    s = s / ((float)n_total * (float)K);
-    loss[0] = accumulate ? loss[0] + s : s;
+    for (int64_t r = lane; r < n; r += kWave) s += sq[r];
+    s = wave_sum(s) / ((float)n_total * (float)K);
+    if (lane == 0) loss[0] = accumulate ? loss[0] + s : s;
   }
 }
 
@@ -290,7 +297,7 @@ hipError_t launch_backward(int64_t n, int64_t ws_rows, int D, int H, int K, cons
                        p, dX ? dX + r0 * D : nullptr, d1, d2, sq);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(mlpk::k_backward_sum, grid_for(P + 1, 256), dim3(256), 0, s, m, n,
+    hipLaunchKernelGGL(mlpk::k_backward_sum, grid_for(P + 1, 256 / mlpk::kWave), dim3(256), 0, s, m, n,
                        r0 > 0 ? 1 : 0, D, H, K, X + r0 * D, A + r0 * H, d1, d2, sq, g,
                        dY ? nullptr : loss);
     e = hipGetLastError();
