@@ -190,7 +190,7 @@ def bench_batched(args):
     import torch
     from paper_1908_07847_amd import mlp, synth, tune
 
-    w = synth.batched()
+    w = synth.batched(heldout=True)
     items = w["items"]
     plan = mlp.BatchPlan(items)
     X = torch.from_numpy(w["X"]).cuda()
@@ -210,6 +210,19 @@ def bench_batched(args):
     stream = torch.cuda.current_stream()
     wall, kern = timed(graph.replay, stream)
     mlp.reset_launch_hint()
+    # cross-validation read-out: every net on its held-out fold (mlp_eval_batched),
+    # then the hyperparameter group with the lowest mean held-out loss
+    vplan = mlp.BatchPlan(w["items_val"])
+    Xv, Tv = torch.from_numpy(w["X_val"]).cuda(), torch.from_numpy(w["T_val"]).cuda()
+    mlp.eval_batched(vplan, Xv, Tv, th, 33, 3)
+    _, eval_s = timed(lambda: mlp.eval_batched(vplan, Xv, Tv, th, 33, 3), stream)
+    vloss, vcor = mlp.eval_batched(vplan, Xv, Tv, th, 33, 3)
+    vloss, vcor = vloss.cpu().numpy(), vcor.cpu().numpy()
+    groups = np.array([it["group"] for it in w["items_val"]])
+    ng = int(groups.max()) + 1
+    gmean = np.bincount(groups, weights=vloss, minlength=ng) / np.bincount(groups, minlength=ng)
+    best = int(np.argmin(gmean))
+    vrows = int(sum(it["n_rows"] for it in w["items_val"]))
     rows = sum(it["n_rows"] for it in items)
     flops = 0
     for it in items:
@@ -224,6 +237,11 @@ def bench_batched(args):
                             "(5-fold CV splits), lr~logU(0.01,1), full batch, one launch",
                 "nets": len(items), "total_rows": rows, "step": "one epoch of every net",
                 "threads_per_net": threads, "launch": "hipGraph replay of one persistent kernel"},
+        cv_eval={"kernel": "mlpk::k_eval_batched", "ms": eval_s * 1e3, "heldout_rows": vrows,
+                 "rows_per_s": vrows / eval_s, "best_group": best, "best_group_hidden": int(
+                     w["items_val"][int(np.nonzero(groups == best)[0][0])]["n_hidden"]),
+                 "best_mean_heldout_loss": float(gmean[best]),
+                 "heldout_accuracy": float(vcor.sum() / vrows)},
         roofline={"bound": "alu", "achieved": achieved, "peak": PEAK["fp32"], "unit": "TFLOP/s",
                   "frac": achieved / PEAK["fp32"], "traffic": measured_traffic(f"w3-fp32-steps{steps}", "small"),
                   "traffic_unit": "bytes per launch", "kernel": "mlpk::k_small_train",

@@ -170,6 +170,20 @@ mlp_status mlp_train_batched(const mlp_batch_item *items_host, const mlp_batch_i
                              float *comp_packed, int64_t total_params, int32_t epochs,
                              float *loss_hist, void *stream);
 
+/* Evaluate n_nets networks, each on its own rows of X_packed / T_packed (for
+ * instance the held-out fold of a cross-validation split), in one launch:
+ * loss[i] = sum (Y - T)^2 / (N_i K) of net i's forward pass (section 2.2)
+ * and, if correct is not NULL, correct[i] (int32) = rows whose class (index
+ * of the largest output, lowest on ties) equals the target's.  The item
+ * table is the batched trainer's (n_rows, n_hidden, x_off, p_off of each
+ * net; lr is ignored), given on the host (validated) and on the device
+ * (read by the kernel); n_hidden and n_rows may exceed the trainer's
+ * limits, n_out <= MLP_SMALL_MAX_OUT.  Sums over rows use a fixed order. */
+mlp_status mlp_eval_batched(const mlp_batch_item *items_host, const mlp_batch_item *items_dev, int32_t n_nets,
+                            int32_t n_in, int32_t n_out, const float *X_packed, const float *T_packed,
+                            int64_t total_rows, const float *theta_packed, int64_t total_params, float *loss,
+                            int32_t *correct, void *stream);
+
 /* ---- networks sharing one dataset --------------------------------------- */
 
 #define MLP_MAX_SHARED_NETS 64

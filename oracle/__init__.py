@@ -148,6 +148,14 @@ def predict(X, p: Params):
     return Y, np.argmax(Y, axis=1).astype(np.int32)
 
 
+def evaluate(X, T, p: Params):
+    """(loss, correct) of a net on rows X, T: the error of section 2.2 (mean
+    squared error over rows and outputs) and the number of rows whose class
+    (first maximum of the outputs) equals the target's."""
+    Y, lab = predict(X, p)
+    return mse(Y, T), int(np.sum(lab == np.argmax(_d(T), axis=1)))
+
+
 def mse(Y, T) -> float:
     Y, T = _d(Y), _d(T)
     return float(_load().ora_mse(Y.shape[0], Y.shape[1], _p(Y), _p(T)))

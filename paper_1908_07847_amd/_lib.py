@@ -50,7 +50,8 @@ assert ctypes.sizeof(BatchItem) == 32 and ctypes.sizeof(Config) == 40 and ctypes
 
 # Every symbol include/mlp.h declares.
 SYMBOLS = ["mlp_workspace_size", "mlp_init", "mlp_destroy", "mlp_forward", "mlp_backward", "mlp_step",
-           "mlp_train", "mlp_predict", "mlp_train_batched", "mlp_shared_workspace_size", "mlp_train_shared",
+           "mlp_train", "mlp_predict", "mlp_train_batched", "mlp_eval_batched", "mlp_shared_workspace_size",
+           "mlp_train_shared",
            "mlp_set_launch_hint", "mlp_status_string", "mlp_last_error"]
 
 
@@ -70,11 +71,13 @@ def _load():
     lib.mlp_predict.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp]
     lib.mlp_train_batched.argtypes = [ctypes.POINTER(BatchItem), vp, i32, i32, i32, vp, vp, i64, vp, vp,
                                       i64, i32, vp, vp]
+    lib.mlp_eval_batched.argtypes = [ctypes.POINTER(BatchItem), vp, i32, i32, i32, vp, vp, i64, vp, i64, vp, vp,
+                                     vp]
     lib.mlp_shared_workspace_size.argtypes = [ctypes.POINTER(Config), i32, ctypes.POINTER(ctypes.c_size_t)]
     lib.mlp_train_shared.argtypes = [ctypes.POINTER(Config), i32, ctypes.POINTER(f32), vp, vp, vp, vp, i32, vp,
                                      vp, ctypes.c_size_t, vp]
     lib.mlp_set_launch_hint.argtypes = [ctypes.POINTER(LaunchHint)]
-    for name in SYMBOLS[:12]:
+    for name in SYMBOLS[:13]:
         getattr(lib, name).restype = ctypes.c_int
     lib.mlp_status_string.argtypes = [ctypes.c_int]
     lib.mlp_status_string.restype = ctypes.c_char_p

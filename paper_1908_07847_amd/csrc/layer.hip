@@ -17,6 +17,9 @@
 //                  partial sums over the rows, then a fixed butterfly, so
 //                  the result is bitwise repeatable.
 //  k_step          theta <- theta - lr g, optionally Kahan-compensated.
+//  k_eval_batched  one workgroup per net of a batched item table: loss and
+//                  correct count of the net on its own rows (e.g. a held-out
+//                  fold), threads over rows, fixed-order block sums
 //  k_argmax        one thread per row: the class is the index of the largest
 //                  output (lowest index on ties); with one-hot targets, the
 //                  count of rows whose class matches the target's, summed
@@ -225,6 +228,57 @@ __device__ __forceinline__ int argmax_row(const float *v, int K) {
   return best;
 }
 
+__global__ __launch_bounds__(256) void k_eval_batched(const mlp_batch_item *__restrict__ items, int D, int K,
+                                                      const float *__restrict__ X, const float *__restrict__ T,
+                                                      const float *__restrict__ theta, float *__restrict__ loss,
+                                                      int32_t *__restrict__ correct) {
+  const mlp_batch_item it = items[blockIdx.x];
+  const int N = it.n_rows, H = it.n_hidden;
+  const float *W1 = theta + it.p_off, *b1 = W1 + (int64_t)H * D, *W2 = b1 + H, *b2 = W2 + (int64_t)K * H;
+  float sq = 0.0f;
+  int hit = 0;
+  for (int r = threadIdx.x; r < N; r += blockDim.x) {
+    const float *x = X + (it.x_off + r) * D;
+    const float *t = T + (it.x_off + r) * K;
+    float z2[MLP_SMALL_MAX_OUT];
+#pragma unroll
+    for (int k = 0; k < MLP_SMALL_MAX_OUT; ++k) z2[k] = k < K ? b2[k] : 0.0f;
+    for (int h = 0; h < H; ++h) {
+      const float *w = W1 + (int64_t)h * D;
+      float z = b1[h];
+      for (int d = 0; d < D; ++d) z = fmaf(x[d], w[d], z);
+      const float a = sigmoid(z);
+#pragma unroll
+      for (int k = 0; k < MLP_SMALL_MAX_OUT; ++k)
+        if (k < K) z2[k] = fmaf(a, W2[(int64_t)k * H + h], z2[k]);
+    }
+    float y[MLP_SMALL_MAX_OUT];
+#pragma unroll
+    for (int k = 0; k < MLP_SMALL_MAX_OUT; ++k) {
+      y[k] = sigmoid(z2[k]);
+      if (k < K) {
+        const float e = y[k] - t[k];
+        sq = fmaf(e, e, sq);
+      }
+    }
+    hit += argmax_row(y, K) == argmax_row(t, K);
+  }
+  __shared__ float ps[4];
+  __shared__ int ph[4];
+  float v = wave_sum(sq);
+  int c = hit;
+  for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off, kWave);
+  if ((threadIdx.x & 63) == 0) {
+    ps[threadIdx.x >> 6] = v;
+    ph[threadIdx.x >> 6] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    loss[blockIdx.x] = ((ps[0] + ps[1]) + (ps[2] + ps[3])) / ((float)N * (float)K);
+    if (correct) correct[blockIdx.x] = (ph[0] + ph[1]) + (ph[2] + ph[3]);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_argmax(int64_t n, int K, const float *__restrict__ Y,
                                                 const float *__restrict__ T, int32_t *__restrict__ labels,
                                                 int32_t *__restrict__ correct) {
@@ -265,6 +319,13 @@ hipError_t launch_forward(int64_t n, int D, int H, int K, const float *X, mlp_pa
     return hipGetLastError();
   }
   hipLaunchKernelGGL(mlpk::k_forward, grid_for(n, 256), dim3(256), 0, s, n, D, H, K, X, p, A, Y);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_batched(const mlp_batch_item *items_dev, int n_nets, int D, int K, const float *X,
+                               const float *T, const float *theta, float *loss, int32_t *correct, hipStream_t s) {
+  hipLaunchKernelGGL(mlpk::k_eval_batched, dim3(n_nets), dim3(256), 0, s, items_dev, D, K, X, T, theta, loss,
+                     correct);
   return hipGetLastError();
 }
 

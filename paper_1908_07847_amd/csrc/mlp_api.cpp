@@ -319,6 +319,36 @@ mlp_status mlp_train_batched(const mlp_batch_item *items_host, const mlp_batch_i
   return e == hipSuccess ? MLP_OK : hip_fail(e, "mlp_train_batched launch");
 }
 
+mlp_status mlp_eval_batched(const mlp_batch_item *items_host, const mlp_batch_item *items_dev, int32_t n_nets,
+                            int32_t n_in, int32_t n_out, const float *X_packed, const float *T_packed,
+                            int64_t total_rows, const float *theta_packed, int64_t total_params, float *loss,
+                            int32_t *correct, void *stream) {
+  if (!items_host || !items_dev) return fail(MLP_ERR_ARG, "item tables must not be NULL");
+  if (n_nets <= 0) return fail(MLP_ERR_SHAPE, "n_nets must be positive");
+  if (n_in <= 0 || n_in > (1 << 20) || n_out <= 0 || n_out > MLP_SMALL_MAX_OUT)
+    return fail(MLP_ERR_SHAPE, "n_in must be in [1,2^20] and n_out in [1,%d]", MLP_SMALL_MAX_OUT);
+  if (!X_packed || !T_packed || !theta_packed || !loss) return fail(MLP_ERR_ARG, "X, T, theta, loss must not be NULL");
+  if (!aligned16(items_dev) || !aligned16(X_packed) || !aligned16(T_packed))
+    return fail(MLP_ERR_ALIGN, "items, X and T must be 16-byte aligned");
+  if (!aligned4(theta_packed) || !aligned4(loss) || (correct && !aligned4(correct)))
+    return fail(MLP_ERR_ALIGN, "theta, loss, correct must be 4-byte aligned");
+  for (int32_t i = 0; i < n_nets; ++i) {
+    const mlp_batch_item &it = items_host[i];
+    if (it.n_rows <= 0 || it.n_hidden <= 0 || it.n_hidden > (1 << 20))
+      return fail(MLP_ERR_SHAPE, "net %d: n_rows %d / n_hidden %d must be positive (n_hidden <= 2^20)", i,
+                  it.n_rows, it.n_hidden);
+    if (it.reserved != 0) return fail(MLP_ERR_ARG, "net %d: reserved field must be 0", i);
+    if (it.x_off < 0 || it.x_off + it.n_rows > total_rows)
+      return fail(MLP_ERR_SHAPE, "net %d: rows [%lld, %lld) outside the %lld packed rows", i,
+                  (long long)it.x_off, (long long)(it.x_off + it.n_rows), (long long)total_rows);
+    if (it.p_off < 0 || it.p_off + n_params(n_in, it.n_hidden, n_out) > total_params)
+      return fail(MLP_ERR_SHAPE, "net %d: parameters outside the %lld packed floats", i, (long long)total_params);
+  }
+  hipError_t e = mlph::launch_eval_batched(items_dev, n_nets, n_in, n_out, X_packed, T_packed, theta_packed, loss,
+                                           correct, (hipStream_t)stream);
+  return e == hipSuccess ? MLP_OK : hip_fail(e, "mlp_eval_batched launch");
+}
+
 mlp_status mlp_shared_workspace_size(const mlp_config *cfg, int32_t n_nets, size_t *bytes) {
   mlp_status s = check_config(cfg);
   if (s != MLP_OK) return s;

@@ -121,5 +121,7 @@ hipError_t launch_step(int D, int H, int K, mlp_params p, mlp_params g, float *c
                        hipStream_t s);
 hipError_t launch_predict(int64_t n, int D, int H, int K, const float *X, mlp_params p, float *Y,
                           int32_t *labels, const float *T, int32_t *correct, hipStream_t s);
+hipError_t launch_eval_batched(const mlp_batch_item *items_dev, int n_nets, int D, int K, const float *X,
+                               const float *T, const float *theta, float *loss, int32_t *correct, hipStream_t s);
 
 }  // namespace mlph

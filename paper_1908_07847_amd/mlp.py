@@ -221,6 +221,19 @@ class BatchedGraph:
         self.graph.replay()
 
 
+def eval_batched(plan: BatchPlan, X: torch.Tensor, T: torch.Tensor, theta: torch.Tensor, n_in: int, n_out: int,
+                 stream=None):
+    """mlp_eval_batched: (loss [n], correct [n] int32), indexed by the
+    caller's net index (the plan's order is undone)."""
+    n = plan.n
+    loss = torch.empty(max(n, 4), dtype=torch.float32, device=X.device)[:n]
+    correct = torch.empty(max(n, 4), dtype=torch.int32, device=X.device)[:n]
+    check(lib.mlp_eval_batched(plan.host, _ptr(plan.dev), n, int(n_in), int(n_out), _ptr(X), _ptr(T), X.shape[0],
+                               _ptr(theta), theta.numel(), _ptr(loss), _ptr(correct), _stream(stream)))
+    inv = torch.as_tensor(np.argsort(plan.order), device=X.device)
+    return loss[inv], correct[inv]
+
+
 # ---------------------------------------------------------------- nets sharing one dataset
 def shared_workspace_size(n_in: int, n_hidden: int, n_out: int, n_rows: int, batch: int, n_nets: int,
                           prec: str = "fp32") -> int:

@@ -147,7 +147,7 @@ def single(workload: int, n_rows: int | None = None, hidden: int | None = None, 
                 epochs=c["epochs"], batch=c["batch"], name=c["name"])
 
 
-def batched(n_nets: int = 4096, seed_workload: int = 3):
+def batched(n_nets: int = 4096, seed_workload: int = 3, heldout: bool = False):
     """The batched workload: net i -> group i//5, fold i%5.
 
     Each group draws its own dataset (M ~ U{50..150} rows, 22 Gaussian + 11
@@ -155,10 +155,14 @@ def batched(n_nets: int = 4096, seed_workload: int = 3):
     its rows are split into 5 folds by a seeded permutation and net i trains
     on the four folds other than fold i%5 (so N_i is in [40, 120]).
     Packed layout: X rows of net i at x_off (in rows), T at the same row
-    offset, parameters [W1|b1|W2|b2] at p_off (in floats).
+    offset, parameters [W1|b1|W2|b2] at p_off (in floats).  With heldout,
+    also X_val / T_val / items_val: net i's held-out fold (the rows it does
+    not train on), packed the same way, with the same p_off and n_hidden.
     """
     n_groups = (n_nets + 4) // 5
     xs, ts, items, thetas = [], [], [], []
+    xv, tv, items_val = [], [], []
+    vrow = 0
     row = 0
     poff = 0
     for gi in range(n_groups):
@@ -178,11 +182,21 @@ def batched(n_nets: int = 4096, seed_workload: int = 3):
             th = theta0(x.shape[1], h, N_OUT, rng(seed_workload, i, ROLE_THETA))
             items.append(dict(n_rows=len(keep), n_hidden=h, lr=np.float32(lr), x_off=row, p_off=poff))
             xs.append(xi); ts.append(ti); thetas.append(th.packed())
+            if heldout:
+                held = np.sort(folds[f])
+                items_val.append(dict(n_rows=len(held), n_hidden=h, lr=np.float32(0.0), x_off=vrow, p_off=poff,
+                                      group=gi, fold=f))
+                xv.append(x[held]); tv.append(t[held])
+                vrow += len(held)
             row += len(keep)
             poff += n_params(x.shape[1], h, N_OUT)
-    return dict(X=np.ascontiguousarray(np.concatenate(xs)), T=np.ascontiguousarray(np.concatenate(ts)),
-                theta=np.concatenate(thetas).astype(np.float32), items=items, D=33, K=N_OUT,
-                epochs=WORKLOADS[3]["epochs"], name=WORKLOADS[3]["name"])
+    out = dict(X=np.ascontiguousarray(np.concatenate(xs)), T=np.ascontiguousarray(np.concatenate(ts)),
+               theta=np.concatenate(thetas).astype(np.float32), items=items, D=33, K=N_OUT,
+               epochs=WORKLOADS[3]["epochs"], name=WORKLOADS[3]["name"])
+    if heldout:
+        out.update(X_val=np.ascontiguousarray(np.concatenate(xv)), T_val=np.ascontiguousarray(np.concatenate(tv)),
+                   items_val=items_val)
+    return out
 
 
 # learning rates of the nets-sharing-X grid: 10^(-2 + 2j/7), j = 0..7

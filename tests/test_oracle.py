@@ -347,3 +347,15 @@ def test_predict_is_the_first_maximum_of_the_outputs():
     assert np.all(lab == 1)
     one = Params(p.W1, p.b1, p.W2[:1], p.b2[:1])
     assert np.all(oracle.predict(X, one)[1] == 0)
+
+
+def test_evaluate_is_the_loss_and_a_count_of_matching_classes():
+    g = np.random.default_rng(4)
+    X = g.standard_normal((40, 5))
+    T = np.eye(3)[g.integers(0, 3, 40)]
+    p = Params(g.uniform(-1, 1, (6, 5)), g.uniform(-1, 1, 6), g.uniform(-1, 1, (3, 6)), g.uniform(-1, 1, 3))
+    loss, correct = oracle.evaluate(X, T, p)
+    sig = lambda z: 1.0 / (1.0 + np.exp(-z))
+    Y = sig(sig(X @ p.W1.T + p.b1) @ p.W2.T + p.b2)
+    assert abs(loss - np.mean((Y - T) ** 2)) <= 1e-15
+    assert correct == sum(int(np.argmax(Y[r]) == np.argmax(T[r])) for r in range(40))
