@@ -248,8 +248,11 @@ struct LLayout {
 };
 
 // KO: outputs the loops run over (K <= KO <= kMaxK; 3 for the usual K = 3).
-template <int PREC, int KO>
-__global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
+// NHM: most 16-unit hidden tiles per wave (4: hidden blocks of up to 256
+// units, one workgroup per CU; 2: blocks of up to 128 units, compiled for
+// two workgroups per CU so two waves share each SIMD).
+template <int PREC, int KO, int NHM>
+__global__ __launch_bounds__(kLT, NHM <= 2 ? 2 : 1) void k_large_train(LargeArgs a) {
   using O = Ops<PREC>;
   using E = typename O::elem;
   constexpr int XROW = O::XROW;
@@ -528,11 +531,11 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
     // bf16 / e4m3 W1 operands of this wave's hidden tiles are the same for
     // every row chunk of the step: read them from LDS once, keep them in
     // registers (float32 operands would take 64 registers and stay in LDS)
-    bf16x8 w1b[4][2];
-    long w1e[4][2];
+    bf16x8 w1b[NHM][2];
+    long w1e[NHM][2];
     if (PREC != 0) {
 #pragma unroll
-      for (int hb = 0; hb < 4; ++hb)
+      for (int hb = 0; hb < NHM; ++hb)
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
           const bool on = hb < NHB && 32 * ks < DK;
@@ -547,7 +550,7 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
           }
         }
     }
-    auto z1_tiles = [&](int c0, f32x4 (&zt)[4][2]) {
+    auto z1_tiles = [&](int c0, f32x4 (&zt)[NHM][2]) {
       if (PREC == 0) {
         float xa[2][16];
 #pragma unroll
@@ -558,7 +561,7 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
                              ? reinterpret_cast<const float *>(xr)[(c0 + rs * 16 + l16) * XROW + lg + 4 * st]
                              : 0.0f;
 #pragma unroll
-        for (int hb = 0; hb < 4; ++hb) {
+        for (int hb = 0; hb < NHM; ++hb) {
           f32x4 z0 = {0.f, 0.f, 0.f, 0.f}, z1v = {0.f, 0.f, 0.f, 0.f};
           if (hb < NHB) {
             const float *wb = reinterpret_cast<const float *>(w1s) + (wave * HW + hb * 16 + l16) * XROW + lg;
@@ -584,7 +587,7 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
               xa[rs][ks] = *reinterpret_cast<const bf16x8 *>(
                   reinterpret_cast<const __bf16 *>(xr) + (c0 + rs * 16 + l16) * XROW + 8 * lg + 32 * ks);
 #pragma unroll
-        for (int hb = 0; hb < 4; ++hb) {
+        for (int hb = 0; hb < NHM; ++hb) {
           f32x4 z0 = {0.f, 0.f, 0.f, 0.f}, z1v = {0.f, 0.f, 0.f, 0.f};
           if (hb < NHB) {
 #pragma unroll
@@ -608,7 +611,7 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
               xa[rs][ks] = *reinterpret_cast<const long *>(
                   reinterpret_cast<const uint8_t *>(xr) + (c0 + rs * 16 + l16) * XROW + 8 * lg + 32 * ks);
 #pragma unroll
-        for (int hb = 0; hb < 4; ++hb) {
+        for (int hb = 0; hb < NHM; ++hb) {
           f32x4 z0 = {0.f, 0.f, 0.f, 0.f}, z1v = {0.f, 0.f, 0.f, 0.f};
           if (hb < NHB) {
 #pragma unroll
@@ -636,10 +639,10 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
         for (int i = 0; i < 4; ++i)
 #pragma unroll
           for (int k = 0; k < KO; ++k) zp[rs][i][k] = 0.0f;
-      f32x4 zt[4][2];
+      f32x4 zt[NHM][2];
       z1_tiles(c0, zt);
 #pragma unroll
-      for (int hb = 0; hb < 4; ++hb) {
+      for (int hb = 0; hb < NHM; ++hb) {
         if (hb >= NHB) continue;
         const int hl = wave * HW + hb * 16 + l16;
         const float bias = b1s[hl];
@@ -701,15 +704,17 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
     // starting from the one phase 1 left in LDS): output layer, error and
     // delta2 of its rows, then delta1 and the gradient contributions.
     float sq = 0.0f, gb2 = 0.0f;
-    f32x4 gacc[4][4];
+    f32x4 gacc[NHM][4];
 #pragma unroll
-    for (int hb = 0; hb < 4; ++hb)
+    for (int hb = 0; hb < NHM; ++hb)
 #pragma unroll
       for (int fb = 0; fb < 4; ++fb) gacc[hb][fb] = f32x4{0.f, 0.f, 0.f, 0.f};
-    float gb1[4] = {0.f, 0.f, 0.f, 0.f};
-    float gw2[4][KO];
+    float gb1[NHM];
 #pragma unroll
-    for (int hb = 0; hb < 4; ++hb)
+    for (int hb = 0; hb < NHM; ++hb) gb1[hb] = 0.0f;
+    float gw2[NHM][KO];
+#pragma unroll
+    for (int hb = 0; hb < NHM; ++hb)
 #pragma unroll
       for (int k = 0; k < KO; ++k) gw2[hb][k] = 0.0f;
     float d1max = 0.0f;
@@ -778,10 +783,10 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
 
       // recompute a, form delta1, accumulate gW1 (MFMA), gb1, gW2
       for (int c0 = 0; c0 < RBP; c0 += kRC) {
-      f32x4 zt[4][2];
+      f32x4 zt[NHM][2];
       z1_tiles(c0, zt);
 #pragma unroll
-      for (int hb = 0; hb < 4; ++hb) {
+      for (int hb = 0; hb < NHM; ++hb) {
         if (hb < NHB) {
           const int hl = wave * HW + hb * 16 + l16;
           const float bias = b1s[hl];
@@ -875,7 +880,7 @@ __global__ __launch_bounds__(kLT) void k_large_train(LargeArgs a) {
       float *gpi = a.gp + (int64_t)gi * PT + (int64_t)net * P;
       const float gscale = PREC == 2 ? isd * isx : 1.0f;
 #pragma unroll
-      for (int hb = 0; hb < 4; ++hb) {
+      for (int hb = 0; hb < NHM; ++hb) {
         if (hb < NHB) {
 #pragma unroll
           for (int fb = 0; fb < 4; ++fb) {
@@ -1015,6 +1020,7 @@ int g_grid_rows = 0, g_grid_hidden = 0;  // launch hint (0: automatic)
 
 struct Plan {
   int Gi, Gj, Hp, RBP;
+  int per_cu;   // workgroups per CU the grid needs (1 or 2)
   size_t lds;
 };
 
@@ -1030,10 +1036,11 @@ size_t lds_for(int prec, int HB, int RB) {
 }
 
 // Rows staged in LDS at a time: the largest multiple of 32 that divides the
-// row block, is at most 512 and fits the LDS with the hidden block (0: none).
-int piece_rows(int prec, int HB, int RB) {
+// row block, is at most 512 and fits the LDS budget with the hidden block
+// (0: none).
+int piece_rows(int prec, int HB, int RB, size_t limit) {
   for (int r = std::min(RB, 512) / 32 * 32; r >= 32; r -= 32)
-    if (RB % r == 0 && lds_for(prec, HB, r) <= kLdsLimit) return r;
+    if (RB % r == 0 && lds_for(prec, HB, r) <= limit) return r;
   return 0;
 }
 
@@ -1099,10 +1106,17 @@ static bool plan_for(const mlp_config &c, int M, int n_cu, Plan *pl, std::string
   if (Hp / Gj > 256) { *why = "hidden block above 256 units"; return false; }
   if (Gi > max_row_blocks(M, Gj) || Gj > kMaxHiddenBlocks) { *why = "grid above the workspace plan"; return false; }
   if (b % Gi != 0 || (b / Gi) % 32 != 0) { *why = "rows per block must be a multiple of 32"; return false; }
+  // a grid of more workgroups than CUs runs two per CU: hidden blocks of at
+  // most 128 units (two tiles per wave) and half the LDS each
+  const int G = Gi * M * Gj;
+  const int per_cu = (G + n_cu - 1) / n_cu;
+  if (per_cu > 2) { *why = "grid above two workgroups per CU"; return false; }
+  if (per_cu == 2 && Hp / Gj > 128) { *why = "two workgroups per CU need hidden blocks of at most 128 units"; return false; }
   pl->Gi = Gi;
   pl->Gj = Gj;
   pl->Hp = Hp;
-  pl->RBP = piece_rows(c.prec, Hp / Gj, (int)(b / Gi));
+  pl->per_cu = per_cu;
+  pl->RBP = piece_rows(c.prec, Hp / Gj, (int)(b / Gi), kLdsLimit / per_cu);
   if (pl->RBP == 0) { *why = "no row piece of the block fits the LDS"; return false; }
   pl->lds = lds_for(c.prec, Hp / Gj, pl->RBP);
   return true;
@@ -1111,6 +1125,20 @@ static bool plan_for(const mlp_config &c, int M, int n_cu, Plan *pl, std::string
 void set_large_grid_hint(int row_blocks, int hidden_blocks) {
   g_grid_rows = row_blocks;
   g_grid_hidden = hidden_blocks;
+}
+
+// The kernel instance: operand type, output count (3 or 4), hidden tiles per
+// wave (2 when two workgroups share a CU, else 4).
+static const void *kernel_for(int prec, bool k3, bool two) {
+  using namespace mlpk;
+  if (prec == MLP_FP32)
+    return two ? (k3 ? (const void *)k_large_train<0, 3, 2> : (const void *)k_large_train<0, 4, 2>)
+               : (k3 ? (const void *)k_large_train<0, 3, 4> : (const void *)k_large_train<0, 4, 4>);
+  if (prec == MLP_BF16)
+    return two ? (k3 ? (const void *)k_large_train<1, 3, 2> : (const void *)k_large_train<1, 4, 2>)
+               : (k3 ? (const void *)k_large_train<1, 3, 4> : (const void *)k_large_train<1, 4, 4>);
+  return two ? (k3 ? (const void *)k_large_train<2, 3, 2> : (const void *)k_large_train<2, 4, 2>)
+             : (k3 ? (const void *)k_large_train<2, 3, 4> : (const void *)k_large_train<2, 4, 4>);
 }
 
 mlp_status large_workspace_bytes(const mlp_config &c, int n_nets, size_t *bytes) {
@@ -1199,10 +1227,7 @@ mlp_status large_train(const mlp_config &c, int n_nets, const float *lrs, const 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) { *err = hipGetErrorString(e); return MLP_ERR_HIP; }
 
-  const bool k3 = c.n_out <= 3;
-  const void *kern = c.prec == MLP_FP32 ? (k3 ? (const void *)mlpk::k_large_train<0, 3> : (const void *)mlpk::k_large_train<0, 4>)
-                   : c.prec == MLP_BF16 ? (k3 ? (const void *)mlpk::k_large_train<1, 3> : (const void *)mlpk::k_large_train<1, 4>)
-                                        : (k3 ? (const void *)mlpk::k_large_train<2, 3> : (const void *)mlpk::k_large_train<2, 4>);
+  const void *kern = kernel_for(c.prec, c.n_out <= 3, pl.per_cu == 2);
   e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.lds);
   if (e != hipSuccess) { *err = std::string("hipFuncSetAttribute: ") + hipGetErrorString(e); return MLP_ERR_HIP; }
   int per_cu = 0;

@@ -258,3 +258,24 @@ def test_wide_workload_65536_row_subset_error_vs_exact_oracle(M):
         lerr = float(abs(hist[0] - ref_hist[0]) / ref_hist[0])
         say(f"  wide net, 65,536 rows, {prec}: params {errs} loss {lerr:.2e}")
         assert lerr <= l_tol and max(errs.values()) <= w_tol, (prec, errs, lerr)
+
+
+@pytest.mark.parametrize("wl,n,batch,grid,prec,tol", [
+    (4, 8 * 4096, 4096, (128, 4), "fp32", TOL),
+    (5, 2 * 16384, 16384, (64, 8), "fp32", TOL),
+    (5, 2 * 16384, 16384, (64, 8), "bf16", 1e-3)])
+def test_two_workgroups_per_cu_grids_keep_parity(M, wl, n, batch, grid, prec, tol):
+    """Grids of more workgroups than CUs run two per CU (hidden blocks of at
+    most 128 units, half the LDS each); results still match the oracle (bf16
+    within its many-step sanity gate)."""
+    w = synth.single(wl, n_rows=n)
+    M.set_launch_hint(large_grid=grid)
+    try:
+        _, flat, hist = gpu_train(M, w["X"], w["T"], w["theta"], 2, batch, prec=prec)
+    finally:
+        M.reset_launch_hint()
+    q, ref_hist = oracle.train(w["X"], w["T"], Params.of(w["theta"]), 0.1, 2, batch=batch)
+    errs = errors(flat, q)
+    say(f"  workload {wl} {prec} grid {grid}: {errs}")
+    assert max(errs.values()) <= tol
+    assert float(np.max(np.abs(hist - ref_hist) / ref_hist)) <= tol
