@@ -61,7 +61,8 @@ struct SmallLayout {
   __host__ __device__ int total() const { return part() + NW * PW; }
 };
 
-template <int NW, int HTM>
+// KO: outputs the output-layer code runs over (K <= KO; 3 covers K <= 3).
+template <int NW, int HTM, int KO>
 __global__ __launch_bounds__(NW * 64) void k_small_train(
     const mlp_batch_item *__restrict__ items, mlp_batch_item one, int D, int K,
     const float *__restrict__ X, const float *__restrict__ T, float *__restrict__ theta,
@@ -173,7 +174,9 @@ __global__ __launch_bounds__(NW * 64) void k_small_train(
         }
       }
       // output layer for this lane's 4 rows: partial over its hidden units,
-      // then summed across the 16 lanes of the row group
+      // then summed across the 16 lanes of the row group.  Branch-free (the
+      // selects keep padding rows, outputs and hidden tiles at zero), so the
+      // 4 x KO independent chains can be interleaved.
       float d2[4][4];  // [i][k]
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -181,21 +184,22 @@ __global__ __launch_bounds__(NW * 64) void k_small_train(
         const bool valid = r < N;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
+          if (k >= KO) {
+            d2[i][k] = 0.0f;
+            continue;
+          }
           float zp = 0.0f;
-          if (k < K) {
 #pragma unroll
-            for (int ht = 0; ht < HTM; ++ht)
-              if (ht < HT) zp = fmaf(av[ht][i], W2s[k * HP + ht * 16 + l16], zp);
+          for (int ht = 0; ht < HTM; ++ht) {
+            const float wv = W2s[k * HP + (ht < HT ? ht : 0) * 16 + l16];
+            zp = fmaf(av[ht][i], ht < HT ? wv : 0.0f, zp);
           }
           zp = sum16(zp);
-          float dv = 0.0f;
-          if (k < K && valid) {
-            const float y = sigmoid(zp + b2s[k]);
-            const float err = y - Ts[r * 4 + k];
-            if (l16 == 0) sq = fmaf(err, err, sq);
-            dv = dscale * err * y * (1.0f - y);
-          }
-          d2[i][k] = dv;
+          const float y = sigmoid(zp + b2s[k]);
+          const bool on = k < K && valid;
+          const float err = on ? y - Ts[r * 4 + k] : 0.0f;
+          sq = fmaf(l16 == 0 ? err : 0.0f, err, sq);
+          d2[i][k] = dscale * err * y * (1.0f - y);
         }
       }
       if (l16 == 0) {
@@ -211,7 +215,7 @@ __global__ __launch_bounds__(NW * 64) void k_small_train(
           for (int i = 0; i < 4; ++i) {
             float bp = 0.0f;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
+            for (int k = 0; k < KO; ++k) {
               bp = fmaf(d2[i][k], W2s[k * HP + hc], bp);
               gw2[k][ht] = fmaf(d2[i][k], av[ht][i], gw2[k][ht]);
             }
@@ -326,11 +330,11 @@ __global__ __launch_bounds__(NW * 64) void k_small_train(
   }
 }
 
-template <int NW, int HTM>
+template <int NW, int HTM, int KO>
 hipError_t launch_one(const mlp_batch_item *items, mlp_batch_item one, int n_nets, int n_in,
                       int n_out, size_t lds, const float *X, const float *T, float *theta,
                       float *comp, int epochs, float *loss_hist, hipStream_t s) {
-  auto kern = k_small_train<NW, HTM>;
+  auto kern = k_small_train<NW, HTM, KO>;
   hipError_t e = hipFuncSetAttribute((const void *)kern,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -345,14 +349,18 @@ hipError_t launch_nw(int max_hidden, const mlp_batch_item *items, mlp_batch_item
                      float *theta, float *comp, int epochs, float *loss_hist, hipStream_t s) {
   // registers are sized for the widest hidden layer of the launch
   const int ht = (max_hidden + 15) / 16;
+  if (n_out <= 3) {
+    if (ht <= 1)
+      return launch_one<NW, 1, 3>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs, loss_hist, s);
+    if (ht <= 2)
+      return launch_one<NW, 2, 3>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs, loss_hist, s);
+    return launch_one<NW, 4, 3>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs, loss_hist, s);
+  }
   if (ht <= 1)
-    return launch_one<NW, 1>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs,
-                             loss_hist, s);
+    return launch_one<NW, 1, 4>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs, loss_hist, s);
   if (ht <= 2)
-    return launch_one<NW, 2>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs,
-                             loss_hist, s);
-  return launch_one<NW, 4>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs,
-                           loss_hist, s);
+    return launch_one<NW, 2, 4>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs, loss_hist, s);
+  return launch_one<NW, 4, 4>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs, loss_hist, s);
 }
 
 }  // namespace mlpk
