@@ -50,6 +50,7 @@ PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = {
     "small": ["small_train.hip", "mlp_device.hpp"],
     "large": ["large_train.hip", "mlp_device.hpp", "mlp_large.hpp"],
+    "layer": ["layer.hip", "mlp_device.hpp"],
 }
 
 
@@ -140,7 +141,7 @@ def bench_single(args):
     if wl in (4, 5):
         flops = contraction_flops_per_sample(D, H) * N * steps
         pi = {"fp32": 0, "bf16": 1, "e4m3": 2}[prec]
-        bound, peak, unit, kname, kind = "mfma", PEAK[prec], "TFLOP/s", f"mlpk::k_large_train<{pi}, {3 if K <= 3 else 4}>", "large"
+        bound, peak, unit, kname, kind = "mfma", PEAK[prec], "TFLOP/s", f"mlpk::k_large_train<{pi}, {3 if K <= 3 else 4}, 4>", "large"
     else:
         flops = flops_per_sample_epoch(D, H, K) * N * steps + 2 * P * n_updates
         bound, peak, unit, kname, kind = "alu", PEAK["fp32"], "TFLOP/s", "mlpk::k_small_train", "small"
@@ -302,7 +303,7 @@ def bench_shared(args):
                 "compensated_update": True, "operand_precision": prec, "step": "one epoch of every net"},
         roofline={"bound": "mfma", "achieved": achieved, "peak": PEAK[prec], "unit": "TFLOP/s",
                   "frac": achieved / PEAK[prec], "traffic": measured_traffic(f"w6-{prec}-steps{steps}", "large"),
-                  "traffic_unit": "bytes per launch", "kernel": f"mlpk::k_large_train<{pi}, 3>",
+                  "traffic_unit": "bytes per launch", "kernel": f"mlpk::k_large_train<{pi}, 3, 4>",
                   "kernel_ms": kern * 1e3, "flops_per_launch": flops},
         final_loss_mean=float(hist[:, steps - 1].mean().item()) if steps else None, steps=steps, warmup=warmup)
     return res, dict(w=w, batch=batch)
@@ -403,8 +404,10 @@ def bench_predict(args):
                             "correct count)", "n_rows": N, "n_in": D, "n_hidden": H, "n_out": K,
                 "step": "one mlp_predict call over all rows"},
         roofline={"bound": "alu", "achieved": achieved, "peak": PEAK["fp32"], "unit": "TFLOP/s",
-                  "frac": achieved / PEAK["fp32"], "traffic": None, "traffic_unit": "bytes per launch",
-                  "kernel": "mlpk::k_forward", "kernel_ms": kern * 1e3 / steps, "flops_per_launch": flops // steps},
+                  "frac": achieved / PEAK["fp32"], "traffic": measured_traffic(f"p4-fp32-steps{steps}", "layer"),
+                  "traffic_unit": "bytes per launch",
+                  "kernel": "mlp_predict (mlpk::k_fill_i32 + k_forward_tiled + k_argmax)",
+                  "kernel_ms": kern * 1e3 / steps, "flops_per_launch": flops // steps},
         steps=steps, warmup=warmup)
     return res, dict(w=w)
 
