@@ -8,17 +8,24 @@
 // HBM is read once at the start and written once at the end.  Each of the
 // NW waves owns every NW-th 16-row tile of the batch and, per epoch:
 //
-//   z1 = [X 1][W1 b1]^T        v_mfma_f32_16x16x4_f32, M = rows, N = hidden
+//   z1^T = [W1 b1] [X 1]^T     v_mfma_f32_16x16x4_f32, M = hidden, N = rows
 //   a = sigma(z1), slope = a (1 - a) (as e^-z a^2), kept in registers in the
-//       MFMA accumulator layout (lane: 4 rows x 1 hidden unit per 16x16 tile)
-//   z2 = a W2^T + b2           per lane over its hidden units, then summed
-//                              across the 16 lanes of each row
+//       MFMA accumulator layout (lane: 1 row x 4 hidden units per 16x16 tile)
+//   z2 = a W2^T + b2           per lane over its hidden units, then a
+//                              reduce-scatter over the lanes of the row, so
+//                              that lane (row n, group g) holds output g of
+//                              row n and every lane evaluates one sigmoid
 //   y = sigma(z2), delta2 = 2 (y - t) / (N K) . y (1 - y)
-//   delta1 = (delta2 W2) . slope   (the pre-update W2)
+//   delta1^T = W2^T delta2^T   v_mfma_f32_16x16x4_f32 (the pre-update W2;
+//                              the contraction over the <= 4 outputs is one
+//                              instruction), times the slope
+//   gW2^T += a^T delta2        v_mfma_f32_16x16x4_f32, K = the tile's rows
 //   gW1 += delta1^T [X 1]      v_mfma_f32_16x16x4_f32, M = hidden, N = features,
-//                              K = the tile's rows (delta1 staged through a
-//                              wave-private LDS tile to transpose it)
-//   gW2 += delta2^T a, gb2 += sum delta2   (lane partials)
+//                              K = the tile's rows
+//   gb2 += sum delta2          lane partials
+//
+// a, delta1 and delta2 pass through wave-private LDS tiles where a
+// contraction needs them transposed.
 //
 // After a barrier the NW wave partials of every parameter are summed in wave
 // order (bitwise repeatable) and the owner thread applies the update to the
@@ -56,8 +63,9 @@ struct SmallLayout {
   __host__ __device__ int w2() const { return w1() + HP * XS; }     // [4][HP]  master W2
   __host__ __device__ int b2() const { return w2() + 4 * HP; }      // [4]      master b2
   __host__ __device__ int ts() const { return b2() + 4; }           // [NP][4]  targets
-  __host__ __device__ int dst() const { return ts() + NP * 4; }     // [NW][16][16] delta1 staging
-  __host__ __device__ int part() const { return dst() + NW * 256; } // [NW][PW] partials
+  __host__ __device__ int dst() const { return ts() + NP * 4; }     // [NW][16][16] a / delta1 staging
+  __host__ __device__ int dd() const { return dst() + NW * 256; }   // [NW][16][4] delta2 staging
+  __host__ __device__ int part() const { return dd() + NW * 64; }   // [NW][PW] partials
   __host__ __device__ int total() const { return part() + NW * PW; }
 };
 
@@ -86,6 +94,7 @@ __global__ __launch_bounds__(NW * 64) void k_small_train(
   float *b2s = sm + L.b2();
   float *Ts = sm + L.ts();
   float *Dst = sm + L.dst() + wave * 256;
+  float *Dd = sm + L.dd() + wave * 64;
   float *Part = sm + L.part();
 
   const float *Xg = X + it.x_off * D;
@@ -142,22 +151,23 @@ __global__ __launch_bounds__(NW * 64) void k_small_train(
 
   for (int e = 0; e < epochs; ++e) {
     // ======================= rows of this wave: forward, deltas, partial gradients
-    f32x4_s gacc[HTM][4];
+    f32x4_s gacc[HTM][4];   // gW1 tiles [hidden][feature]
+    f32x4_s g2acc[HTM];     // gW2^T tiles [hidden][output]
 #pragma unroll
-    for (int ht = 0; ht < HTM; ++ht)
+    for (int ht = 0; ht < HTM; ++ht) {
+      g2acc[ht] = f32x4_s{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int ft = 0; ft < 4; ++ft) gacc[ht][ft] = f32x4_s{0.f, 0.f, 0.f, 0.f};
-    float gw2[4][HTM];   // [k][ht]: this lane's hidden unit, summed over its rows
-    float gb2[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-      for (int ht = 0; ht < HTM; ++ht) gw2[k][ht] = 0.0f;
+    }
+    float gb2 = 0.0f;   // output lg of this lane's rows
     float sq = 0.0f;
 
     for (int rt = wave; rt < L.NPT; rt += NW) {
       const int r0 = rt * 16;
-      // z1 tiles over every hidden tile; a and its slope stay in registers
+      const int n = r0 + l16;   // this lane's row
+      // z1^T tiles (M = hidden, N = rows): lane (row l16, group lg) holds
+      // hidden units 4 lg .. 4 lg + 3 of each tile; a and its slope stay in
+      // registers
       float av[HTM][4], sl[HTM][4];
 #pragma unroll
       for (int ht = 0; ht < HTM; ++ht) {
@@ -168,59 +178,62 @@ __global__ __launch_bounds__(NW * 64) void k_small_train(
           const float *xa = Xs + (r0 + l16) * XS + lg;
           const float *wb = W1s + (ht * 16 + l16) * XS + lg;
           for (int k0 = 0; k0 < DK; k0 += 4)
-            z = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[k0], wb[k0], z, 0, 0, 0);
+            z = __builtin_amdgcn_mfma_f32_16x16x4f32(wb[k0], xa[k0], z, 0, 0, 0);
 #pragma unroll
           for (int i = 0; i < 4; ++i) av[ht][i] = sigmoid_slope(z[i], sl[ht][i]);
         }
       }
-      // output layer for this lane's 4 rows: partial over its hidden units,
-      // then summed across the 16 lanes of the row group.  Branch-free (the
-      // selects keep padding rows, outputs and hidden tiles at zero), so the
-      // 4 x KO independent chains can be interleaved.
-      float d2[4][4];  // [i][k]
+      // output layer: each lane's share of z2 (its 4 hidden units per tile)
+      // for every output, then a reduce-scatter over the four row groups
+      // (lanes n, n+16, n+32, n+48) leaves z2[n][lg] in lane (n, lg): every
+      // lane evaluates one output of one row.  Padding hidden tiles read
+      // tile 0's weights and multiply them by a zero activation.
+      float zp[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int r = r0 + 4 * lg + i;
-        const bool valid = r < N;
+      for (int ht = 0; ht < HTM; ++ht) {
+        const int hs = (ht < HT ? ht : 0) * 16 + 4 * lg;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          if (k >= KO) {
-            d2[i][k] = 0.0f;
-            continue;
-          }
-          float zp = 0.0f;
+        for (int k = 0; k < KO; ++k) {
+          const f32x4_s w = *reinterpret_cast<const f32x4_s *>(W2s + k * HP + hs);
 #pragma unroll
-          for (int ht = 0; ht < HTM; ++ht) {
-            const float wv = W2s[k * HP + (ht < HT ? ht : 0) * 16 + l16];
-            zp = fmaf(av[ht][i], ht < HT ? wv : 0.0f, zp);
-          }
-          zp = sum16(zp);
-          const float y = sigmoid(zp + b2s[k]);
-          const bool on = k < K && valid;
-          const float err = on ? y - Ts[r * 4 + k] : 0.0f;
-          sq = fmaf(l16 == 0 ? err : 0.0f, err, sq);
-          d2[i][k] = dscale * err * y * (1.0f - y);
+          for (int i = 0; i < 4; ++i) zp[k] = fmaf(av[ht][i], w[i], zp[k]);
         }
       }
-      if (l16 == 0) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) gb2[k] += (d2[0][k] + d2[1][k]) + (d2[2][k] + d2[3][k]);
-      }
-      // hidden deltas, gW2 lane partials, and gW1 on MFMA
+      const bool hi2 = (lg & 2) != 0, hi1 = (lg & 1) != 0;
+      float ka = hi2 ? zp[2] : zp[0], kb = hi2 ? zp[3] : zp[1];   // outputs kept
+      const float sa = hi2 ? zp[0] : zp[2], sb = hi2 ? zp[1] : zp[3];
+      ka += __shfl_xor(sa, 32, kWave);
+      kb += __shfl_xor(sb, 32, kWave);
+      const float z2 = (hi1 ? kb : ka) + __shfl_xor(hi1 ? ka : kb, 16, kWave);
+      const int k = lg;
+      const float y = sigmoid(z2 + b2s[k]);
+      const bool on = k < K && n < N;
+      const float err = on ? y - Ts[n * 4 + k] : 0.0f;
+      sq = fmaf(err, err, sq);
+      const float d2 = dscale * err * y * (1.0f - y);
+      gb2 += d2;
+      Dd[l16 * 4 + k] = d2;   // row-major [row][output] for the gW2 contraction
 #pragma unroll
       for (int ht = 0; ht < HTM; ++ht) {
         if (ht < HT) {
-          const int hc = ht * 16 + l16;
+          // gW2^T += a^T delta2 (M = hidden, N = outputs, K = the tile's
+          // rows), a staged row-major through the wave's LDS tile
+          *reinterpret_cast<f32x4_s *>(Dst + l16 * 16 + 4 * lg) =
+              f32x4_s{av[ht][0], av[ht][1], av[ht][2], av[ht][3]};
+          f32x4_s g2 = g2acc[ht];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            float bp = 0.0f;
-#pragma unroll
-            for (int k = 0; k < KO; ++k) {
-              bp = fmaf(d2[i][k], W2s[k * HP + hc], bp);
-              gw2[k][ht] = fmaf(d2[i][k], av[ht][i], gw2[k][ht]);
-            }
-            Dst[(4 * lg + i) * 16 + l16] = bp * sl[ht][i];
+          for (int s = 0; s < 4; ++s) {
+            const float dv = Dd[(4 * s + lg) * 4 + (l16 & 3)];
+            g2 = __builtin_amdgcn_mfma_f32_16x16x4f32(Dst[(4 * s + lg) * 16 + l16], l16 < 4 ? dv : 0.0f,
+                                                     g2, 0, 0, 0);
           }
+          g2acc[ht] = g2;
+          // delta1^T = W2^T delta2^T (the pre-update W2), times the slope
+          const f32x4_s bp = __builtin_amdgcn_mfma_f32_16x16x4f32(
+              W2s[lg * HP + ht * 16 + l16], d2, f32x4_s{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+          *reinterpret_cast<f32x4_s *>(Dst + l16 * 16 + 4 * lg) =
+              f32x4_s{bp[0] * sl[ht][0], bp[1] * sl[ht][1], bp[2] * sl[ht][2], bp[3] * sl[ht][3]};
+          // gW1 += delta1^T [X 1] on MFMA
           const float *da = Dst + lg * 16 + l16;
 #pragma unroll
           for (int ft = 0; ft < 4; ++ft) {
@@ -249,22 +262,12 @@ __global__ __launch_bounds__(NW * 64) void k_small_train(
             for (int i = 0; i < 4; ++i) pw[(ht * 16 + 4 * lg + i) * DN + ft * 16 + l16] = gacc[ht][ft][i];
           }
         }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          float v = gw2[k][ht];
-          v += __shfl_xor(v, 16, kWave);
-          v += __shfl_xor(v, 32, kWave);
-          if (lg == 0) pw[HP * DN + k * HP + ht * 16 + l16] = v;
-        }
+        // lane (output l16, group lg): hidden units 4 lg .. 4 lg + 3
+        if (l16 < 4) *reinterpret_cast<f32x4_s *>(pw + HP * DN + l16 * HP + ht * 16 + 4 * lg) = g2acc[ht];
       }
     }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      float v = gb2[k];
-      v += __shfl_xor(v, 16, kWave);
-      v += __shfl_xor(v, 32, kWave);
-      if (lane == 0) pw[HP * DN + 4 * HP + k] = v;
-    }
+    gb2 = sum16(gb2);
+    if (l16 == 0) pw[HP * DN + 4 * HP + lg] = gb2;
     sq = wave_sum(sq);
     if (lane == 0) pw[HP * DN + 4 * HP + 4] = sq;
     __syncthreads();
