@@ -144,6 +144,35 @@ __global__ __launch_bounds__(NW * 64) void k_small_train(
     }
     ccomp[j] = c;
   }
+  // LDS offsets of parameter q (update order): its partial within a wave's
+  // block and its master copy.  Kept packed in registers across epochs when
+  // a thread owns few parameters.
+  auto offsets = [&](int q, int &po, int &mo) {
+    if (q < H * D1) {
+      const int h = q / D1, d = q - h * D1;
+      po = h * DN + d;
+      mo = L.w1() + h * XS + d;
+    } else if (q < H * D1 + K * H) {
+      const int o = q - H * D1, k = o / H, h = o - k * H;
+      po = HP * DN + k * HP + h;
+      mo = L.w2() + k * HP + h;
+    } else {
+      const int k = q - H * D1 - K * H;
+      po = HP * DN + 4 * HP + k;
+      mo = L.b2() + k;
+    }
+  };
+  constexpr bool kKeepOfs = JM <= 8;
+  int uofs[kKeepOfs ? JM : 1];
+  if constexpr (kKeepOfs) {
+#pragma unroll
+    for (int j = 0; j < JM; ++j) {
+      const int q = tid + j * NT;
+      int po = 0, mo = 0;
+      if (q < nP) offsets(q, po, mo);
+      uofs[j] = (po << 16) | mo;   // both below 2^16
+    }
+  }
   __syncthreads();
 
   const float dscale = 2.0f / (float)(N * K);
@@ -282,26 +311,18 @@ __global__ __launch_bounds__(NW * 64) void k_small_train(
     for (int j = 0; j < JM; ++j) {
       const int q = tid + j * NT;
       if (q < nP) {
-        int po;       // partial offset within a wave's block
-        float *mw;    // master copy in LDS
-        if (q < H * D1) {
-          const int h = q / D1, d = q - h * D1;
-          po = h * DN + d;
-          mw = W1s + h * XS + d;
-        } else if (q < H * D1 + K * H) {
-          const int o = q - H * D1, k = o / H, h = o - k * H;
-          po = HP * DN + k * HP + h;
-          mw = W2s + k * HP + h;
+        int po, mo;
+        if constexpr (kKeepOfs) {
+          po = uofs[j] >> 16;
+          mo = uofs[j] & 0xffff;
         } else {
-          const int k = q - H * D1 - K * H;
-          po = HP * DN + 4 * HP + k;
-          mw = b2s + k;
+          offsets(q, po, mo);
         }
         float g = 0.0f;
         for (int w = 0; w < NW; ++w) g += Part[w * PW + po];
-        float wv = *mw;
+        float wv = sm[mo];
         gd_update(wv, ccomp[j], lr, g, compensated);
-        *mw = wv;
+        sm[mo] = wv;
       }
     }
     __syncthreads();
