@@ -23,7 +23,12 @@ w4/w5 take --prec fp32|bf16|e4m3, w6 fp32|bf16 (operand precision of the two con
 The timed region is one training call of K steps (one kernel launch).  The
 JSON line carries the roofline of that kernel, timed with HIP events on the
 stream it runs on, and the FP64 CPU oracle's throughput on a bounded sample
-of the same workload on the host cores.
+of the same workload on the host cores.  Also reported: `repeats` (median and
+minimum per step over the timed run and five more runs of the same K steps,
+when one run takes under 1.5 s) and `vs_plain` (the chosen form's rate over
+the plain single-network FP32 kernel's on the same GPU: w3 against one launch
+per net on a sample of its nets, w4/w5 bf16/e4m3 against their FP32 runs, w6
+against one net of its shape).
 """
 from __future__ import annotations
 
@@ -116,6 +121,16 @@ def timed(fn, stream):
     return time.perf_counter() - t0, ev0.elapsed_time(ev1) / 1e3
 
 
+def repeats(fn, stream, first_wall: float, steps: int, max_wall: float = 1.5, runs: int = 5):
+    """Median and minimum over the timed run and up to `runs` more runs of
+    the same K steps (only when one run is short)."""
+    ms = [first_wall * 1e3 / steps]
+    if first_wall < max_wall:
+        for _ in range(runs):
+            ms.append(timed(fn, stream)[0] * 1e3 / steps)
+    return {"runs": len(ms), "median_ms_per_step": float(np.median(ms)), "min_ms_per_step": float(min(ms))}
+
+
 # ---------------------------------------------------------------- single nets (w1, w2, w4, w5)
 def bench_single(args):
     import torch
@@ -136,6 +151,17 @@ def bench_single(args):
         net.train(X, T, warmup, loss_hist=hist[:warmup])
     stream = torch.cuda.current_stream()
     wall, kern = timed(lambda: net.train(X, T, steps, loss_hist=hist[:steps]), stream)
+    final_loss = float(hist[steps - 1].item()) if steps else None
+    reps = repeats(lambda: net.train(X, T, steps, loss_hist=hist[:steps]), stream, wall, steps)
+    vs_plain = None
+    if prec != "fp32":
+        # the same run on the plain FP32 kernel (same initial parameters)
+        plain = mlp.Net(D, H, K, N, batch=w["batch"], lr=w["lr"], prec="fp32", theta=w["theta"])
+        plain.train(X, T, 1)
+        pwall, _ = timed(lambda: plain.train(X, T, steps), stream)
+        pv = N * steps / pwall
+        vs_plain = {"speedup": (N * steps / wall) / pv, "plain_value": pv,
+                    "plain": "the same workload on the FP32 operand kernel", "sample": "the full workload"}
     P = D * H + H + H * K + K
     n_updates = steps * (-(-N // batch))
     if wl in (4, 5):
@@ -160,7 +186,7 @@ def bench_single(args):
         roofline={"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
                   "traffic": measured_traffic(tkey, kind), "traffic_unit": "bytes per launch", "kernel": kname,
                   "kernel_ms": kern * 1e3, "flops_per_launch": flops},
-        final_loss=float(hist[steps - 1].item()) if steps else None, steps=steps, warmup=warmup)
+        final_loss=final_loss, repeats=reps, vs_plain=vs_plain, steps=steps, warmup=warmup)
     return res, dict(w=w, wl=wl, batch=batch)
 
 
@@ -210,7 +236,31 @@ def bench_batched(args):
     graph = mlp.BatchedGraph(plan, X, T, th, comp, steps, 33, 3, loss_hist=hist)
     stream = torch.cuda.current_stream()
     wall, kern = timed(graph.replay, stream)
+    reps = repeats(graph.replay, stream, wall, steps)
     mlp.reset_launch_hint()
+    # plain form: the single-network kernel launched once per net, one net
+    # after another, on the first 32 nets
+    sample = items[:32]
+    nets = []
+    for it in sample:
+        H = it["n_hidden"]
+        P = 33 * H + H + 3 * H + 3
+        r0, n = it["x_off"], it["n_rows"]
+        nets.append((mlp.Net(33, H, 3, n, lr=float(it["lr"]),
+                             theta=synth.Theta.unpack(w["theta"][it["p_off"]:it["p_off"] + P], 33, H, 3)),
+                     X[r0:r0 + n].clone(), T[r0:r0 + n].clone()))   # own (aligned) allocations
+    for net, Xi, Ti in nets[:2]:
+        net.train(Xi, Ti, 1)
+
+    def plain_loop():
+        for net, Xi, Ti in nets:
+            net.train(Xi, Ti, steps)
+    pwall, _ = timed(plain_loop, stream)
+    prows = sum(it["n_rows"] for it in sample)
+    vs_plain = {"speedup": (sum(it["n_rows"] for it in items) * steps / wall) / (prows * steps / pwall),
+                "plain_value": prows * steps / pwall,
+                "plain": "the single-network FP32 kernel, one launch per net, nets one after another",
+                "sample": f"the first {len(sample)} nets, {steps} epochs each"}
     # cross-validation read-out: every net on its held-out fold (mlp_eval_batched),
     # then the hyperparameter group with the lowest mean held-out loss
     vplan = mlp.BatchPlan(w["items_val"])
@@ -246,7 +296,8 @@ def bench_batched(args):
         roofline={"bound": "alu", "achieved": achieved, "peak": PEAK["fp32"], "unit": "TFLOP/s",
                   "frac": achieved / PEAK["fp32"], "traffic": measured_traffic(f"w3-fp32-steps{steps}", "small"),
                   "traffic_unit": "bytes per launch", "kernel": "mlpk::k_small_train",
-                  "kernel_ms": kern * 1e3, "flops_per_launch": flops}, steps=steps, warmup=warmup)
+                  "kernel_ms": kern * 1e3, "flops_per_launch": flops}, repeats=reps, vs_plain=vs_plain,
+        steps=steps, warmup=warmup)
     return res, dict(w=w)
 
 
@@ -291,6 +342,16 @@ def bench_shared(args):
     stream = torch.cuda.current_stream()
     wall, kern = timed(lambda: mlp.train_shared(X, T, th, w["lrs"], steps, H, batch=batch, prec=prec, comp=comp,
                                                 loss_hist=hist[:, :steps], workspace=ws), stream)
+    final_loss_mean = float(hist[:, steps - 1].mean().item()) if steps else None
+    # plain form: one net of the same shape on the single-network FP32
+    # kernel (the 64 nets would run one after another), one epoch
+    plain = mlp.Net(D, H, K, N, batch=batch, lr=float(w["lrs"][0]), prec="fp32",
+                    theta=synth.Theta.unpack(w["theta"][0], D, H, K))
+    plain.train(X, T, 1)
+    pwall, _ = timed(lambda: plain.train(X, T, 1), stream)
+    vs_plain = {"speedup": (M * N * steps / wall) / (N / pwall), "plain_value": N / pwall,
+                "plain": "one net of the same shape on the single-network FP32 kernel (the nets one after another)",
+                "sample": "net 0, one epoch"}
     flops = contraction_flops_per_sample(D, H) * N * M * steps
     achieved = flops / kern / 1e12
     pi = {"fp32": 0, "bf16": 1}[prec]
@@ -305,7 +366,9 @@ def bench_shared(args):
                   "frac": achieved / PEAK[prec], "traffic": measured_traffic(f"w6-{prec}-steps{steps}", "large"),
                   "traffic_unit": "bytes per launch", "kernel": f"mlpk::k_large_train<{pi}, 3, 4>",
                   "kernel_ms": kern * 1e3, "flops_per_launch": flops},
-        final_loss_mean=float(hist[:, steps - 1].mean().item()) if steps else None, steps=steps, warmup=warmup)
+        final_loss_mean=final_loss_mean, repeats={"runs": 1, "median_ms_per_step": wall * 1e3 / steps,
+                                                  "min_ms_per_step": wall * 1e3 / steps},
+        vs_plain=vs_plain, steps=steps, warmup=warmup)
     return res, dict(w=w, batch=batch)
 
 
@@ -395,6 +458,7 @@ def bench_predict(args):
         for _ in range(steps):
             net.predict(X, T)
     wall, kern = timed(run, stream)
+    reps = repeats(run, stream, wall, steps)
     flops = (2 * D * H + 4 * H + 2 * H * K + 4 * K) * N * steps    # z1, sigma, z2, sigma per row
     achieved = flops / kern / 1e12
     res = dict(
@@ -408,7 +472,7 @@ def bench_predict(args):
                   "traffic_unit": "bytes per launch",
                   "kernel": "mlp_predict (mlpk::k_fill_i32 + k_forward_tiled + k_argmax)",
                   "kernel_ms": kern * 1e3 / steps, "flops_per_launch": flops // steps},
-        steps=steps, warmup=warmup)
+        repeats=reps, steps=steps, warmup=warmup)
     return res, dict(w=w)
 
 
