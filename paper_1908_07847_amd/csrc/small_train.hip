@@ -42,6 +42,11 @@ namespace mlpk {
 
 typedef float f32x4_s __attribute__((ext_vector_type(4)));
 
+// The value of v in lane l of the wave (uniform result).
+__device__ __forceinline__ float lane_value(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
 // LDS plan (floats).
 struct SmallLayout {
   int N, H, D, K, NW, NP, NPT, DA, DK, DN, XS, HP, HT, FT, PW;
@@ -297,8 +302,11 @@ __global__ __launch_bounds__(NW * 64) void k_small_train(
     }
     gb2 = sum16(gb2);
     if (l16 == 0) pw[HP * DN + 4 * HP + lg] = gb2;
-    sq = wave_sum(sq);
-    if (lane == 0) pw[HP * DN + 4 * HP + 4] = sq;
+    // (the lane reads stay outside the branch: the row sums must be complete
+    // in all four rows, not only in the lane that stores)
+    sq = sum16(sq);
+    const float sqw = (lane_value(sq, 0) + lane_value(sq, 16)) + (lane_value(sq, 32) + lane_value(sq, 48));
+    if (lane == 0) pw[HP * DN + 4 * HP + 4] = sqw;
     __syncthreads();
 
     // ======================= sum the wave partials in order; update
@@ -307,22 +315,42 @@ __global__ __launch_bounds__(NW * 64) void k_small_train(
       for (int w = 0; w < NW; ++w) s += Part[w * PW + HP * DN + 4 * HP + 4];
       loss_hist[(int64_t)blockIdx.x * epochs + e] = s * inv_nk;
     }
+    if constexpr (kKeepOfs) {
+      // the partial sums of a thread's first two parameters load
+      // unconditionally (an unused slot reads offset 0), so both batches of
+      // loads are in flight together
+      float gs[JM];
 #pragma unroll
-    for (int j = 0; j < JM; ++j) {
-      const int q = tid + j * NT;
-      if (q < nP) {
-        int po, mo;
-        if constexpr (kKeepOfs) {
-          po = uofs[j] >> 16;
-          mo = uofs[j] & 0xffff;
-        } else {
-          offsets(q, po, mo);
+      for (int j = 0; j < JM; ++j) {
+        gs[j] = 0.0f;
+        if (j < 2 || tid + j * NT < nP) {
+          const int po = uofs[j] >> 16;
+#pragma unroll
+          for (int w = 0; w < NW; ++w) gs[j] += Part[w * PW + po];
         }
-        float g = 0.0f;
-        for (int w = 0; w < NW; ++w) g += Part[w * PW + po];
-        float wv = sm[mo];
-        gd_update(wv, ccomp[j], lr, g, compensated);
-        sm[mo] = wv;
+      }
+#pragma unroll
+      for (int j = 0; j < JM; ++j) {
+        if (tid + j * NT < nP) {
+          const int mo = uofs[j] & 0xffff;
+          float wv = sm[mo];
+          gd_update(wv, ccomp[j], lr, gs[j], compensated);
+          sm[mo] = wv;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < JM; ++j) {
+        const int q = tid + j * NT;
+        if (q < nP) {
+          int po, mo;
+          offsets(q, po, mo);
+          float g = 0.0f;
+          for (int w = 0; w < NW; ++w) g += Part[w * PW + po];
+          float wv = sm[mo];
+          gd_update(wv, ccomp[j], lr, g, compensated);
+          sm[mo] = wv;
+        }
       }
     }
     __syncthreads();
