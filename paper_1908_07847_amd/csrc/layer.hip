@@ -20,7 +20,8 @@
 //  k_eval_batched  one workgroup per net of a batched item table: loss and
 //                  correct count of the net on its own rows (e.g. a held-out
 //                  fold), threads over rows, fixed-order block sums
-//  k_argmax        one thread per row: the class is the index of the largest
+//  k_argmax        rows in a grid-stride loop (at most 512 workgroups): the
+//                  class is the index of the largest
 //                  output (lowest index on ties); with one-hot targets, the
 //                  count of rows whose class matches the target's, summed
 //                  per block and added once per block (integer adds, so the
@@ -54,6 +55,8 @@ constexpr int kFwdRows = 64, kFwdHB = 64, kFwdMaxD = 256;
 
 typedef float f32x4_l __attribute__((ext_vector_type(4)));
 
+// KO: output slots held per row in registers (K <= KO).
+template <int KO>
 __global__ __launch_bounds__(256) void k_forward_tiled(int64_t n, int D, int H, int K,
                                                        const float *__restrict__ X, mlp_params p,
                                                        float *__restrict__ A, float *__restrict__ Y) {
@@ -72,11 +75,11 @@ __global__ __launch_bounds__(256) void k_forward_tiled(int64_t n, int D, int H, 
     const int r = q / XS, c = q - r * XS;
     xs[q] = (r < rows && c < D) ? X[(r0 + r) * D + c] : 0.0f;
   }
-  float zp[4][kLayerMaxOut];
+  float zp[4][KO];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int k = 0; k < kLayerMaxOut; ++k) zp[i][k] = 0.0f;
+    for (int k = 0; k < KO; ++k) zp[i][k] = 0.0f;
   for (int h0 = 0; h0 < H; h0 += kFwdHB) {
     __syncthreads();   // the previous block's W1 / W2 are no longer read
     for (int q = tid; q < kFwdHB * XS; q += 256) {
@@ -102,7 +105,7 @@ __global__ __launch_bounds__(256) void k_forward_tiled(int64_t n, int D, int H, 
         const float a = h < H ? sigmoid(z[i] + b1[hl]) : 0.0f;
         if (A && r < rows && h < H) A[(r0 + r) * H + h] = a;
 #pragma unroll
-        for (int k = 0; k < kLayerMaxOut; ++k)
+        for (int k = 0; k < KO; ++k)
           if (k < K) zp[i][k] = fmaf(a, w2[k * kFwdHB + hl], zp[i][k]);
       }
     }
@@ -111,7 +114,7 @@ __global__ __launch_bounds__(256) void k_forward_tiled(int64_t n, int D, int H, 
   for (int i = 0; i < 4; ++i) {
     const int r = wave * 16 + 4 * lg + i;
 #pragma unroll
-    for (int k = 0; k < kLayerMaxOut; ++k) {
+    for (int k = 0; k < KO; ++k) {
       if (k < K) {
         const float z2 = sum16(zp[i][k]);
         if (l16 == 0 && r < rows) Y[(r0 + r) * K + k] = sigmoid(z2 + p.b2[k]);
@@ -282,12 +285,11 @@ __global__ __launch_bounds__(256) void k_eval_batched(const mlp_batch_item *__re
 __global__ __launch_bounds__(256) void k_argmax(int64_t n, int K, const float *__restrict__ Y,
                                                 const float *__restrict__ T, int32_t *__restrict__ labels,
                                                 int32_t *__restrict__ correct) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int hit = 0;
-  if (r < n) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
     const int c = argmax_row(Y + r * K, K);
     labels[r] = c;
-    if (T) hit = c == argmax_row(T + r * K, K);
+    if (T) hit += c == argmax_row(T + r * K, K);
   }
   if (T) {
     __shared__ int part[4];
@@ -311,11 +313,17 @@ hipError_t launch_forward(int64_t n, int D, int H, int K, const float *X, mlp_pa
     const int XS = (D + 3) / 4 * 4 + 1;
     const size_t lds = sizeof(float) * ((size_t)(mlpk::kFwdRows + mlpk::kFwdHB) * XS +
                                         mlpk::kLayerMaxOut * mlpk::kFwdHB + mlpk::kFwdHB);
-    hipError_t e = hipFuncSetAttribute((const void *)mlpk::k_forward_tiled,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const void *kern = K <= 4 ? (const void *)mlpk::k_forward_tiled<4>
+                              : (const void *)mlpk::k_forward_tiled<mlpk::kLayerMaxOut>;
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const int64_t blocks = (n + mlpk::kFwdRows - 1) / mlpk::kFwdRows;
-    hipLaunchKernelGGL(mlpk::k_forward_tiled, dim3((unsigned)blocks), dim3(256), lds, s, n, D, H, K, X, p, A, Y);
+    if (K <= 4)
+      hipLaunchKernelGGL(mlpk::k_forward_tiled<4>, dim3((unsigned)blocks), dim3(256), lds, s, n, D, H, K, X, p,
+                         A, Y);
+    else
+      hipLaunchKernelGGL(mlpk::k_forward_tiled<mlpk::kLayerMaxOut>, dim3((unsigned)blocks), dim3(256), lds, s, n,
+                         D, H, K, X, p, A, Y);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(mlpk::k_forward, grid_for(n, 256), dim3(256), 0, s, n, D, H, K, X, p, A, Y);
@@ -337,7 +345,9 @@ hipError_t launch_predict(int64_t n, int D, int H, int K, const float *X, mlp_pa
     hipLaunchKernelGGL(mlpk::k_fill_i32, dim3(1), dim3(1), 0, s, correct, 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(mlpk::k_argmax, grid_for(n, 256), dim3(256), 0, s, n, K, Y, T, labels, correct);
+  // at most 512 blocks (rows in a grid-stride loop): one count add per block
+  const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(512, (n + 255) / 256)));
+  hipLaunchKernelGGL(mlpk::k_argmax, grid, dim3(256), 0, s, n, K, Y, T, labels, correct);
   return hipGetLastError();
 }
 
