@@ -121,6 +121,18 @@ def timed(fn, stream):
     return time.perf_counter() - t0, ev0.elapsed_time(ev1) / 1e3
 
 
+def sync_adjusted(mlp, torch, flops: float, peak_tflops: float, hbm_bytes: float, n_steps: int, kernel_s: float):
+    """The survey's sync-adjusted bound for the persistent large-N trainer:
+    max(flops / peak, bytes / HBM bandwidth) plus, per minibatch step, three
+    grid barriers at the latency measured on this GPU (mlp_barrier_probe with
+    one workgroup per CU, the grid the trainer's plans use here)."""
+    n_wg = torch.cuda.get_device_properties(0).multi_processor_count
+    t_bar = mlp.barrier_latency_us(n_wg)
+    bound_s = max(flops / (peak_tflops * 1e12), hbm_bytes / (PEAK_HBM_GBS * 1e9)) + n_steps * 3 * t_bar * 1e-6
+    return {"t_barrier_us": t_bar, "barriers_per_step": 3, "steps": n_steps, "workgroups": n_wg,
+            "bound_ms": bound_s * 1e3, "frac": bound_s / kernel_s}
+
+
 def repeats(fn, stream, first_wall: float, steps: int, max_wall: float = 1.5, runs: int = 5):
     """Median and minimum over the timed run and up to `runs` more runs of
     the same K steps (only when one run is short)."""
@@ -187,6 +199,9 @@ def bench_single(args):
                   "traffic": measured_traffic(tkey, kind), "traffic_unit": "bytes per launch", "kernel": kname,
                   "kernel_ms": kern * 1e3, "flops_per_launch": flops},
         final_loss=final_loss, repeats=reps, vs_plain=vs_plain, steps=steps, warmup=warmup)
+    if wl in (4, 5):
+        res["roofline"]["sync_adjusted"] = sync_adjusted(mlp, torch, flops, peak, N * steps * (D + K) * 4.0,
+                                                         steps * (-(-N // batch)), kern)
     return res, dict(w=w, wl=wl, batch=batch)
 
 
@@ -369,6 +384,8 @@ def bench_shared(args):
         final_loss_mean=final_loss_mean, repeats={"runs": 1, "median_ms_per_step": wall * 1e3 / steps,
                                                   "min_ms_per_step": wall * 1e3 / steps},
         vs_plain=vs_plain, steps=steps, warmup=warmup)
+    res["roofline"]["sync_adjusted"] = sync_adjusted(mlp, torch, flops, PEAK[prec], N * steps * (D + K) * 4.0,
+                                                     steps * (-(-N // batch)), kern)
     return res, dict(w=w, batch=batch)
 
 

@@ -213,6 +213,28 @@ mlp_status mlp_train_shared(const mlp_config *cfg /*host*/, int32_t n_nets, cons
                             const float *X, const float *T, float *theta, float *comp, int32_t epochs,
                             float *loss_hist, void *workspace, size_t ws_bytes, void *stream);
 
+/* ---- measurement ---------------------------------------------------------- */
+
+/* Bytes of workspace mlp_barrier_probe needs. */
+#define MLP_BARRIER_PROBE_WS_BYTES 2048
+
+/* Grid-barrier latency probe for the sync-adjusted bound of the large-N
+ * trainer: one cooperative launch of n_workgroups workgroups (256 threads
+ * each, at most one per CU on the device) that pass `rounds` grid barriers
+ * of the kind the large-N trainer passes three times per minibatch step
+ * (section 2.2's loop: forward, backpropagation, update), and do nothing
+ * else.  Timing two launches with different round counts on the stream
+ * gives the time one barrier adds.
+ *   n_workgroups  1 .. the device's CU count
+ *   rounds        0 .. 1,000,000
+ *   workspace     >= MLP_BARRIER_PROBE_WS_BYTES device bytes, 16-byte
+ *                 aligned; overwritten (barrier counters).  A barrier that
+ *                 does not complete within its spin limit sets the 32-bit
+ *                 word at index 16 to nonzero instead of hanging.
+ * Asynchronous on the stream; argument errors return before any launch. */
+mlp_status mlp_barrier_probe(int32_t n_workgroups, int32_t rounds, void *workspace, size_t ws_bytes,
+                             void *stream);
+
 /* ---- launch-shape hints -------------------------------------------------- */
 
 /* Overrides of launch shapes that do not change results beyond summation

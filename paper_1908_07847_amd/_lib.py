@@ -49,9 +49,11 @@ class LaunchHint(ctypes.Structure):
 assert ctypes.sizeof(BatchItem) == 32 and ctypes.sizeof(Config) == 40 and ctypes.sizeof(LaunchHint) == 16
 
 # Every symbol include/mlp.h declares.
+BARRIER_PROBE_WS_BYTES = 2048   # MLP_BARRIER_PROBE_WS_BYTES
+
 SYMBOLS = ["mlp_workspace_size", "mlp_init", "mlp_destroy", "mlp_forward", "mlp_backward", "mlp_step",
            "mlp_train", "mlp_predict", "mlp_train_batched", "mlp_eval_batched", "mlp_shared_workspace_size",
-           "mlp_train_shared",
+           "mlp_train_shared", "mlp_barrier_probe",
            "mlp_set_launch_hint", "mlp_status_string", "mlp_last_error"]
 
 
@@ -77,7 +79,8 @@ def _load():
     lib.mlp_train_shared.argtypes = [ctypes.POINTER(Config), i32, ctypes.POINTER(f32), vp, vp, vp, vp, i32, vp,
                                      vp, ctypes.c_size_t, vp]
     lib.mlp_set_launch_hint.argtypes = [ctypes.POINTER(LaunchHint)]
-    for name in SYMBOLS[:13]:
+    lib.mlp_barrier_probe.argtypes = [i32, i32, vp, ctypes.c_size_t, vp]
+    for name in SYMBOLS[:14]:
         getattr(lib, name).restype = ctypes.c_int
     lib.mlp_status_string.argtypes = [ctypes.c_int]
     lib.mlp_status_string.restype = ctypes.c_char_p

@@ -1008,6 +1008,22 @@ __global__ void k_zero_u32(unsigned *p, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
 }
 
+// Grid-barrier probe: the workgroups of a co-resident grid pass `rounds`
+// grid barriers of the trainer's kind and do nothing else, so a launch's
+// time over its rounds is the latency one barrier adds to a step when every
+// workgroup arrives together (the trainer pays three per step, plus the
+// wait for its slowest workgroup).
+__global__ __launch_bounds__(kLT) void k_barrier_probe(unsigned *bar, int rounds) {
+  GridSync gs;
+  if (threadIdx.x == 0) gs.init(bar, gridDim.x);
+  __syncthreads();
+  for (int r = 0; r < rounds; ++r) {
+    __syncthreads();
+    if (threadIdx.x == 0) gs.arrive_and_wait();
+    __syncthreads();
+  }
+}
+
 }  // namespace mlpk
 
 namespace mlph {
@@ -1244,5 +1260,18 @@ mlp_status large_train(const mlp_config &c, int n_nets, const float *lrs, const 
   if (e != hipSuccess) { *err = std::string("cooperative launch: ") + hipGetErrorString(e); return MLP_ERR_HIP; }
   return MLP_OK;
 }
+
+mlp_status barrier_probe(int n_wg, int rounds, void *ws, hipStream_t s, std::string *err) {
+  unsigned *bar = static_cast<unsigned *>(ws);
+  hipLaunchKernelGGL(mlpk::k_zero_u32, dim3(1), dim3(256), 0, s, bar, mlpk::kBarWords);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) { *err = hipGetErrorString(e); return MLP_ERR_HIP; }
+  void *args[] = {&bar, &rounds};
+  e = hipLaunchCooperativeKernel((const void *)mlpk::k_barrier_probe, dim3(n_wg), dim3(mlpk::kLT), args, 0, s);
+  if (e != hipSuccess) { *err = std::string("cooperative launch: ") + hipGetErrorString(e); return MLP_ERR_HIP; }
+  return MLP_OK;
+}
+
+size_t barrier_probe_workspace_bytes() { return sizeof(unsigned) * mlpk::kBarWords; }
 
 }  // namespace mlph

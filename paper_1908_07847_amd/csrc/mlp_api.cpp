@@ -396,4 +396,21 @@ mlp_status mlp_train_shared(const mlp_config *cfg, int32_t n_nets, const float *
                            ws_bytes, ncu, X, T, epochs, loss_hist, (hipStream_t)stream, &g_last_error);
 }
 
+mlp_status mlp_barrier_probe(int32_t n_workgroups, int32_t rounds, void *workspace, size_t ws_bytes,
+                             void *stream) {
+  if (rounds < 0 || rounds > 1000000) return fail(MLP_ERR_ARG, "rounds must be in 0 .. 1000000");
+  if (!workspace || ws_bytes < MLP_BARRIER_PROBE_WS_BYTES || ws_bytes < mlph::barrier_probe_workspace_bytes())
+    return fail(MLP_ERR_WORKSPACE, "workspace of %zu bytes given, %d needed", workspace ? ws_bytes : 0,
+                MLP_BARRIER_PROBE_WS_BYTES);
+  if (!aligned16(workspace)) return fail(MLP_ERR_ALIGN, "workspace must be 16-byte aligned");
+  if (n_workgroups < 1) return fail(MLP_ERR_ARG, "n_workgroups must be >= 1");
+  int dev = 0, ncu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+  if (n_workgroups > ncu) return fail(MLP_ERR_ARG, "n_workgroups %d above the %d CUs", n_workgroups, ncu);
+  return mlph::barrier_probe(n_workgroups, rounds, workspace, (hipStream_t)stream, &g_last_error);
+}
+
 }  // extern "C"

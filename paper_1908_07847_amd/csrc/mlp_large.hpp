@@ -22,4 +22,9 @@ mlp_status large_train(const mlp_config &cfg, int n_nets, const float *lrs, cons
                        float *comp, void *ws, size_t ws_bytes, int n_cu, const float *X, const float *T,
                        int epochs, float *loss_hist, hipStream_t s, std::string *err);
 
+// Grid-barrier probe (cooperative launch of n_wg workgroups, `rounds`
+// barriers); ws holds barrier_probe_workspace_bytes() of counters.
+mlp_status barrier_probe(int n_wg, int rounds, void *ws, hipStream_t s, std::string *err);
+size_t barrier_probe_workspace_bytes();
+
 }  // namespace mlph

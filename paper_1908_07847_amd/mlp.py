@@ -298,3 +298,34 @@ class MLPFunction(torch.autograd.Function):
         net: Net = ctx.net
         g, dX, _ = net.backward(X, A, Y, dY=gY.contiguous(), want_dx=ctx.needs_input_grad[1])
         return None, dX, g.W1, g.b1, g.W2, g.b2
+
+
+# ---------------------------------------------------------------- measurement
+def barrier_probe(n_workgroups: int, rounds: int, workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """mlp_barrier_probe: one cooperative launch whose workgroups pass
+    `rounds` grid barriers; returns the workspace (its int32 word 16 is
+    nonzero if a barrier hit its spin limit)."""
+    ws = workspace if workspace is not None else torch.zeros(_lib.BARRIER_PROBE_WS_BYTES // 4, dtype=torch.int32,
+                                                              device="cuda")
+    check(lib.mlp_barrier_probe(int(n_workgroups), int(rounds), _ptr(ws), ws.numel() * ws.element_size(),
+                                _stream(stream)))
+    return ws
+
+
+def barrier_latency_us(n_workgroups: int, rounds: int = 2000) -> float:
+    """Time one grid barrier adds (µs): launches of `rounds` and 2 x `rounds`
+    barriers timed with HIP events on the current stream, differenced."""
+    ws = torch.zeros(_lib.BARRIER_PROBE_WS_BYTES // 4, dtype=torch.int32, device="cuda")
+    barrier_probe(n_workgroups, 10, ws)
+    times = []
+    for r in (rounds, 2 * rounds):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        barrier_probe(n_workgroups, r, ws)
+        e1.record()
+        torch.cuda.synchronize()
+        if int(ws[16].item()) != 0:
+            raise RuntimeError("a probe barrier hit its spin limit")
+        times.append(e0.elapsed_time(e1) * 1e3)
+    return (times[1] - times[0]) / rounds
+

@@ -168,3 +168,14 @@ def test_train_shared_rejects_before_touching_the_device():
     e4 = L.Config(33, 256, 3, 2, 8192, 1024, 0.1, 1)
     assert call(args(cfg=ctypes.byref(e4))) == L.MLP_ERR_UNSUPPORTED   # e4m3 with several nets
     assert call(args(ep=0)) == L.MLP_OK                           # nothing to do, no device work
+
+
+def test_barrier_probe_rejects_before_touching_the_device():
+    L = _lib()
+    call = lambda n=64, r=100, ws=0x10000, nb=L.BARRIER_PROBE_WS_BYTES: L.lib.mlp_barrier_probe(n, r, ws, nb, None)
+    assert call(r=-1) == L.MLP_ERR_ARG
+    assert call(r=1000001) == L.MLP_ERR_ARG
+    assert call(ws=None) == L.MLP_ERR_WORKSPACE
+    assert call(nb=L.BARRIER_PROBE_WS_BYTES - 4) == L.MLP_ERR_WORKSPACE
+    assert call(ws=0x10004) == L.MLP_ERR_ALIGN
+    assert call(n=0) == L.MLP_ERR_ARG

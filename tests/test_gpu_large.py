@@ -279,3 +279,31 @@ def test_two_workgroups_per_cu_grids_keep_parity(M, wl, n, batch, grid, prec, to
     say(f"  workload {wl} {prec} grid {grid}: {errs}")
     assert max(errs.values()) <= tol
     assert float(np.max(np.abs(hist - ref_hist) / ref_hist)) <= tol
+
+
+@pytest.mark.parametrize("n_wg,rounds", [(1, 5), (64, 100), (0, 300)])
+def test_barrier_probe_counts_every_arrival(M, n_wg, rounds):
+    """mlp_barrier_probe: the grid passes every barrier (no spin-limit flag),
+    and the counters hold exact integer totals: G registrations, rounds x G
+    arrivals over the XCD counters, rounds x (XCDs with members) leader
+    arrivals.  n_wg 0 stands for one workgroup per CU."""
+    if n_wg == 0:
+        n_wg = torch.cuda.get_device_properties(0).multi_processor_count
+    say(f"barrier probe: {n_wg} workgroups, {rounds} rounds")
+    ws = M.barrier_probe(n_wg, rounds)
+    torch.cuda.synchronize()
+    c = ws.cpu().numpy().astype(np.int64)
+    assert c[16] == 0
+    assert c[16 * 18] == n_wg
+    members = np.array([c[16 * (10 + x)] for x in range(8)])
+    arrivals = np.array([c[16 * (2 + x)] for x in range(8)])
+    assert members.sum() == n_wg
+    assert np.array_equal(arrivals, members * rounds)
+    assert c[0] == rounds * int((members > 0).sum())
+
+
+def test_barrier_latency_is_measured(M):
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    t = M.barrier_latency_us(n_cu, rounds=500)
+    say(f"grid barrier over {n_cu} workgroups: {t:.2f} us")
+    assert 0.0 < t < 100.0
