@@ -300,6 +300,32 @@ class MLPFunction(torch.autograd.Function):
         return None, dX, g.W1, g.b1, g.W2, g.b2
 
 
+# ---------------------------------------------------------------- accuracy during training
+def accuracy_curve(net: Net, X_tr: torch.Tensor, T_tr: torch.Tensor, X_te: torch.Tensor | None,
+                   T_te: torch.Tensor | None, epochs: int, every: int) -> dict:
+    """Train `net` for `epochs` epochs on X_tr, T_tr in launches of `every`
+    epochs (a resumed run equals one long run bitwise) and after each launch
+    count the correct class predictions (mlp_predict) on the training rows
+    and, if given, the test rows.  Returns numpy arrays: epochs done, loss
+    history [epochs], train_correct, test_correct (or None)."""
+    if every <= 0 or epochs < 0:
+        raise ValueError("every must be positive and epochs >= 0")
+    hist = torch.empty(max(epochs, 1), dtype=torch.float32, device=net.device)
+    done, tr, te = [], [], []
+    e = 0
+    while e < epochs:
+        k = min(every, epochs - e)
+        net.train(X_tr, T_tr, k, loss_hist=hist[e:e + k])
+        e += k
+        done.append(e)
+        tr.append(net.predict(X_tr, T_tr)[2])
+        if X_te is not None:
+            te.append(net.predict(X_te, T_te)[2])
+    return dict(epochs=np.array(done), loss=hist[:epochs].cpu().numpy(),
+                train_correct=np.array([int(v) for v in tr]),
+                test_correct=np.array([int(v) for v in te]) if X_te is not None else None)
+
+
 # ---------------------------------------------------------------- measurement
 def barrier_probe(n_workgroups: int, rounds: int, workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """mlp_barrier_probe: one cooperative launch whose workgroups pass

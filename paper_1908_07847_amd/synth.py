@@ -147,6 +147,19 @@ def single(workload: int, n_rows: int | None = None, hidden: int | None = None, 
                 epochs=c["epochs"], batch=c["batch"], name=c["name"])
 
 
+def train_test_split(w: dict, train_frac: float = 0.75, workload: int = 1, group: int = 0) -> dict:
+    """The paper's split of a dataset into training and test rows (75/25):
+    a seeded permutation, the first round(train_frac * M) rows train and the
+    rest test (60 rows -> 45/15, 120 -> 90/30).  Returns X_tr, T_tr, X_te,
+    T_te and the permutation."""
+    m = w["X"].shape[0]
+    perm = rng(workload, group, ROLE_PERM).permutation(m)
+    n_tr = int(round(train_frac * m))
+    tr, te = np.sort(perm[:n_tr]), np.sort(perm[n_tr:])
+    return dict(X_tr=np.ascontiguousarray(w["X"][tr]), T_tr=np.ascontiguousarray(w["T"][tr]),
+                X_te=np.ascontiguousarray(w["X"][te]), T_te=np.ascontiguousarray(w["T"][te]), perm=perm)
+
+
 def batched(n_nets: int = 4096, seed_workload: int = 3, heldout: bool = False):
     """The batched workload: net i -> group i//5, fold i%5.
 

@@ -89,3 +89,41 @@ def test_predict_single_output(M):
     T = np.ascontiguousarray(w["T"][:, :1])
     cor, _, _ = check_predict(M, net, w["X"], T, th.packed())
     assert cor == 120
+
+
+def _near_tie_rows(Y, margin):
+    s = np.sort(Y, axis=1)
+    return (s[:, -1] - s[:, -2]) < margin
+
+
+@pytest.mark.parametrize("wl", [1, 2])
+def test_accuracy_curve_on_the_75_25_split(M, wl):
+    """Accuracy during training (accuracy_curve): the workload's rows split
+    75/25 by a seeded permutation, trained in launches of 100 epochs with
+    the correct counts on both parts after each launch.  Against the oracle
+    trained to the same epochs: the loss history within 1e-5, and every row
+    whose class differs between the two sits at a near-tie of the oracle's
+    outputs (a float32 / float64 decision)."""
+    w = synth.single(wl)
+    sp = synth.train_test_split(w, workload=wl)
+    n_tr, n_te = sp["X_tr"].shape[0], sp["X_te"].shape[0]
+    assert n_tr + n_te == w["X"].shape[0] and n_tr == int(round(0.75 * w["X"].shape[0]))
+    epochs, every = (1000, 100) if wl == 1 else (2000, 250)
+    say(f"accuracy curve: workload {wl}, {n_tr} train / {n_te} test rows, {epochs} epochs every {every}")
+    net = M.Net(w["D"], w["H"], w["K"], n_tr, lr=w["lr"], theta=w["theta"])
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    cur = M.accuracy_curve(net, dev(sp["X_tr"]), dev(sp["T_tr"]), dev(sp["X_te"]), dev(sp["T_te"]), epochs, every)
+    q = Params.of(w["theta"])
+    ref_hist = []
+    for i, e in enumerate(cur["epochs"]):
+        q, h = oracle.train(sp["X_tr"], sp["T_tr"], q, w["lr"], every)
+        ref_hist.append(h)
+        for part, Xp, Tp, got in (("train", sp["X_tr"], sp["T_tr"], cur["train_correct"][i]),
+                                  ("test", sp["X_te"], sp["T_te"], cur["test_correct"][i])):
+            Y, lab = oracle.predict(Xp, q)
+            ref = int(np.sum(lab == np.argmax(Tp, axis=1)))
+            tie = _near_tie_rows(Y, 1e-4)
+            assert abs(got - ref) <= int(tie.sum()), (e, part, got, ref, int(tie.sum()))
+        say(f"  epoch {e}: train {cur['train_correct'][i]}/{n_tr}, test {cur['test_correct'][i]}/{n_te}")
+    ref_hist = np.concatenate(ref_hist)
+    assert np.max(np.abs(cur["loss"] - ref_hist)) / np.max(np.abs(ref_hist)) <= 1e-5

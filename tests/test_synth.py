@@ -68,3 +68,14 @@ def test_theta_pack_roundtrip():
     th = synth.theta0(7, 5, 3, np.random.default_rng(0))
     back = synth.Theta.unpack(th.packed(), 7, 5, 3)
     assert np.array_equal(back.W1, th.W1) and np.array_equal(back.b2, th.b2)
+
+
+def test_train_test_split_is_a_seeded_75_25_partition():
+    for wl, m, n_tr in ((1, 60, 45), (2, 120, 90)):
+        w = synth.single(wl)
+        a, b = synth.train_test_split(w, workload=wl), synth.train_test_split(w, workload=wl)
+        assert np.array_equal(a["perm"], b["perm"])
+        assert a["X_tr"].shape == (n_tr, 33) and a["X_te"].shape == (m - n_tr, 33)
+        tr, te = np.sort(a["perm"][:n_tr]), np.sort(a["perm"][n_tr:])
+        assert len(set(tr) | set(te)) == m and not set(tr) & set(te)
+        assert np.array_equal(a["X_tr"], w["X"][tr]) and np.array_equal(a["T_te"], w["T"][te])
