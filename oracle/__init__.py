@@ -3,8 +3,9 @@
 TEST INFRASTRUCTURE ONLY.  Only `tests/`, `__graft_entry__.smoke()` and the
 CPU-baseline leg of `bench.py` may import this package.  It shares no code
 with the HIP library: the C sources here (`mlp_oracle.c`,
-`mlp_oracle_lowp.c`) are plain float64 loops written from the paper's
-section 2.2 and Equation 1, compiled with gcc into `liboracle.so`.
+`mlp_oracle_lowp.c`, `mlp_oracle_variants.c`) are plain float64 loops
+written from the paper's section 2.2 and Equation 1, compiled with gcc into
+`liboracle.so`.
 
 Every array argument is converted to float64 here (an exact widening of
 float32 inputs), so the oracle sees exactly the values the GPU sees.
@@ -19,7 +20,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SRCS = [os.path.join(_HERE, "mlp_oracle.c"), os.path.join(_HERE, "mlp_oracle_lowp.c")]
+_SRCS = [os.path.join(_HERE, "mlp_oracle.c"), os.path.join(_HERE, "mlp_oracle_lowp.c"),
+         os.path.join(_HERE, "mlp_oracle_variants.c")]
+VARIANTS_SRC = _SRCS[2]
 _lib = None
 
 
@@ -70,6 +73,10 @@ def _bind(path: str):
     lib.ora_train_lowp.argtypes = [i64, i32, i32, i32, i64, P, P, P, P, P, P, dbl, i32, i32, P,
                                    ctypes.c_void_p, P, P]
     lib.ora_round_array.argtypes = [i32, i32, P, P, i64]
+    if hasattr(lib, "ora_train_var"):
+        lib.ora_train_var.argtypes = [i64, i32, i32, i32, i64, i32, dbl, P, P, P, P, P, P, dbl, i32, P, P]
+        lib.ora_loss_grad_var.argtypes = [i64, i32, i32, i32, i32, P, P, P, P, P, P, P, P, P, P]
+        lib.ora_loss_grad_var.restype = dbl
     return lib
 
 
@@ -256,3 +263,37 @@ def round_array(values, prec: str, scale_exp: int = 0) -> np.ndarray:
     out = np.empty_like(v)
     _load().ora_round_array(PREC[prec], int(scale_exp), _p(v), _p(out), v.size)
     return out.reshape(np.shape(values))
+
+
+# ---------------------------------------------------------------- variants (tanh hidden, momentum)
+ACT = {"sigmoid": 0, "tanh": 1}
+
+
+def train_var(X, T, p: Params, lr: float, epochs: int, batch: int = 0, act: str = "sigmoid", mu: float = 0.0,
+              velocity=None):
+    """Training with the hidden activation `act` ("sigmoid": the paper's,
+    "tanh") and heavy-ball momentum mu (0: the paper's plain descent).
+    Returns (trained Params, loss_hist [epochs], velocity [P] or None); the
+    velocity starts from `velocity` (packed, default zeros) when mu != 0."""
+    X, T = _d(X), _d(T)
+    d, h, k = p.shape
+    q = p.copy()
+    hist = np.zeros(max(epochs, 0))
+    v = None
+    if mu != 0.0:
+        v = np.zeros(d * h + h + h * k + k) if velocity is None else _d(velocity).copy()
+    _load().ora_train_var(X.shape[0], d, h, k, int(batch), ACT[act], float(mu), _p(X), _p(T), _p(q.W1),
+                          _p(q.b1), _p(q.W2), _p(q.b2), float(lr), int(epochs), _p(v) if v is not None else None,
+                          _p(hist))
+    return q, hist, v
+
+
+def loss_grad_var(X, T, p: Params, act: str = "sigmoid"):
+    """(L, gradient Params) with the hidden activation `act`."""
+    X, T = _d(X), _d(T)
+    d, h, k = p.shape
+    g = Params(np.zeros((h, d)), np.zeros(h), np.zeros((k, h)), np.zeros(k))
+    L = _load().ora_loss_grad_var(X.shape[0], d, h, k, ACT[act], _p(X), _p(T), _p(p.W1), _p(p.b1), _p(p.W2),
+                                  _p(p.b2), _p(g.W1), _p(g.b1), _p(g.W2), _p(g.b2))
+    return float(L), g
+
