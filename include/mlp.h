@@ -63,7 +63,14 @@ typedef enum { MLP_FP32 = 0, MLP_BF16 = 1, MLP_FP8_E4M3 = 2 } mlp_precision;
 enum {
   /* Compensated (Kahan) float32 parameter update, using the caller's
    * compensation buffer.  Same update, computed more exactly. */
-  MLP_F_COMPENSATED = 1u
+  MLP_F_COMPENSATED = 1u,
+  /* Hidden neurons apply tanh (derivative 1 - tanh^2) instead of the
+   * sigmoid of Equation 1; the output neurons stay sigmoid.  A variant of
+   * section 2.2's network (the paper's neurons are all sigmoid), honoured by
+   * mlp_forward, mlp_backward, mlp_predict and the full-batch small trainer
+   * of mlp_train; the minibatch / large-shape trainer and mlp_train_shared
+   * return MLP_ERR_UNSUPPORTED for it. */
+  MLP_F_TANH_HIDDEN = 8u
 };
 
 typedef struct {
@@ -98,6 +105,17 @@ mlp_status mlp_init(mlp_net **out /*host out*/, const mlp_config *cfg /*host*/, 
 
 /* Release the handle (host memory only). */
 mlp_status mlp_destroy(mlp_net *net);
+
+/* Heavy-ball momentum for the handle's updates (a variant: section 2.2
+ * trains without momentum, which is mu = 0, the default):
+ *   v <- mu v + g,  theta <- theta - lr v   (compensated like the plain step)
+ * for every parameter, simultaneously.  velocity [P] (device, packed order
+ * W1 | b1 | W2 | b2, 4-byte aligned, caller-owned; zero it before the first
+ * update) carries v across calls, so training a then b epochs equals a+b.
+ * Applies to mlp_step and to the full-batch small trainer of mlp_train; the
+ * minibatch / large-shape trainer returns MLP_ERR_UNSUPPORTED while it is
+ * set.  mu in [0, 1); mu > 0 needs velocity; mu = 0 turns momentum off. */
+mlp_status mlp_set_momentum(mlp_net *net, float mu, float *velocity);
 
 /* Feed-forward pass over n rows (section 2.2, Equation 1):
  * A[n][H] (may be NULL) and Y[n][K] are overwritten.  Any n >= 1. */

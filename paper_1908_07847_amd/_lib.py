@@ -49,11 +49,12 @@ class LaunchHint(ctypes.Structure):
 assert ctypes.sizeof(BatchItem) == 32 and ctypes.sizeof(Config) == 40 and ctypes.sizeof(LaunchHint) == 16
 
 # Every symbol include/mlp.h declares.
+F_COMPENSATED, F_TANH_HIDDEN = 1, 8   # mlp_config flags
 BARRIER_PROBE_WS_BYTES = 2048   # MLP_BARRIER_PROBE_WS_BYTES
 
 SYMBOLS = ["mlp_workspace_size", "mlp_init", "mlp_destroy", "mlp_forward", "mlp_backward", "mlp_step",
            "mlp_train", "mlp_predict", "mlp_train_batched", "mlp_eval_batched", "mlp_shared_workspace_size",
-           "mlp_train_shared", "mlp_barrier_probe",
+           "mlp_train_shared", "mlp_barrier_probe", "mlp_set_momentum",
            "mlp_set_launch_hint", "mlp_status_string", "mlp_last_error"]
 
 
@@ -80,7 +81,8 @@ def _load():
                                      vp, ctypes.c_size_t, vp]
     lib.mlp_set_launch_hint.argtypes = [ctypes.POINTER(LaunchHint)]
     lib.mlp_barrier_probe.argtypes = [i32, i32, vp, ctypes.c_size_t, vp]
-    for name in SYMBOLS[:14]:
+    lib.mlp_set_momentum.argtypes = [vp, f32, vp]
+    for name in SYMBOLS[:15]:
         getattr(lib, name).restype = ctypes.c_int
     lib.mlp_status_string.argtypes = [ctypes.c_int]
     lib.mlp_status_string.restype = ctypes.c_char_p

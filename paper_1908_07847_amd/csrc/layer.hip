@@ -16,7 +16,10 @@
 //  k_backward_sum  one wave per parameter (plus one for the loss): lane
 //                  partial sums over the rows, then a fixed butterfly, so
 //                  the result is bitwise repeatable.
-//  k_step          theta <- theta - lr g, optionally Kahan-compensated.
+//  k_step          theta <- theta - lr g, optionally Kahan-compensated; with
+//                  a velocity buffer, heavy-ball momentum (v <- mu v + g,
+//                  theta <- theta - lr v).  Forward and backward take the
+//                  hidden activation (sigma, or the tanh variant).
 //  k_eval_batched  one workgroup per net of a batched item table: loss and
 //                  correct count of the net on its own rows (e.g. a held-out
 //                  fold), threads over rows, fixed-order block sums
@@ -34,7 +37,7 @@ namespace mlpk {
 
 __global__ __launch_bounds__(256) void k_forward(int64_t n, int D, int H, int K,
                                                  const float *__restrict__ X, mlp_params p,
-                                                 float *__restrict__ A, float *__restrict__ Y) {
+                                                 float *__restrict__ A, float *__restrict__ Y, int act) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   const float *x = X + r * D;
@@ -44,7 +47,8 @@ __global__ __launch_bounds__(256) void k_forward(int64_t n, int D, int H, int K,
     const float *w = p.W1 + (int64_t)h * D;
     float z = p.b1[h];
     for (int d = 0; d < D; ++d) z += x[d] * w[d];
-    float a = sigmoid(z);
+    float slope;
+    const float a = hidden_act(act, z, slope);
     if (A) A[r * H + h] = a;
     for (int k = 0; k < K && k < kLayerMaxOut; ++k) z2[k] += a * p.W2[(int64_t)k * H + h];
   }
@@ -55,8 +59,9 @@ constexpr int kFwdRows = 64, kFwdHB = 64, kFwdMaxD = 256;
 
 typedef float f32x4_l __attribute__((ext_vector_type(4)));
 
-// KO: output slots held per row in registers (K <= KO).
-template <int KO>
+// KO: output slots held per row in registers (K <= KO); ACT: the hidden
+// activation (0 sigma, 1 tanh).
+template <int KO, int ACT>
 __global__ __launch_bounds__(256) void k_forward_tiled(int64_t n, int D, int H, int K,
                                                        const float *__restrict__ X, mlp_params p,
                                                        float *__restrict__ A, float *__restrict__ Y) {
@@ -102,7 +107,8 @@ __global__ __launch_bounds__(256) void k_forward_tiled(int64_t n, int D, int H, 
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int r = wave * 16 + 4 * lg + i;
-        const float a = h < H ? sigmoid(z[i] + b1[hl]) : 0.0f;
+        float slope;
+        const float a = h < H ? hidden_act(ACT, z[i] + b1[hl], slope) : 0.0f;
         if (A && r < rows && h < H) A[(r0 + r) * H + h] = a;
 #pragma unroll
         for (int k = 0; k < KO; ++k)
@@ -127,7 +133,7 @@ __global__ __launch_bounds__(256) void k_backward_rows(
     int64_t n, int64_t n_total, int D, int H, int K, const float *__restrict__ A, const float *__restrict__ Y,
     const float *__restrict__ dY, const float *__restrict__ T, mlp_params p,
     float *__restrict__ dX, float *__restrict__ d1_out, float *__restrict__ d2_out,
-    float *__restrict__ sq_out) {
+    float *__restrict__ sq_out, int act) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   const float mse_scale = 2.0f / ((float)n_total * (float)K);
@@ -149,7 +155,7 @@ __global__ __launch_bounds__(256) void k_backward_rows(
     float s = 0.0f;
     for (int k = 0; k < K; ++k) s += d2_out[r * K + k] * p.W2[(int64_t)k * H + h];
     float a = A[r * H + h];
-    d1_out[r * H + h] = s * a * (1.0f - a);
+    d1_out[r * H + h] = act == 1 ? s * (1.0f - a * a) : s * a * (1.0f - a);
   }
   if (dX) {
     for (int d = 0; d < D; ++d) {
@@ -201,7 +207,8 @@ __global__ __launch_bounds__(256) void k_backward_sum(
 }
 
 __global__ __launch_bounds__(256) void k_step(int D, int H, int K, mlp_params p, mlp_params g,
-                                              float *__restrict__ comp, float lr) {
+                                              float *__restrict__ comp, float lr, float mu,
+                                              float *__restrict__ vel) {
   const int64_t P = (int64_t)D * H + H + (int64_t)H * K + K;
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= P) return;
@@ -213,7 +220,12 @@ __global__ __launch_bounds__(256) void k_step(int D, int H, int K, mlp_params p,
   else if (q < oB2) { w = p.W2 + (q - oW2); gr = g.W2 + (q - oW2); }
   else { w = p.b2 + (q - oB2); gr = g.b2 + (q - oB2); }
   float wv = *w, c = comp ? comp[q] : 0.0f;
-  gd_update(wv, c, lr, *gr, comp != nullptr);
+  float step = *gr;
+  if (vel) {   // heavy-ball momentum: v <- mu v + g, theta <- theta - lr v
+    step = fmaf(mu, vel[q], step);
+    vel[q] = step;
+  }
+  gd_update(wv, c, lr, step, comp != nullptr);
   *w = wv;
   if (comp) comp[q] = c;
 }
@@ -308,25 +320,25 @@ namespace mlph {
 static dim3 grid_for(int64_t n, int b) { return dim3((unsigned)((n + b - 1) / b)); }
 
 hipError_t launch_forward(int64_t n, int D, int H, int K, const float *X, mlp_params p, float *A,
-                          float *Y, hipStream_t s) {
+                          float *Y, int act, hipStream_t s) {
   if (D <= mlpk::kFwdMaxD && K <= mlpk::kLayerMaxOut) {
     const int XS = (D + 3) / 4 * 4 + 1;
     const size_t lds = sizeof(float) * ((size_t)(mlpk::kFwdRows + mlpk::kFwdHB) * XS +
                                         mlpk::kLayerMaxOut * mlpk::kFwdHB + mlpk::kFwdHB);
-    const void *kern = K <= 4 ? (const void *)mlpk::k_forward_tiled<4>
-                              : (const void *)mlpk::k_forward_tiled<mlpk::kLayerMaxOut>;
+    using mlpk::k_forward_tiled;
+    using mlpk::kLayerMaxOut;
+    const void *kern = K <= 4 ? (act ? (const void *)k_forward_tiled<4, 1> : (const void *)k_forward_tiled<4, 0>)
+                              : (act ? (const void *)k_forward_tiled<kLayerMaxOut, 1>
+                                     : (const void *)k_forward_tiled<kLayerMaxOut, 0>);
     hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const int64_t blocks = (n + mlpk::kFwdRows - 1) / mlpk::kFwdRows;
-    if (K <= 4)
-      hipLaunchKernelGGL(mlpk::k_forward_tiled<4>, dim3((unsigned)blocks), dim3(256), lds, s, n, D, H, K, X, p,
-                         A, Y);
-    else
-      hipLaunchKernelGGL(mlpk::k_forward_tiled<mlpk::kLayerMaxOut>, dim3((unsigned)blocks), dim3(256), lds, s, n,
-                         D, H, K, X, p, A, Y);
+    void *args[] = {&n, &D, &H, &K, &X, &p, &A, &Y};
+    e = hipLaunchKernel(kern, dim3((unsigned)blocks), dim3(256), args, lds, s);
+    if (e != hipSuccess) return e;
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(mlpk::k_forward, grid_for(n, 256), dim3(256), 0, s, n, D, H, K, X, p, A, Y);
+  hipLaunchKernelGGL(mlpk::k_forward, grid_for(n, 256), dim3(256), 0, s, n, D, H, K, X, p, A, Y, act);
   return hipGetLastError();
 }
 
@@ -338,8 +350,8 @@ hipError_t launch_eval_batched(const mlp_batch_item *items_dev, int n_nets, int 
 }
 
 hipError_t launch_predict(int64_t n, int D, int H, int K, const float *X, mlp_params p, float *Y,
-                          int32_t *labels, const float *T, int32_t *correct, hipStream_t s) {
-  hipError_t e = launch_forward(n, D, H, K, X, p, nullptr, Y, s);
+                          int32_t *labels, const float *T, int32_t *correct, int act, hipStream_t s) {
+  hipError_t e = launch_forward(n, D, H, K, X, p, nullptr, Y, act, s);
   if (e != hipSuccess) return e;
   if (T) {
     hipLaunchKernelGGL(mlpk::k_fill_i32, dim3(1), dim3(1), 0, s, correct, 0);
@@ -356,7 +368,7 @@ hipError_t launch_predict(int64_t n, int D, int H, int K, const float *X, mlp_pa
 // added to the previous ones in chunk order (fixed, so still repeatable).
 hipError_t launch_backward(int64_t n, int64_t ws_rows, int D, int H, int K, const float *X,
                            const float *A, const float *Y, const float *dY, const float *T,
-                           mlp_params p, mlp_params g, float *dX, float *loss, float *ws,
+                           mlp_params p, mlp_params g, float *dX, float *loss, float *ws, int act,
                            hipStream_t s) {
   const int64_t chunk = std::min<int64_t>(n, ws_rows);
   float *d1 = ws, *d2 = ws + chunk * H, *sq = d2 + chunk * K;
@@ -365,7 +377,7 @@ hipError_t launch_backward(int64_t n, int64_t ws_rows, int D, int H, int K, cons
     const int64_t m = std::min(chunk, n - r0);
     hipLaunchKernelGGL(mlpk::k_backward_rows, grid_for(m, 256), dim3(256), 0, s, m, n, D, H, K,
                        A + r0 * H, Y + r0 * K, dY ? dY + r0 * K : nullptr, T ? T + r0 * K : nullptr,
-                       p, dX ? dX + r0 * D : nullptr, d1, d2, sq);
+                       p, dX ? dX + r0 * D : nullptr, d1, d2, sq, act);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(mlpk::k_backward_sum, grid_for(P + 1, 256 / mlpk::kWave), dim3(256), 0, s, m, n,
@@ -377,10 +389,10 @@ hipError_t launch_backward(int64_t n, int64_t ws_rows, int D, int H, int K, cons
   return hipSuccess;
 }
 
-hipError_t launch_step(int D, int H, int K, mlp_params p, mlp_params g, float *comp, float lr,
-                       hipStream_t s) {
+hipError_t launch_step(int D, int H, int K, mlp_params p, mlp_params g, float *comp, float lr, float mu,
+                       float *vel, hipStream_t s) {
   const int64_t P = (int64_t)D * H + H + (int64_t)H * K + K;
-  hipLaunchKernelGGL(mlpk::k_step, grid_for(P, 256), dim3(256), 0, s, D, H, K, p, g, comp, lr);
+  hipLaunchKernelGGL(mlpk::k_step, grid_for(P, 256), dim3(256), 0, s, D, H, K, p, g, comp, lr, mu, vel);
   return hipGetLastError();
 }
 

@@ -22,6 +22,8 @@ struct mlp_net {
   size_t ws_bytes;
   int device;
   int n_cu;
+  float mu;         // momentum rate (0: plain gradient descent)
+  float *velocity;  // [P] packed, device; null without momentum
 };
 
 namespace {
@@ -60,7 +62,8 @@ mlp_status check_config(const mlp_config *c) {
     return fail(MLP_ERR_SHAPE, "n_in / n_hidden above 2^20");
   if (c->prec != MLP_FP32 && c->prec != MLP_BF16 && c->prec != MLP_FP8_E4M3)
     return fail(MLP_ERR_ARG, "unknown precision %d", c->prec);
-  if (c->flags & ~(uint32_t)MLP_F_COMPENSATED) return fail(MLP_ERR_ARG, "unknown flag bits 0x%x", c->flags);
+  if (c->flags & ~(uint32_t)(MLP_F_COMPENSATED | MLP_F_TANH_HIDDEN))
+    return fail(MLP_ERR_ARG, "unknown flag bits 0x%x", c->flags);
   if (!(c->lr >= 0.0f) || c->lr > 1e6f) return fail(MLP_ERR_ARG, "lr must be finite and >= 0");
   return MLP_OK;
 }
@@ -79,6 +82,8 @@ bool small_path(const mlp_config &c) {
          c.n_hidden <= MLP_SMALL_MAX_HIDDEN && c.n_in <= MLP_SMALL_MAX_IN &&
          c.n_out <= MLP_SMALL_MAX_OUT;
 }
+
+int act_of(const mlp_config &c) { return (c.flags & MLP_F_TANH_HIDDEN) ? 1 : 0; }
 
 size_t backward_ws_bytes(const mlp_config &c) {
   const int64_t rows = std::min<int64_t>(c.n_rows, mlph::kBackwardChunk);
@@ -168,6 +173,8 @@ mlp_status mlp_init(mlp_net **out, const mlp_config *cfg, mlp_params theta, floa
   n->ws_bytes = ws_bytes;
   n->device = dev;
   n->n_cu = ncu;
+  n->mu = 0.0f;
+  n->velocity = nullptr;
   *out = n;
   return MLP_OK;
 }
@@ -185,7 +192,7 @@ mlp_status mlp_forward(mlp_net *net, const float *X, int64_t n, float *A, float 
   if (!aligned16(X) || !aligned4(Y) || (A && !aligned4(A)))
     return fail(MLP_ERR_ALIGN, "X must be 16-byte and A, Y 4-byte aligned");
   const mlp_config &c = net->cfg;
-  hipError_t e = mlph::launch_forward(n, c.n_in, c.n_hidden, c.n_out, X, net->theta, A, Y,
+  hipError_t e = mlph::launch_forward(n, c.n_in, c.n_hidden, c.n_out, X, net->theta, A, Y, act_of(c),
                                       (hipStream_t)stream);
   return e == hipSuccess ? MLP_OK : hip_fail(e, "mlp_forward launch");
 }
@@ -200,7 +207,7 @@ mlp_status mlp_predict(mlp_net *net, const float *X, int64_t n, float *Y, int32_
     return fail(MLP_ERR_ALIGN, "X must be 16-byte and Y, labels, T, correct 4-byte aligned");
   const mlp_config &c = net->cfg;
   hipError_t e = mlph::launch_predict(n, c.n_in, c.n_hidden, c.n_out, X, net->theta, Y, labels, T, correct,
-                                      (hipStream_t)stream);
+                                      act_of(c), (hipStream_t)stream);
   return e == hipSuccess ? MLP_OK : hip_fail(e, "mlp_predict launch");
 }
 
@@ -222,7 +229,7 @@ mlp_status mlp_backward(mlp_net *net, const float *X, const float *A, const floa
     return fail(MLP_ERR_WORKSPACE, "backward needs %zu workspace bytes", backward_ws_bytes(c));
   const int64_t ws_rows = std::min<int64_t>(c.n_rows, mlph::kBackwardChunk);
   hipError_t e = mlph::launch_backward(n, ws_rows, c.n_in, c.n_hidden, c.n_out, X, A, Y, dY, T,
-                                       net->theta, grads, dX, loss, (float *)net->ws,
+                                       net->theta, grads, dX, loss, (float *)net->ws, act_of(c),
                                        (hipStream_t)stream);
   return e == hipSuccess ? MLP_OK : hip_fail(e, "mlp_backward launch");
 }
@@ -233,8 +240,8 @@ mlp_status mlp_step(mlp_net *net, mlp_params grads, float lr, void *stream) {
   if (s != MLP_OK) return s;
   if (!(lr >= 0.0f) || lr > 1e6f) return fail(MLP_ERR_ARG, "lr must be finite and >= 0");
   const mlp_config &c = net->cfg;
-  hipError_t e = mlph::launch_step(c.n_in, c.n_hidden, c.n_out, net->theta, grads, net->comp, lr,
-                                   (hipStream_t)stream);
+  hipError_t e = mlph::launch_step(c.n_in, c.n_hidden, c.n_out, net->theta, grads, net->comp, lr, net->mu,
+                                   net->velocity, (hipStream_t)stream);
   return e == hipSuccess ? MLP_OK : hip_fail(e, "mlp_step launch");
 }
 
@@ -262,12 +269,19 @@ mlp_status mlp_train(mlp_net *net, const float *X, const float *T, int32_t epoch
     one.lr = c.lr;
     one.x_off = 0;
     one.p_off = 0;
+    // the tanh variant runs 8 waves per net (its only instances)
+    const int threads = act_of(c) ? 512 : mlph::small_threads(1, g_hint.small_threads);
+    if (act_of(c) && mlph::small_lds_bytes((int)c.n_rows, (int)H, (int)D, 512, net->velocity != nullptr) >
+                         160 * 1024)
+      return fail(MLP_ERR_UNSUPPORTED, "the tanh variant's 8-wave plan does not fit in LDS at this shape");
     hipError_t e = mlph::launch_small_train(nullptr, one, 1, (int)D, (int)K, (int)c.n_rows, (int)H,
-                                            X, T, p.W1, net->comp, epochs, loss_hist,
-                                            mlph::small_threads(1, g_hint.small_threads),
-                                            (hipStream_t)stream);
+                                            X, T, p.W1, net->comp, epochs, loss_hist, act_of(c), net->mu,
+                                            net->velocity, threads, (hipStream_t)stream);
     return e == hipSuccess ? MLP_OK : hip_fail(e, "mlp_train (small) launch");
   }
+  if (act_of(c) != 0 || net->velocity)
+    return fail(MLP_ERR_UNSUPPORTED, "the large-N trainer (minibatches or large shapes) trains the sigmoid "
+                                     "network without momentum only");
   return mlph::large_train(net->cfg, 1, nullptr, net->theta, net->comp, net->ws, net->ws_bytes, net->n_cu,
                            X, T, epochs, loss_hist, (hipStream_t)stream, &g_last_error);
 }
@@ -313,8 +327,8 @@ mlp_status mlp_train_batched(const mlp_batch_item *items_host, const mlp_batch_i
   }
   mlp_batch_item none{};
   hipError_t e = mlph::launch_small_train(items_dev, none, n_nets, n_in, n_out, max_rows, max_h, X_packed,
-                                          T_packed, theta_packed, comp_packed, epochs, loss_hist,
-                                          mlph::small_threads(n_nets, g_hint.small_threads),
+                                          T_packed, theta_packed, comp_packed, epochs, loss_hist, 0, 0.0f,
+                                          nullptr, mlph::small_threads(n_nets, g_hint.small_threads),
                                           (hipStream_t)stream);
   return e == hipSuccess ? MLP_OK : hip_fail(e, "mlp_train_batched launch");
 }
@@ -375,6 +389,8 @@ mlp_status mlp_train_shared(const mlp_config *cfg, int32_t n_nets, const float *
   if (epochs < 0) return fail(MLP_ERR_ARG, "epochs must be >= 0");
   if (cfg->prec == MLP_FP8_E4M3 && n_nets > 1)
     return fail(MLP_ERR_UNSUPPORTED, "e4m3 operands need n_nets == 1 (per-tensor scales)");
+  if (cfg->flags & MLP_F_TANH_HIDDEN)
+    return fail(MLP_ERR_UNSUPPORTED, "nets sharing X are sigmoid networks");
   if (lr)
     for (int32_t i = 0; i < n_nets; ++i)
       if (!(lr[i] >= 0.0f) || lr[i] > 1e6f) return fail(MLP_ERR_ARG, "net %d: lr must be finite and >= 0", i);
@@ -411,6 +427,16 @@ mlp_status mlp_barrier_probe(int32_t n_workgroups, int32_t rounds, void *workspa
   if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
   if (n_workgroups > ncu) return fail(MLP_ERR_ARG, "n_workgroups %d above the %d CUs", n_workgroups, ncu);
   return mlph::barrier_probe(n_workgroups, rounds, workspace, (hipStream_t)stream, &g_last_error);
+}
+
+mlp_status mlp_set_momentum(mlp_net *net, float mu, float *velocity) {
+  if (!net) return fail(MLP_ERR_ARG, "net is NULL");
+  if (!(mu >= 0.0f) || !(mu < 1.0f)) return fail(MLP_ERR_ARG, "mu must be in [0, 1)");
+  if (mu > 0.0f && !velocity) return fail(MLP_ERR_ARG, "momentum needs a velocity buffer");
+  if (velocity && !aligned4(velocity)) return fail(MLP_ERR_ALIGN, "velocity must be 4-byte aligned");
+  net->mu = mu;
+  net->velocity = mu > 0.0f ? velocity : nullptr;
+  return MLP_OK;
 }
 
 }  // extern "C"

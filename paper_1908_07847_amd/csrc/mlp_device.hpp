@@ -49,6 +49,19 @@ __device__ __forceinline__ float sigmoid_slope(float z, float &slope) {
   return a;
 }
 
+// The tanh hidden activation (a variant; the paper's neurons are sigmoid)
+// and its slope 1 - tanh(z)^2.
+__device__ __forceinline__ float tanh_slope(float z, float &slope) {
+  const float a = tanhf(z);
+  slope = 1.0f - a * a;
+  return a;
+}
+
+// Hidden activation by kind (0: sigma, 1: tanh) and its slope.
+__device__ __forceinline__ float hidden_act(int act, float z, float &slope) {
+  return act == 1 ? tanh_slope(z, slope) : sigmoid_slope(z, slope);
+}
+
 // theta <- theta - lr*g.  With a compensation term c (Kahan summation of the
 // update stream) the low-order bits lost when a small step is added to a
 // larger weight are carried to the next update instead of being dropped.
@@ -102,25 +115,27 @@ constexpr int64_t kBackwardChunk = 16384;
 // Small-network trainer: one workgroup per net, all epochs in one launch.
 // items == nullptr means a single net described by `one`.  threads is 256,
 // 512 or 1024 (small_threads picks it from the net count and a hint).
-size_t small_lds_bytes(int n_rows, int n_hidden, int n_in, int threads);
-size_t small_launch_lds_bytes(int max_rows, int max_hidden, int n_in, int threads);
+size_t small_lds_bytes(int n_rows, int n_hidden, int n_in, int threads, bool momentum = false);
+size_t small_launch_lds_bytes(int max_rows, int max_hidden, int n_in, int threads, bool momentum = false);
 int small_threads(int n_nets, int hint);
+// act: hidden activation (0 sigma, 1 tanh); vel != nullptr: heavy-ball
+// momentum mu with the velocity vel[P] (packed, a single net only).
 hipError_t launch_small_train(const mlp_batch_item *items, mlp_batch_item one, int n_nets,
                               int n_in, int n_out, int max_rows, int max_hidden, const float *X,
                               const float *T, float *theta, float *comp, int epochs,
-                              float *loss_hist, int threads, hipStream_t s);
+                              float *loss_hist, int act, float mu, float *vel, int threads, hipStream_t s);
 
 // Generic layer kernels (any sizes) for mlp_forward / mlp_backward / mlp_step.
 hipError_t launch_forward(int64_t n, int D, int H, int K, const float *X, mlp_params p, float *A,
-                          float *Y, hipStream_t s);
+                          float *Y, int act, hipStream_t s);
 hipError_t launch_backward(int64_t n, int64_t ws_rows, int D, int H, int K, const float *X,
                            const float *A, const float *Y, const float *dY, const float *T,
-                           mlp_params p, mlp_params g, float *dX, float *loss, float *ws,
+                           mlp_params p, mlp_params g, float *dX, float *loss, float *ws, int act,
                            hipStream_t s);
-hipError_t launch_step(int D, int H, int K, mlp_params p, mlp_params g, float *comp, float lr,
-                       hipStream_t s);
+hipError_t launch_step(int D, int H, int K, mlp_params p, mlp_params g, float *comp, float lr, float mu,
+                       float *vel, hipStream_t s);
 hipError_t launch_predict(int64_t n, int D, int H, int K, const float *X, mlp_params p, float *Y,
-                          int32_t *labels, const float *T, int32_t *correct, hipStream_t s);
+                          int32_t *labels, const float *T, int32_t *correct, int act, hipStream_t s);
 hipError_t launch_eval_batched(const mlp_batch_item *items_dev, int n_nets, int D, int K, const float *X,
                                const float *T, const float *theta, float *loss, int32_t *correct, hipStream_t s);
 

@@ -71,15 +71,29 @@ struct SmallLayout {
   __host__ __device__ int dst() const { return ts() + NP * 4; }     // [NW][16][16] a / delta1 staging
   __host__ __device__ int dd() const { return dst() + NW * 256; }   // [NW][16][4] delta2 staging
   __host__ __device__ int part() const { return dd() + NW * 64; }   // [NW][PW] partials
-  __host__ __device__ int total() const { return part() + NW * PW; }
+  __host__ __device__ int vs() const { return part() + NW * PW; }   // [P] velocity (momentum only)
+  __host__ __device__ int total(bool mom = false) const {
+    return vs() + (mom ? (H * (D + 1) + K * H + K + 3) / 4 * 4 : 0);
+  }
+};
+
+// Training variants (the paper's method is act 0 without momentum):
+// hidden activation act (0 sigma, 1 tanh); heavy-ball momentum with rate mu
+// when vel (the velocity [P], packed order, of a single net) is not null.
+struct SmallVariant {
+  int act;
+  float mu;
+  float *vel;
 };
 
 // KO: outputs the output-layer code runs over (K <= KO; 3 covers K <= 3).
-template <int NW, int HTM, int KO>
+// ACT: the hidden activation (0 sigma, 1 tanh), fixed per instance so the
+// paper's sigmoid network carries no branch for the variant.
+template <int NW, int HTM, int KO, int ACT>
 __global__ __launch_bounds__(NW * 64) void k_small_train(
     const mlp_batch_item *__restrict__ items, mlp_batch_item one, int D, int K,
     const float *__restrict__ X, const float *__restrict__ T, float *__restrict__ theta,
-    float *__restrict__ comp, int epochs, float *__restrict__ loss_hist) {
+    float *__restrict__ comp, int epochs, float *__restrict__ loss_hist, SmallVariant var) {
   constexpr int NT = NW * 64;
   constexpr int PMAX = 48 * 64 + 64 + 64 * 4 + 4;   // largest parameter count
   constexpr int JM = (PMAX + NT - 1) / NT;          // parameters per thread
@@ -130,25 +144,25 @@ __global__ __launch_bounds__(NW * 64) void k_small_train(
   }
   if (tid < 4) b2s[tid] = tid < K ? P[oB2 + tid] : 0.0f;
   // Kahan terms of the parameters this thread updates (q = tid + j*NT)
+  // packed offset of parameter q (update order)
+  auto packed = [&](int q) {
+    if (q < H * D1) {
+      const int h = q / D1, d = q - h * D1;
+      return d < D ? h * D + d : oB1 + h;
+    }
+    if (q < H * D1 + K * H) return oW2 + (q - H * D1);
+    return oB2 + (q - H * D1 - K * H);
+  };
   float ccomp[JM];
 #pragma unroll
   for (int j = 0; j < JM; ++j) {
     const int q = tid + j * NT;
-    float c = 0.0f;
-    if (compensated && q < nP) {
-      int o;
-      if (q < H * D1) {
-        const int h = q / D1, d = q - h * D1;
-        o = d < D ? h * D + d : oB1 + h;
-      } else if (q < H * D1 + K * H) {
-        o = oW2 + (q - H * D1);
-      } else {
-        o = oB2 + (q - H * D1 - K * H);
-      }
-      c = Cp[o];
-    }
-    ccomp[j] = c;
+    ccomp[j] = (compensated && q < nP) ? Cp[packed(q)] : 0.0f;
   }
+  // momentum: the velocity lives in LDS in update order for the whole run
+  float *Vs = sm + L.vs();
+  if (var.vel)
+    for (int q = tid; q < nP; q += NT) Vs[q] = var.vel[packed(q)];
   // LDS offsets of parameter q (update order): its partial within a wave's
   // block and its master copy.  Kept packed in registers across epochs when
   // a thread owns few parameters.
@@ -214,7 +228,7 @@ __global__ __launch_bounds__(NW * 64) void k_small_train(
           for (int k0 = 0; k0 < DK; k0 += 4)
             z = __builtin_amdgcn_mfma_f32_16x16x4f32(wb[k0], xa[k0], z, 0, 0, 0);
 #pragma unroll
-          for (int i = 0; i < 4; ++i) av[ht][i] = sigmoid_slope(z[i], sl[ht][i]);
+          for (int i = 0; i < 4; ++i) av[ht][i] = hidden_act(ACT, z[i], sl[ht][i]);
         }
       }
       // output layer: each lane's share of z2 (its 4 hidden units per tile)
@@ -333,8 +347,12 @@ __global__ __launch_bounds__(NW * 64) void k_small_train(
       for (int j = 0; j < JM; ++j) {
         if (tid + j * NT < nP) {
           const int mo = uofs[j] & 0xffff;
-          float wv = sm[mo];
-          gd_update(wv, ccomp[j], lr, gs[j], compensated);
+          float wv = sm[mo], g = gs[j];
+          if (var.vel) {   // heavy-ball momentum: v <- mu v + g, step along v
+            g = fmaf(var.mu, Vs[tid + j * NT], g);
+            Vs[tid + j * NT] = g;
+          }
+          gd_update(wv, ccomp[j], lr, g, compensated);
           sm[mo] = wv;
         }
       }
@@ -347,6 +365,10 @@ __global__ __launch_bounds__(NW * 64) void k_small_train(
           offsets(q, po, mo);
           float g = 0.0f;
           for (int w = 0; w < NW; ++w) g += Part[w * PW + po];
+          if (var.vel) {
+            g = fmaf(var.mu, Vs[q], g);
+            Vs[q] = g;
+          }
           float wv = sm[mo];
           gd_update(wv, ccomp[j], lr, g, compensated);
           sm[mo] = wv;
@@ -380,48 +402,51 @@ __global__ __launch_bounds__(NW * 64) void k_small_train(
       if (compensated) Cp[o] = ccomp[j];
     }
   }
+  if (var.vel)
+    for (int q = tid; q < nP; q += NT) var.vel[packed(q)] = Vs[q];
 }
 
-template <int NW, int HTM, int KO>
+template <int NW, int HTM, int KO, int ACT>
 hipError_t launch_one(const mlp_batch_item *items, mlp_batch_item one, int n_nets, int n_in,
                       int n_out, size_t lds, const float *X, const float *T, float *theta,
-                      float *comp, int epochs, float *loss_hist, hipStream_t s) {
-  auto kern = k_small_train<NW, HTM, KO>;
+                      float *comp, int epochs, float *loss_hist, SmallVariant var, hipStream_t s) {
+  auto kern = k_small_train<NW, HTM, KO, ACT>;
   hipError_t e = hipFuncSetAttribute((const void *)kern,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(n_nets), dim3(NW * 64), lds, s, items, one, n_in, n_out, X, T,
-                     theta, comp, epochs, loss_hist);
+                     theta, comp, epochs, loss_hist, var);
   return hipGetLastError();
 }
 
-template <int NW>
+template <int NW, int ACT>
 hipError_t launch_nw(int max_hidden, const mlp_batch_item *items, mlp_batch_item one, int n_nets,
                      int n_in, int n_out, size_t lds, const float *X, const float *T,
-                     float *theta, float *comp, int epochs, float *loss_hist, hipStream_t s) {
+                     float *theta, float *comp, int epochs, float *loss_hist, SmallVariant var,
+                     hipStream_t s) {
   // registers are sized for the widest hidden layer of the launch
   const int ht = (max_hidden + 15) / 16;
   if (n_out <= 3) {
     if (ht <= 1)
-      return launch_one<NW, 1, 3>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs, loss_hist, s);
+      return launch_one<NW, 1, 3, ACT>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs, loss_hist, var, s);
     if (ht <= 2)
-      return launch_one<NW, 2, 3>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs, loss_hist, s);
-    return launch_one<NW, 4, 3>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs, loss_hist, s);
+      return launch_one<NW, 2, 3, ACT>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs, loss_hist, var, s);
+    return launch_one<NW, 4, 3, ACT>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs, loss_hist, var, s);
   }
   if (ht <= 1)
-    return launch_one<NW, 1, 4>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs, loss_hist, s);
+    return launch_one<NW, 1, 4, ACT>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs, loss_hist, var, s);
   if (ht <= 2)
-    return launch_one<NW, 2, 4>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs, loss_hist, s);
-  return launch_one<NW, 4, 4>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs, loss_hist, s);
+    return launch_one<NW, 2, 4, ACT>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs, loss_hist, var, s);
+  return launch_one<NW, 4, 4, ACT>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs, loss_hist, var, s);
 }
 
 }  // namespace mlpk
 
 namespace mlph {
 
-size_t small_lds_bytes(int n_rows, int n_hidden, int n_in, int threads) {
+size_t small_lds_bytes(int n_rows, int n_hidden, int n_in, int threads, bool momentum) {
   mlpk::SmallLayout L(n_rows, n_hidden, n_in, 4, threads / 64);
-  return sizeof(float) * (size_t)L.total();
+  return sizeof(float) * (size_t)L.total(momentum);
 }
 
 int small_threads(int n_nets, int hint) {
@@ -429,27 +454,36 @@ int small_threads(int n_nets, int hint) {
   return n_nets <= 64 ? 512 : 128;
 }
 
-size_t small_launch_lds_bytes(int max_rows, int max_hidden, int n_in, int threads) {
+size_t small_launch_lds_bytes(int max_rows, int max_hidden, int n_in, int threads, bool momentum) {
   // the layout grows monotonically with N and H
-  return small_lds_bytes(max_rows, max_hidden, n_in, threads);
+  return small_lds_bytes(max_rows, max_hidden, n_in, threads, momentum);
 }
 
 hipError_t launch_small_train(const mlp_batch_item *items, mlp_batch_item one, int n_nets,
                               int n_in, int n_out, int max_rows, int max_hidden, const float *X,
                               const float *T, float *theta, float *comp, int epochs,
-                              float *loss_hist, int threads, hipStream_t s) {
+                              float *loss_hist, int act, float mu, float *vel, int threads, hipStream_t s) {
+  const mlpk::SmallVariant var{act, mu, vel};
+  const bool mom = vel != nullptr;
   // fewer waves when the per-wave partial buffers would not fit in LDS
-  while (threads > 128 && small_launch_lds_bytes(max_rows, max_hidden, n_in, threads) > 160 * 1024)
+  while (threads > 128 && small_launch_lds_bytes(max_rows, max_hidden, n_in, threads, mom) > 160 * 1024)
     threads /= 2;
-  const size_t lds = small_launch_lds_bytes(max_rows, max_hidden, n_in, threads);
+  const size_t lds = small_launch_lds_bytes(max_rows, max_hidden, n_in, threads, mom);
+  if (act == 1) {
+    // the tanh variant is instantiated for 8 waves only; the host API
+    // checks that its LDS plan fits before launching
+    if (threads != 512) return hipErrorInvalidValue;
+    return mlpk::launch_nw<8, 1>(max_hidden, items, one, n_nets, n_in, n_out, lds, X, T, theta, comp,
+                                 epochs, loss_hist, var, s);
+  }
   if (threads == 512)
-    return mlpk::launch_nw<8>(max_hidden, items, one, n_nets, n_in, n_out, lds, X, T, theta, comp,
-                              epochs, loss_hist, s);
+    return mlpk::launch_nw<8, 0>(max_hidden, items, one, n_nets, n_in, n_out, lds, X, T, theta, comp,
+                                 epochs, loss_hist, var, s);
   if (threads == 256)
-    return mlpk::launch_nw<4>(max_hidden, items, one, n_nets, n_in, n_out, lds, X, T, theta, comp,
-                              epochs, loss_hist, s);
-  return mlpk::launch_nw<2>(max_hidden, items, one, n_nets, n_in, n_out, lds, X, T, theta, comp,
-                            epochs, loss_hist, s);
+    return mlpk::launch_nw<4, 0>(max_hidden, items, one, n_nets, n_in, n_out, lds, X, T, theta, comp,
+                                 epochs, loss_hist, var, s);
+  return mlpk::launch_nw<2, 0>(max_hidden, items, one, n_nets, n_in, n_out, lds, X, T, theta, comp,
+                               epochs, loss_hist, var, s);
 }
 
 }  // namespace mlph

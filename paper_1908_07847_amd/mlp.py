@@ -68,7 +68,10 @@ class Net:
 
     def __init__(self, n_in: int, n_hidden: int, n_out: int, n_rows: int, *, batch: int = 0,
                  lr: float = 0.1, prec: str = "fp32", compensated: bool = True, theta=None,
-                 device="cuda"):
+                 act: str = "sigmoid", momentum: float = 0.0, device="cuda"):
+        """act: the hidden activation, "sigmoid" (the paper's) or "tanh";
+        momentum: heavy-ball rate mu (0, the paper's plain descent), with a
+        zeroed velocity buffer `self.velocity` owned by the net."""
         self.D, self.H, self.K = int(n_in), int(n_hidden), int(n_out)
         self.n_rows, self.batch, self.lr, self.prec = int(n_rows), int(batch), float(lr), prec
         self.device = torch.device(device)
@@ -80,8 +83,11 @@ class Net:
             self.flat.zero_()
         self.W1, self.b1, self.W2, self.b2 = split_packed(self.flat, self.D, self.H, self.K)
         self.comp = torch.zeros(max(P, 4), dtype=torch.float32, device=self.device)[:P] if compensated else None
-        self.cfg = Config(self.D, self.H, self.K, _lib.PREC[prec], self.n_rows, self.batch, self.lr,
-                          _lib.MLP_F_COMPENSATED if compensated else 0)
+        if act not in ("sigmoid", "tanh"):
+            raise ValueError(f"unknown hidden activation {act!r}")
+        self.act = act
+        flags = (_lib.MLP_F_COMPENSATED if compensated else 0) | (_lib.F_TANH_HIDDEN if act == "tanh" else 0)
+        self.cfg = Config(self.D, self.H, self.K, _lib.PREC[prec], self.n_rows, self.batch, self.lr, flags)
         nbytes = ctypes.c_size_t(0)
         check(lib.mlp_workspace_size(ctypes.byref(self.cfg), ctypes.byref(nbytes)))
         self.ws_bytes = int(nbytes.value)
@@ -90,6 +96,20 @@ class Net:
         check(lib.mlp_init(ctypes.byref(h), ctypes.byref(self.cfg), self.params_c(), _ptr(self.comp),
                            _ptr(self.ws), self.ws_bytes))
         self._h = h
+        self.velocity = None
+        if momentum:
+            self.set_momentum(momentum)
+
+    def set_momentum(self, mu: float, velocity: torch.Tensor | None = None) -> None:
+        """mlp_set_momentum: heavy-ball momentum mu for mlp_step / mlp_train
+        (0 turns it off).  The velocity starts at zero unless given."""
+        if mu > 0:
+            P = self.flat.numel()
+            self.velocity = velocity if velocity is not None else torch.zeros(max(P, 4), dtype=torch.float32,
+                                                                                device=self.device)[:P]
+        else:
+            self.velocity = None
+        check(lib.mlp_set_momentum(self._h, float(mu), _ptr(self.velocity)))
 
     def __del__(self):
         h = getattr(self, "_h", None)

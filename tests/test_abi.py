@@ -55,7 +55,7 @@ def test_workspace_size_and_config_validation():
     for c in bad:
         assert _ws(c)[0] == L.MLP_ERR_SHAPE
     assert _ws(L.Config(33, 16, 3, 7, 120, 0, 0.1, 1))[0] == L.MLP_ERR_ARG        # precision
-    assert _ws(L.Config(33, 16, 3, 0, 120, 0, 0.1, 8))[0] == L.MLP_ERR_ARG        # flags
+    assert _ws(L.Config(33, 16, 3, 0, 120, 0, 0.1, 16))[0] == L.MLP_ERR_ARG       # unknown flag bit
     assert _ws(L.Config(33, 16, 3, 0, 120, 0, float("nan"), 1))[0] == L.MLP_ERR_ARG
     assert L.lib.mlp_workspace_size(None, None) == L.MLP_ERR_ARG
     assert b"NULL" in L.lib.mlp_last_error()
@@ -179,3 +179,13 @@ def test_barrier_probe_rejects_before_touching_the_device():
     assert call(nb=L.BARRIER_PROBE_WS_BYTES - 4) == L.MLP_ERR_WORKSPACE
     assert call(ws=0x10004) == L.MLP_ERR_ALIGN
     assert call(n=0) == L.MLP_ERR_ARG
+
+
+def test_variant_flag_and_momentum_arguments():
+    L = _lib()
+    n = ctypes.c_size_t(0)
+    ok = L.Config(33, 16, 3, 0, 120, 0, 0.1, L.MLP_F_COMPENSATED | L.F_TANH_HIDDEN)
+    assert L.lib.mlp_workspace_size(ctypes.byref(ok), ctypes.byref(n)) == L.MLP_OK
+    bad = L.Config(33, 16, 3, 0, 120, 0, 0.1, 16)
+    assert L.lib.mlp_workspace_size(ctypes.byref(bad), ctypes.byref(n)) == L.MLP_ERR_ARG
+    assert L.lib.mlp_set_momentum(None, 0.9, 0x1000) == L.MLP_ERR_ARG
