@@ -153,7 +153,10 @@ def bench_single(args):
     D, H, K, N = w["D"], w["H"], w["K"], w["X"].shape[0]
     batch = w["batch"] or N
     prec = args.prec if wl in (4, 5) else "fp32"
-    net = mlp.Net(D, H, K, N, batch=w["batch"], lr=w["lr"], prec=prec, theta=w["theta"])
+    act, mu = args.act, args.momentum
+    if (act != "sigmoid" or mu) and wl not in (1, 2):
+        raise SystemExit("--act tanh / --momentum apply to the full-batch workloads w1 and w2")
+    net = mlp.Net(D, H, K, N, batch=w["batch"], lr=w["lr"], prec=prec, theta=w["theta"], act=act, momentum=mu)
     X = torch.from_numpy(w["X"]).cuda()
     T = torch.from_numpy(w["T"]).cuda()
     steps = args.steps if args.steps is not None else w["epochs"]
@@ -192,9 +195,11 @@ def bench_single(args):
     res = dict(
         metric="training samples*epochs/s", value=N * steps / wall, unit="samples*epochs/s",
         ms_per_step=wall * 1e3 / steps, dtype={"fp32": "f32", "bf16": "bf16", "e4m3": "e4m3"}[prec],
-        config={"workload": names[wl] + ", sigmoid both layers, MSE, GD lr=0.1", "n_rows": N, "n_in": D,
+        config={"workload": names[wl] + (", sigmoid both layers" if act == "sigmoid" else
+                                         ", tanh hidden / sigmoid output (variant)") + ", MSE, " +
+                    ("GD lr=0.1" if not mu else f"heavy-ball momentum {mu}, lr={w['lr']} (variant)"), "n_rows": N, "n_in": D,
                 "n_hidden": H, "n_out": K, "batch": batch, "lr": w["lr"], "compensated_update": True,
-                "operand_precision": prec, "step": "one epoch"},
+                "operand_precision": prec, "hidden_activation": act, "momentum": mu, "step": "one epoch"},
         roofline={"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
                   "traffic": measured_traffic(tkey, kind), "traffic_unit": "bytes per launch", "kernel": kname,
                   "kernel_ms": kern * 1e3, "flops_per_launch": flops},
@@ -202,7 +207,7 @@ def bench_single(args):
     if wl in (4, 5):
         res["roofline"]["sync_adjusted"] = sync_adjusted(mlp, torch, flops, peak, N * steps * (D + K) * 4.0,
                                                          steps * (-(-N // batch)), kern)
-    return res, dict(w=w, wl=wl, batch=batch)
+    return res, dict(w=w, wl=wl, batch=batch, act=act, mu=mu)
 
 
 def cpu_single(ctx, budget_s: float):
@@ -219,7 +224,10 @@ def cpu_single(ctx, budget_s: float):
     reps, t_total = 0, 0.0
     while (t_total < budget_s or reps == 0) and reps < 100000:
         t0 = time.perf_counter()
-        oracle.train(X, T, p, w["lr"], epochs, batch=0 if wl in (1, 2) else batch)
+        if ctx.get("act", "sigmoid") != "sigmoid" or ctx.get("mu", 0.0):
+            oracle.train_var(X, T, p, w["lr"], epochs, act=ctx["act"], mu=ctx["mu"])
+        else:
+            oracle.train(X, T, p, w["lr"], epochs, batch=0 if wl in (1, 2) else batch)
         t_total += time.perf_counter() - t0
         reps += 1
     return {"value": rows * epochs * reps / t_total, "unit": "samples*epochs/s", "cores": 1, "kind": "oracle",
@@ -527,6 +535,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="w2", choices=["w1", "w2", "w2a", "w3", "w4", "w5", "w6", "p4"])
     ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16", "e4m3"])
+    ap.add_argument("--act", default="sigmoid", choices=["sigmoid", "tanh"],
+                    help="hidden activation (w1, w2; tanh is a variant of the paper's sigmoid)")
+    ap.add_argument("--momentum", type=float, default=0.0, help="heavy-ball rate (w1, w2; 0 = the paper's GD)")
     ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="only run a 1 GiB device copy (counter scale)")
