@@ -148,11 +148,13 @@ mlp_status mlp_train(mlp_net *net, const float *X, const float *T, int32_t epoch
 /* Class predictions: the network outputs Y = sigma(sigma(X W1^T + b1) W2^T
  * + b2) of section 2.2 read as a class, the index of the largest output
  * (the lowest index on ties), as in the paper's evaluation of the trained
- * network.  X [n][D]; Y [n][K] (out, the outputs themselves); labels [n]
- * (out, int32).  With one-hot targets T [n][K] (may be NULL), correct [1]
- * (out, int32, device) receives the number of rows whose class equals the
- * target's (argmax of T with the same rule); correct must be non-NULL iff T
- * is.  Uses the parameters bound to net; X 16-byte aligned, the rest 4. */
+ * network; with one output (K = 1, the two-class good/poor-control
+ * reading) class 1 when the output is above 1/2, else 0.  X [n][D]; Y [n][K]
+ * (out, the outputs themselves); labels [n] (out, int32).  With targets
+ * T [n][K] (one-hot, or 0/1 for K = 1; may be NULL), correct [1] (out,
+ * int32, device) receives the number of rows whose class equals the
+ * target's (same rule applied to T); correct must be non-NULL iff T is.
+ * Uses the parameters bound to net; X 16-byte aligned, the rest 4. */
 mlp_status mlp_predict(mlp_net *net, const float *X, int64_t n, float *Y, int32_t *labels,
                        const float *T, int32_t *correct, void *stream);
 

@@ -146,13 +146,22 @@ def forward(X, p: Params):
     return A, Y
 
 
+def classes(V) -> np.ndarray:
+    """Class of each row of outputs (or one-hot / 0-1 targets) V [n][K]: the
+    index of the largest entry, the lowest index on ties (np.argmax returns
+    the first maximum); with a single output (K = 1, a two-class net) class 1
+    when the entry is above 1/2, else 0."""
+    V = np.asarray(V)
+    if V.shape[1] == 1:
+        return (V[:, 0] > 0.5).astype(np.int32)
+    return np.argmax(V, axis=1).astype(np.int32)
+
+
 def predict(X, p: Params):
-    """(Y, labels): the outputs of the forward pass and, per row, the index of
-    the largest output with the lowest index on ties -- the trained network's
-    class (section 2.2's network read as a classifier; np.argmax returns the
-    first maximum)."""
+    """(Y, labels): the outputs of the forward pass and each row's class
+    (section 2.2's network read as a classifier; see `classes`)."""
     _, Y = forward(X, p)
-    return Y, np.argmax(Y, axis=1).astype(np.int32)
+    return Y, classes(Y)
 
 
 def evaluate(X, T, p: Params):
@@ -160,7 +169,7 @@ def evaluate(X, T, p: Params):
     squared error over rows and outputs) and the number of rows whose class
     (first maximum of the outputs) equals the target's."""
     Y, lab = predict(X, p)
-    return mse(Y, T), int(np.sum(lab == np.argmax(_d(T), axis=1)))
+    return mse(Y, T), int(np.sum(lab == classes(_d(T))))
 
 
 def mse(Y, T) -> float:

@@ -236,7 +236,10 @@ namespace mlpk {
 
 __global__ void k_fill_i32(int32_t *p, int32_t v) { *p = v; }
 
+// Class of a row of outputs (or targets): the largest entry, the lowest
+// index on ties; a single output is a two-class net, class 1 above 1/2.
 __device__ __forceinline__ int argmax_row(const float *v, int K) {
+  if (K == 1) return v[0] > 0.5f ? 1 : 0;
   int best = 0;
   for (int k = 1; k < K; ++k)
     if (v[k] > v[best]) best = k;   // strict: the lowest index wins ties

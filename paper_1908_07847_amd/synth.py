@@ -147,6 +147,13 @@ def single(workload: int, n_rows: int | None = None, hidden: int | None = None, 
                 epochs=c["epochs"], batch=c["batch"], name=c["name"])
 
 
+def binary_targets(w: dict) -> np.ndarray:
+    """The two-class reading of the targets: one output, 1 for the top class
+    (HbA1c at or above the paper's 6.5 % threshold: poor glucose control),
+    0 otherwise; shape [N][1], float32."""
+    return (w["classes"] == 2).astype(np.float32)[:, None].copy()
+
+
 def train_test_split(w: dict, train_frac: float = 0.75, workload: int = 1, group: int = 0) -> dict:
     """The paper's split of a dataset into training and test rows (75/25):
     a seeded permutation, the first round(train_frac * M) rows train and the

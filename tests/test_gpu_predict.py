@@ -37,8 +37,8 @@ def check_predict(M, net, X, T, th_flat):
     torch.cuda.synchronize()
     Y, lab, cor = Y.cpu().numpy(), lab.cpu().numpy(), int(cor.cpu().numpy()[0])
     # the decision on the kernel's own float32 outputs is exact
-    assert np.array_equal(lab, np.argmax(Y, axis=1))
-    assert cor == int(np.sum(lab == np.argmax(T, axis=1)))
+    assert np.array_equal(lab, oracle.classes(Y))
+    assert cor == int(np.sum(lab == oracle.classes(T)))
     p = Params.of(synth.Theta.unpack(th_flat, d, h, k))
     Yr, labr = oracle.predict(X, p)
     err = float(np.max(np.abs(Y - Yr)))
@@ -46,8 +46,11 @@ def check_predict(M, net, X, T, th_flat):
     # where the oracle's class differs, its top two outputs are within the output error
     diff = np.nonzero(lab != labr)[0]
     for r in diff:
-        top = np.sort(Yr[r])[-2:]
-        assert top[1] - top[0] <= 4 * err + 1e-7, (r, Yr[r])
+        if k == 1:   # one output: the decision is its side of 1/2
+            assert abs(Yr[r, 0] - 0.5) <= 4 * err + 1e-7, (r, Yr[r])
+        else:
+            top = np.sort(Yr[r])[-2:]
+            assert top[1] - top[0] <= 4 * err + 1e-7, (r, Yr[r])
     return cor, len(diff), err
 
 
@@ -82,13 +85,24 @@ def test_predict_ties_go_to_the_lowest_index(M):
     assert np.all(lab.cpu().numpy() == 0)
 
 
-def test_predict_single_output(M):
+def test_binary_output_trains_and_predicts(M):
+    """The two-class reading (one sigmoid output: HbA1c at or above 6.5 %,
+    poor control, or not) on workload 2's rows: the fused trainer against the
+    oracle for 5000 epochs, then the predictions (class 1 above 1/2)."""
     w = synth.single(2)
+    T1 = synth.binary_targets(w)
     th = synth.Theta(w["theta"].W1, w["theta"].b1, w["theta"].W2[:1].copy(), w["theta"].b2[:1].copy())
     net = net_for(M, th, 120)
-    T = np.ascontiguousarray(w["T"][:, :1])
-    cor, _, _ = check_predict(M, net, w["X"], T, th.packed())
-    assert cor == 120
+    hist = net.train(torch.from_numpy(w["X"]).cuda(), torch.from_numpy(T1).cuda(), w["epochs"])
+    torch.cuda.synchronize()
+    q, ref_hist = oracle.train(w["X"], T1, Params.of(th), 0.1, w["epochs"])
+    flat = net.flat.cpu().numpy()
+    e = float(np.max(np.abs(flat - q.flat())) / np.max(np.abs(q.flat())))
+    lerr = float(np.max(np.abs(hist.cpu().numpy() - ref_hist)) / np.max(ref_hist))
+    assert e <= 1e-5 and lerr <= 1e-5, (e, lerr)
+    cor, nd, err = check_predict(M, net, w["X"], T1, flat)
+    say(f"  binary reading: {int(T1.sum())} positive rows, {cor}/120 correct after {w['epochs']} epochs, "
+        f"{nd} near-threshold differences, parameter error {e:.1e}")
 
 
 def _near_tie_rows(Y, margin):

@@ -345,8 +345,12 @@ def test_predict_is_the_first_maximum_of_the_outputs():
     tie = Params(p.W1, p.b1, np.zeros((3, 5)), np.array([0.2, 0.7, 0.7]))
     _, lab = oracle.predict(X, tie)
     assert np.all(lab == 1)
+    # one output (the two-class reading: poor control or not): class 1 above 1/2
     one = Params(p.W1, p.b1, p.W2[:1], p.b2[:1])
-    assert np.all(oracle.predict(X, one)[1] == 0)
+    Y1, lab1 = oracle.predict(X, one)
+    assert np.array_equal(lab1, np.array([1 if y > 0.5 else 0 for y in Y1[:, 0]]))
+    lo = Params(p.W1, p.b1, np.zeros((1, 5)), np.array([0.0]))     # every output exactly 1/2
+    assert np.all(oracle.predict(X, lo)[1] == 0)
 
 
 def test_evaluate_is_the_loss_and_a_count_of_matching_classes():
@@ -359,3 +363,9 @@ def test_evaluate_is_the_loss_and_a_count_of_matching_classes():
     Y = sig(sig(X @ p.W1.T + p.b1) @ p.W2.T + p.b2)
     assert abs(loss - np.mean((Y - T) ** 2)) <= 1e-15
     assert correct == sum(int(np.argmax(Y[r]) == np.argmax(T[r])) for r in range(40))
+
+
+def test_classes_of_one_output_threshold_at_one_half():
+    V = np.array([[0.2], [0.5], [0.5000001], [0.99]])
+    assert oracle.classes(V).tolist() == [0, 0, 1, 1]
+    assert oracle.classes(np.array([[0.1, 0.7, 0.7], [0.3, 0.2, 0.1]])).tolist() == [1, 0]
