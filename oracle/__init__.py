@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY.  Only `tests/`, `__graft_entry__.smoke()` and the
 CPU-baseline leg of `bench.py` may import this package.  It shares no code
 with the HIP library: the C sources here (`mlp_oracle.c`,
-`mlp_oracle_lowp.c`, `mlp_oracle_variants.c`) are plain float64 loops
+`mlp_oracle_lowp.c`, `mlp_oracle_variants.c`, `mlp_oracle_deep.c`) are plain float64 loops
 written from the paper's section 2.2 and Equation 1, compiled with gcc into
 `liboracle.so`.
 
@@ -21,8 +21,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 _SRCS = [os.path.join(_HERE, "mlp_oracle.c"), os.path.join(_HERE, "mlp_oracle_lowp.c"),
-         os.path.join(_HERE, "mlp_oracle_variants.c")]
+         os.path.join(_HERE, "mlp_oracle_variants.c"), os.path.join(_HERE, "mlp_oracle_deep.c")]
 VARIANTS_SRC = _SRCS[2]
+DEEP_SRC = _SRCS[3]
 _lib = None
 
 
@@ -77,6 +78,11 @@ def _bind(path: str):
         lib.ora_train_var.argtypes = [i64, i32, i32, i32, i64, i32, dbl, P, P, P, P, P, P, dbl, i32, P, P]
         lib.ora_loss_grad_var.argtypes = [i64, i32, i32, i32, i32, P, P, P, P, P, P, P, P, P, P]
         lib.ora_loss_grad_var.restype = dbl
+    if hasattr(lib, "ora_deep_train"):
+        vp = ctypes.c_void_p
+        lib.ora_deep_loss_grad.argtypes = [i64, i32, vp, i32, P, P, P, P]
+        lib.ora_deep_loss_grad.restype = dbl
+        lib.ora_deep_train.argtypes = [i64, i32, vp, i32, P, P, P, dbl, i32, P]
     return lib
 
 
@@ -305,4 +311,31 @@ def loss_grad_var(X, T, p: Params, act: str = "sigmoid"):
     L = _load().ora_loss_grad_var(X.shape[0], d, h, k, ACT[act], _p(X), _p(T), _p(p.W1), _p(p.b1), _p(p.W2),
                                   _p(p.b2), _p(g.W1), _p(g.b1), _p(g.W2), _p(g.b2))
     return float(L), g
+
+
+# ---------------------------------------------------------------- deeper nets
+def deep_n_params(widths) -> int:
+    return int(sum(widths[l + 1] * widths[l] + widths[l + 1] for l in range(len(widths) - 1)))
+
+
+def deep_loss_grad(X, T, widths, theta, act: str = "sigmoid"):
+    """(L, gradient [P]) of an L-layer network: widths [w0 .. wL], parameters
+    packed layer by layer (W_l [w(l+1)][w(l)], then b_l)."""
+    X, T, th = _d(X), _d(T), _d(theta)
+    w = np.ascontiguousarray(widths, dtype=np.int32)
+    g = np.zeros(deep_n_params(widths))
+    L = _load().ora_deep_loss_grad(X.shape[0], len(widths) - 1, w.ctypes.data, ACT[act], _p(X), _p(T), _p(th),
+                                   _p(g))
+    return float(L), g
+
+
+def deep_train(X, T, widths, theta, lr: float, epochs: int, act: str = "sigmoid"):
+    """Full-batch training of an L-layer network; returns (theta, loss_hist)."""
+    X, T = _d(X), _d(T)
+    th = _d(theta).copy()
+    w = np.ascontiguousarray(widths, dtype=np.int32)
+    hist = np.zeros(max(epochs, 0))
+    _load().ora_deep_train(X.shape[0], len(widths) - 1, w.ctypes.data, ACT[act], _p(X), _p(T), _p(th), float(lr),
+                           int(epochs), _p(hist))
+    return th, hist
 
