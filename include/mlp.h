@@ -233,6 +233,29 @@ mlp_status mlp_train_shared(const mlp_config *cfg /*host*/, int32_t n_nets, cons
                             const float *X, const float *T, float *theta, float *comp, int32_t epochs,
                             float *loss_hist, void *workspace, size_t ws_bytes, void *stream);
 
+/* ---- networks with several hidden layers ----------------------------------- */
+
+/* One fully connected layer of a deeper network (section 2.2's layer,
+ * stacked; the paper's network has one hidden layer):
+ *   Y = act(X W^T + b),  X [n][d_in], W [d_out][d_in], b [d_out], Y [n][d_out]
+ * act 0: the sigmoid of Equation 1; 1: tanh.  n >= 1; d_in, d_out in
+ * 1 .. 65536.  Device pointers, 4-byte aligned. */
+mlp_status mlp_dense_forward(const float *X, int64_t n, int32_t d_in, int32_t d_out, const float *W,
+                             const float *b, int32_t act, float *Y, void *stream);
+
+/* Adjoint of mlp_dense_forward from dY = dL/dY [n][d_out] and the layer's
+ * own output Y:  dZ = dY . act'(Y),  gW = dZ^T X,  gb = sum over rows of dZ,
+ * dX = dZ W (dX may be NULL).  gW [d_out][d_in], gb [d_out] are
+ * overwritten; row sums run in a fixed order (bitwise repeatable).
+ * workspace: >= n * d_out * 4 bytes (dZ), 4-byte aligned. */
+mlp_status mlp_dense_backward(const float *X, const float *Y, const float *dY, int64_t n, int32_t d_in,
+                              int32_t d_out, const float *W, int32_t act, float *gW, float *gb, float *dX,
+                              void *workspace, size_t ws_bytes, void *stream);
+
+/* theta <- theta - lr g over P packed parameters (any network), Kahan-
+ * compensated with comp [P] when comp is not NULL. */
+mlp_status mlp_update(float *theta, const float *grad, float *comp, int64_t P, float lr, void *stream);
+
 /* ---- measurement ---------------------------------------------------------- */
 
 /* Bytes of workspace mlp_barrier_probe needs. */

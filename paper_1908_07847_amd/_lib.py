@@ -54,7 +54,8 @@ BARRIER_PROBE_WS_BYTES = 2048   # MLP_BARRIER_PROBE_WS_BYTES
 
 SYMBOLS = ["mlp_workspace_size", "mlp_init", "mlp_destroy", "mlp_forward", "mlp_backward", "mlp_step",
            "mlp_train", "mlp_predict", "mlp_train_batched", "mlp_eval_batched", "mlp_shared_workspace_size",
-           "mlp_train_shared", "mlp_barrier_probe", "mlp_set_momentum",
+           "mlp_train_shared", "mlp_barrier_probe", "mlp_set_momentum", "mlp_dense_forward", "mlp_dense_backward",
+           "mlp_update",
            "mlp_set_launch_hint", "mlp_status_string", "mlp_last_error"]
 
 
@@ -82,7 +83,10 @@ def _load():
     lib.mlp_set_launch_hint.argtypes = [ctypes.POINTER(LaunchHint)]
     lib.mlp_barrier_probe.argtypes = [i32, i32, vp, ctypes.c_size_t, vp]
     lib.mlp_set_momentum.argtypes = [vp, f32, vp]
-    for name in SYMBOLS[:15]:
+    lib.mlp_dense_forward.argtypes = [vp, i64, i32, i32, vp, vp, i32, vp, vp]
+    lib.mlp_dense_backward.argtypes = [vp, vp, vp, i64, i32, i32, vp, i32, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.mlp_update.argtypes = [vp, vp, vp, i64, f32, vp]
+    for name in SYMBOLS[:18]:
         getattr(lib, name).restype = ctypes.c_int
     lib.mlp_status_string.argtypes = [ctypes.c_int]
     lib.mlp_status_string.restype = ctypes.c_char_p

@@ -439,4 +439,44 @@ mlp_status mlp_set_momentum(mlp_net *net, float mu, float *velocity) {
   return MLP_OK;
 }
 
+mlp_status mlp_dense_forward(const float *X, int64_t n, int32_t d_in, int32_t d_out, const float *W,
+                             const float *b, int32_t act, float *Y, void *stream) {
+  if (!X || !W || !b || !Y) return fail(MLP_ERR_ARG, "X, W, b and Y must not be NULL");
+  if (n <= 0 || d_in <= 0 || d_out <= 0 || d_in > 65536 || d_out > 65536)
+    return fail(MLP_ERR_SHAPE, "n >= 1 and d_in, d_out in 1 .. 65536 required");
+  if (act != 0 && act != 1) return fail(MLP_ERR_ARG, "act must be 0 (sigmoid) or 1 (tanh)");
+  if (!aligned4(X) || !aligned4(W) || !aligned4(b) || !aligned4(Y))
+    return fail(MLP_ERR_ALIGN, "device pointers must be 4-byte aligned");
+  hipError_t e = mlph::launch_dense_forward(n, d_in, d_out, X, W, b, act, Y, (hipStream_t)stream);
+  return e == hipSuccess ? MLP_OK : hip_fail(e, "mlp_dense_forward launch");
+}
+
+mlp_status mlp_dense_backward(const float *X, const float *Y, const float *dY, int64_t n, int32_t d_in,
+                              int32_t d_out, const float *W, int32_t act, float *gW, float *gb, float *dX,
+                              void *workspace, size_t ws_bytes, void *stream) {
+  if (!X || !Y || !dY || !W || !gW || !gb) return fail(MLP_ERR_ARG, "X, Y, dY, W, gW and gb must not be NULL");
+  if (n <= 0 || d_in <= 0 || d_out <= 0 || d_in > 65536 || d_out > 65536)
+    return fail(MLP_ERR_SHAPE, "n >= 1 and d_in, d_out in 1 .. 65536 required");
+  if (act != 0 && act != 1) return fail(MLP_ERR_ARG, "act must be 0 (sigmoid) or 1 (tanh)");
+  const void *ptrs[] = {X, Y, dY, W, gW, gb, dX, workspace};
+  for (const void *p : ptrs)
+    if (p && !aligned4(p)) return fail(MLP_ERR_ALIGN, "device pointers must be 4-byte aligned");
+  const size_t need = sizeof(float) * (size_t)n * (size_t)d_out;
+  if (!workspace || ws_bytes < need)
+    return fail(MLP_ERR_WORKSPACE, "workspace of %zu bytes given, %zu needed", workspace ? ws_bytes : 0, need);
+  hipError_t e = mlph::launch_dense_backward(n, d_in, d_out, X, Y, dY, W, act, gW, gb, dX,
+                                             static_cast<float *>(workspace), (hipStream_t)stream);
+  return e == hipSuccess ? MLP_OK : hip_fail(e, "mlp_dense_backward launch");
+}
+
+mlp_status mlp_update(float *theta, const float *grad, float *comp, int64_t P, float lr, void *stream) {
+  if (!theta || !grad) return fail(MLP_ERR_ARG, "theta and grad must not be NULL");
+  if (P <= 0) return fail(MLP_ERR_SHAPE, "P must be positive");
+  if (!(lr >= 0.0f) || lr > 1e6f) return fail(MLP_ERR_ARG, "lr must be finite and >= 0");
+  if (!aligned4(theta) || !aligned4(grad) || (comp && !aligned4(comp)))
+    return fail(MLP_ERR_ALIGN, "device pointers must be 4-byte aligned");
+  hipError_t e = mlph::launch_update(P, theta, grad, comp, lr, (hipStream_t)stream);
+  return e == hipSuccess ? MLP_OK : hip_fail(e, "mlp_update launch");
+}
+
 }  // extern "C"

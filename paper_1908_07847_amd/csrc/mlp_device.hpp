@@ -136,6 +136,13 @@ hipError_t launch_step(int D, int H, int K, mlp_params p, mlp_params g, float *c
                        float *vel, hipStream_t s);
 hipError_t launch_predict(int64_t n, int D, int H, int K, const float *X, mlp_params p, float *Y,
                           int32_t *labels, const float *T, int32_t *correct, int act, hipStream_t s);
+// One dense layer (several-hidden-layer networks) and a packed update.
+hipError_t launch_dense_forward(int64_t n, int din, int dout, const float *X, const float *W, const float *b,
+                                int act, float *Y, hipStream_t s);
+hipError_t launch_dense_backward(int64_t n, int din, int dout, const float *X, const float *Y, const float *dY,
+                                 const float *W, int act, float *gW, float *gb, float *dX, float *dZ,
+                                 hipStream_t s);
+hipError_t launch_update(int64_t P, float *theta, const float *g, float *comp, float lr, hipStream_t s);
 hipError_t launch_eval_batched(const mlp_batch_item *items_dev, int n_nets, int D, int K, const float *X,
                                const float *T, const float *theta, float *loss, int32_t *correct, hipStream_t s);
 

@@ -375,3 +375,96 @@ def barrier_latency_us(n_workgroups: int, rounds: int = 2000) -> float:
         times.append(e0.elapsed_time(e1) * 1e3)
     return (times[1] - times[0]) / rounds
 
+
+
+# ---------------------------------------------------------------- networks with several hidden layers
+class DenseFunction(torch.autograd.Function):
+    """Y = act(X W^T + b) (mlp_dense_forward, act 0 sigmoid / 1 tanh) with the
+    hand-written adjoint (mlp_dense_backward).  When gradient buffers are
+    given, the parameter gradients are written into them (views of a packed
+    gradient vector) and returned as they are."""
+
+    @staticmethod
+    def forward(ctx, X, W, b, act: int, gW_buf=None, gb_buf=None):
+        X = X.contiguous()
+        n, din = X.shape
+        dout = W.shape[0]
+        Y = torch.empty((n, dout), dtype=torch.float32, device=X.device)
+        check(lib.mlp_dense_forward(_ptr(X), n, din, dout, _ptr(W), _ptr(b), int(act), _ptr(Y), _stream()))
+        ctx.save_for_backward(X, W, Y)
+        ctx.act, ctx.bufs = int(act), (gW_buf, gb_buf)
+        return Y
+
+    @staticmethod
+    def backward(ctx, gY):
+        X, W, Y = ctx.saved_tensors
+        gY = gY.contiguous()
+        n, din = X.shape
+        dout = W.shape[0]
+        gW = ctx.bufs[0] if ctx.bufs[0] is not None else torch.empty_like(W)
+        gb = ctx.bufs[1] if ctx.bufs[1] is not None else torch.empty(dout, dtype=torch.float32, device=X.device)
+        dX = torch.empty_like(X) if ctx.needs_input_grad[0] else None
+        ws = torch.empty(max(n * dout, 4), dtype=torch.float32, device=X.device)
+        check(lib.mlp_dense_backward(_ptr(X), _ptr(Y), _ptr(gY), n, din, dout, _ptr(W), ctx.act, _ptr(gW), _ptr(gb),
+                                     _ptr(dX), _ptr(ws), ws.numel() * 4, _stream()))
+        return dX, gW, gb, None, None, None
+
+
+def deep_n_params(widths) -> int:
+    return int(sum(widths[l + 1] * widths[l] + widths[l + 1] for l in range(len(widths) - 1)))
+
+
+class DeepNet:
+    """A network with several hidden layers (section 2.2's network stacked):
+    widths [D, h1, ..., K]; hidden layers apply `act` ("sigmoid" or "tanh"),
+    the output layer the sigmoid; parameters packed layer by layer (W_l
+    [w(l+1)][w(l)], then b_l) in `flat`.  Trained full batch through
+    DenseFunction and torch.autograd (torch's mean squared error), the
+    gradients landing in the packed `grad`, and mlp_update."""
+
+    def __init__(self, widths, theta=None, act: str = "sigmoid", lr: float = 0.1, compensated: bool = True,
+                 device="cuda"):
+        if len(widths) < 2 or act not in ("sigmoid", "tanh"):
+            raise ValueError("widths needs at least an input and an output width; act sigmoid or tanh")
+        self.widths, self.act, self.lr = [int(v) for v in widths], act, float(lr)
+        self.device = torch.device(device)
+        P = deep_n_params(self.widths)
+        self.flat = _aligned_empty(P, self.device)
+        if theta is not None:
+            self.flat.copy_(torch.as_tensor(np.asarray(theta, dtype=np.float32)))
+        else:
+            self.flat.zero_()
+        self.grad = _aligned_empty(P, self.device)
+        self.comp = torch.zeros(max(P, 4), dtype=torch.float32, device=self.device)[:P] if compensated else None
+        self.layers, self.grads = [], []
+        o = 0
+        for l in range(len(self.widths) - 1):
+            din, dout = self.widths[l], self.widths[l + 1]
+            W, gW = self.flat[o:o + dout * din].view(dout, din), self.grad[o:o + dout * din].view(dout, din)
+            o += dout * din
+            b, gb = self.flat[o:o + dout], self.grad[o:o + dout]
+            o += dout
+            W.requires_grad_(True)
+            b.requires_grad_(True)
+            self.layers.append((W, b))
+            self.grads.append((gW, gb))
+        self.params = [t for wb in self.layers for t in wb]
+
+    def forward(self, X: torch.Tensor) -> torch.Tensor:
+        a = X
+        L = len(self.layers)
+        for l, ((W, b), (gW, gb)) in enumerate(zip(self.layers, self.grads)):
+            act = 1 if (self.act == "tanh" and l < L - 1) else 0
+            a = DenseFunction.apply(a, W, b, act, gW, gb)
+        return a
+
+    def train(self, X: torch.Tensor, T: torch.Tensor, epochs: int, loss_hist: torch.Tensor | None = None):
+        hist = loss_hist if loss_hist is not None else torch.empty(max(epochs, 1), dtype=torch.float32,
+                                                                     device=self.device)
+        P = self.flat.numel()
+        for e in range(epochs):
+            loss = torch.nn.functional.mse_loss(self.forward(X), T)
+            torch.autograd.grad(loss, self.params)   # the adjoint writes the packed gradient
+            check(lib.mlp_update(_ptr(self.flat), _ptr(self.grad), _ptr(self.comp), P, self.lr, _stream()))
+            hist[e:e + 1].copy_(loss.detach())
+        return hist[:epochs]

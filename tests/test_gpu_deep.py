@@ -1,0 +1,72 @@
+"""Networks with several hidden layers on the GPU: the dense layer
+(mlp_dense_forward / mlp_dense_backward) against float64 on the host at
+ragged sizes, and DeepNet training (the layers composed by torch.autograd,
+mlp_update) against the FP64 oracle's L-layer training."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1908_07847_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def M():
+    from paper_1908_07847_amd import mlp
+    return mlp
+
+
+def normwise(got, ref):
+    got, ref = np.asarray(got, np.float64).ravel(), np.asarray(ref, np.float64).ravel()
+    return float(np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-30))
+
+
+@pytest.mark.parametrize("n,din,dout,act", [(1, 1, 1, 0), (77, 33, 50, 1), (300, 70, 130, 0), (4096, 33, 256, 1)])
+def test_dense_layer_forward_and_backward(M, n, din, dout, act):
+    g = np.random.default_rng(n + din)
+    X = g.normal(size=(n, din)).astype(np.float32)
+    W = g.uniform(-0.5, 0.5, (dout, din)).astype(np.float32)
+    b = g.uniform(-0.5, 0.5, dout).astype(np.float32)
+    dY = g.normal(size=(n, dout)).astype(np.float32)
+    Xd = torch.from_numpy(X).cuda().requires_grad_(True)
+    Wd = torch.from_numpy(W).cuda().requires_grad_(True)
+    bd = torch.from_numpy(b).cuda().requires_grad_(True)
+    Y = M.DenseFunction.apply(Xd, Wd, bd, act)
+    dX, gW, gb = torch.autograd.grad(Y, [Xd, Wd, bd], torch.from_numpy(dY).cuda())
+    torch.cuda.synchronize()
+    Z = X.astype(np.float64) @ W.T.astype(np.float64) + b
+    Yr = np.tanh(Z) if act == 1 else 1 / (1 + np.exp(-Z))
+    dZ = dY * ((1 - Yr * Yr) if act == 1 else Yr * (1 - Yr))
+    # float32 contraction of din terms: |dz| <= din u sum|x w| (u = 2^-24); act' <= 1
+    zbound = (din + 1) * 2.0 ** -24 * float(np.max(np.abs(X) @ np.abs(W).T + np.abs(b)))
+    assert float(np.max(np.abs(Y.detach().cpu().numpy() - Yr))) <= zbound + 1e-7
+    assert normwise(gW.cpu().numpy(), dZ.T @ X) <= 1e-5
+    assert normwise(gb.cpu().numpy(), dZ.sum(axis=0)) <= 1e-5
+    assert normwise(dX.cpu().numpy(), dZ @ W) <= 1e-5
+
+
+@pytest.mark.parametrize("widths,act,epochs", [([33, 16, 3], "sigmoid", 2000), ([33, 24, 12, 3], "tanh", 1000),
+                                               ([33, 16, 16, 3], "sigmoid", 1000), ([33, 20, 10, 6, 1], "tanh", 500)])
+def test_deep_net_training_matches_the_oracle(M, widths, act, epochs):
+    w = synth.single(2)
+    T = w["T"] if widths[-1] == 3 else synth.binary_targets(w)
+    g = np.random.default_rng(len(widths))
+    theta = g.uniform(-0.5, 0.5, oracle.deep_n_params(widths)).astype(np.float32)
+    say(f"deep net {widths} hidden {act}: {epochs} epochs on workload 2's rows")
+    net = M.DeepNet(widths, theta=theta, act=act)
+    hist = net.train(torch.from_numpy(w["X"]).cuda(), torch.from_numpy(T).cuda(), epochs)
+    torch.cuda.synchronize()
+    q, ref_hist = oracle.deep_train(w["X"], T, widths, theta, 0.1, epochs, act=act)
+    e = normwise(net.flat.detach().cpu().numpy(), q)
+    lerr = normwise(hist.cpu().numpy(), ref_hist)
+    say(f"  params {e:.2e}  loss history {lerr:.2e}  final loss {ref_hist[-1]:.4f}")
+    assert e <= 1e-5 and lerr <= 1e-5
