@@ -14,6 +14,8 @@ Workloads (all synthetic, from the seeded generator):
   w5   4,194,304 x 64, 64-1024-3, minibatch 16384             step = 1 epoch (256 minibatches)
   w6   64 nets of w5's shape sharing its X (grid of 8 learning rates x 8 initialisations)
                                                                step = 1 epoch of every net
+  w2d  w2's rows through a network with two hidden layers (33-16-16-3), the dense
+       layer kernels composed by torch.autograd     step = 1 epoch
   w2a  w2 through the differentiation path: per epoch MLPFunction (forward
        kernel), torch's MSE, the hand-written adjoint (backward kernels) and
        mlp_step, launched from Python                 step = 1 epoch
@@ -417,6 +419,67 @@ def cpu_shared(ctx, budget_s: float):
                       f"float64, single thread, {cpu_info()}", "seconds": t_total}
 
 
+# ---------------------------------------------------------------- several hidden layers (w2d)
+DEEP_WIDTHS = [33, 16, 16, 3]
+
+
+def bench_deep(args):
+    import torch
+    from paper_1908_07847_amd import mlp, synth
+
+    w = synth.single(2)
+    widths, N = DEEP_WIDTHS, w["X"].shape[0]
+    theta = np.random.default_rng(2).uniform(-0.5, 0.5, mlp.deep_n_params(widths)).astype(np.float32)
+    net = mlp.DeepNet(widths, theta=theta, act=args.act)
+    X = torch.from_numpy(w["X"]).cuda()
+    T = torch.from_numpy(w["T"]).cuda()
+    steps = args.steps if args.steps is not None else 1000
+    warmup = args.warmup if args.warmup is not None else 20
+    hist = torch.empty(max(steps, warmup, 1), device="cuda")
+    net.train(X, T, warmup, loss_hist=hist)
+    net.flat.detach().copy_(torch.from_numpy(theta))
+    stream = torch.cuda.current_stream()
+    wall, kern = timed(lambda: net.train(X, T, steps, loss_hist=hist), stream)
+    # per sample-epoch: forward 2 w(l) w(l+1) + activation, backward 4 w(l) w(l+1) (gW and dX; dX skipped for
+    # the first layer), plus the update 2P per epoch
+    P = mlp.deep_n_params(widths)
+    f = 0
+    for l in range(len(widths) - 1):
+        f += 2 * widths[l] * widths[l + 1] + 2 * widths[l] * widths[l + 1] + (2 * widths[l] * widths[l + 1] if l else 0)
+        f += 4 * widths[l + 1]
+    flops = f * N * steps + 2 * P * steps
+    achieved = flops / kern / 1e12
+    res = dict(
+        metric="training samples*epochs/s", value=N * steps / wall, unit="samples*epochs/s",
+        ms_per_step=wall * 1e3 / steps, dtype="f32",
+        config={"workload": f"several hidden layers: N=120 x 33, {'-'.join(map(str, widths))}, full batch, hidden "
+                            f"{args.act}, sigmoid output, MSE, GD lr=0.1; dense-layer kernels composed by torch.autograd "
+                            "(launched from Python per layer and epoch)", "n_rows": N, "widths": widths,
+                "step": "one epoch"},
+        roofline={"bound": "alu", "achieved": achieved, "peak": PEAK["fp32"], "unit": "TFLOP/s",
+                  "frac": achieved / PEAK["fp32"], "traffic": None, "traffic_unit": "bytes per launch",
+                  "kernel": "mlpk::k_dense_fwd + k_dense_dz + k_dense_wsum + k_dense_dx + k_update + torch's loss "
+                            "(per epoch)", "kernel_ms": kern * 1e3, "flops_per_launch": flops},
+        final_loss=float(hist[steps - 1].item()) if steps else None, steps=steps, warmup=warmup)
+    return res, dict(w=w, theta=theta, widths=widths, act=args.act)
+
+
+def cpu_deep(ctx, budget_s: float):
+    import oracle
+    w = ctx["w"]
+    epochs = 200
+    reps, t_total = 0, 0.0
+    while (t_total < budget_s or reps == 0) and reps < 100000:
+        t0 = time.perf_counter()
+        oracle.deep_train(w["X"], w["T"], ctx["widths"], ctx["theta"], 0.1, epochs, act=ctx["act"])
+        t_total += time.perf_counter() - t0
+        reps += 1
+    rows = w["X"].shape[0]
+    return {"value": rows * epochs * reps / t_total, "unit": "samples*epochs/s", "cores": 1, "kind": "oracle",
+            "sample": f"{rows} rows x {epochs} epochs, run {reps} time(s), float64, single thread, {cpu_info()}",
+            "seconds": t_total}
+
+
 # ---------------------------------------------------------------- differentiation path (w2a)
 def bench_autograd(args):
     import torch
@@ -533,7 +596,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the workload's epochs)")
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="w2", choices=["w1", "w2", "w2a", "w3", "w4", "w5", "w6", "p4"])
+    ap.add_argument("--workload", default="w2", choices=["w1", "w2", "w2a", "w2d", "w3", "w4", "w5", "w6", "p4"])
     ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16", "e4m3"])
     ap.add_argument("--act", default="sigmoid", choices=["sigmoid", "tanh"],
                     help="hidden activation (w1, w2; tanh is a variant of the paper's sigmoid)")
@@ -552,6 +615,9 @@ def main():
     if args.workload == "w3":
         res, ctx = bench_batched(args)
         cpu = None if args.no_cpu else cpu_batched(ctx, args.cpu_budget)
+    elif args.workload == "w2d":
+        res, ctx = bench_deep(args)
+        cpu = None if args.no_cpu else cpu_deep(ctx, args.cpu_budget)
     elif args.workload == "w2a":
         res, ctx = bench_autograd(args)
         cpu = None if args.no_cpu else cpu_single(ctx, args.cpu_budget)
