@@ -435,11 +435,25 @@ def bench_deep(args):
     T = torch.from_numpy(w["T"]).cuda()
     steps = args.steps if args.steps is not None else 1000
     warmup = args.warmup if args.warmup is not None else 20
+    G = 50   # epochs per captured graph
+    if steps % G:
+        raise SystemExit(f"w2d: --steps must be a multiple of {G}")
     hist = torch.empty(max(steps, warmup, 1), device="cuda")
-    net.train(X, T, warmup, loss_hist=hist)
-    net.flat.detach().copy_(torch.from_numpy(theta))
     stream = torch.cuda.current_stream()
-    wall, kern = timed(lambda: net.train(X, T, steps, loss_hist=hist), stream)
+    # reference form: torch.autograd over DenseFunction, launched from Python
+    net.train(X, T, warmup, loss_hist=hist)
+    ag_epochs = min(steps, 200)
+    awall, _ = timed(lambda: net.train(X, T, ag_epochs, loss_hist=hist), stream)
+    # timed form: the fused epoch (library calls only) replayed from a HIP graph of G epochs
+    net.flat.detach().copy_(torch.from_numpy(theta))
+    net.comp.zero_()
+    graph = mlp.DeepGraph(net, X, T, G)
+
+    def run():
+        for r in range(steps // G):
+            graph.replay()
+            hist[r * G:(r + 1) * G].copy_(graph.loss)
+    wall, kern = timed(run, stream)
     # per sample-epoch: forward 2 w(l) w(l+1) + activation, backward 4 w(l) w(l+1) (gW and dX; dX skipped for
     # the first layer), plus the update 2P per epoch
     P = mlp.deep_n_params(widths)
@@ -453,12 +467,14 @@ def bench_deep(args):
         metric="training samples*epochs/s", value=N * steps / wall, unit="samples*epochs/s",
         ms_per_step=wall * 1e3 / steps, dtype="f32",
         config={"workload": f"several hidden layers: N=120 x 33, {'-'.join(map(str, widths))}, full batch, hidden "
-                            f"{args.act}, sigmoid output, MSE, GD lr=0.1; dense-layer kernels composed by torch.autograd "
-                            "(launched from Python per layer and epoch)", "n_rows": N, "widths": widths,
-                "step": "one epoch"},
+                            f"{args.act}, sigmoid output, MSE, GD lr=0.1; per epoch the dense-layer forward, the "
+                            "squared-error gradient, the dense-layer adjoints and the update, replayed from a HIP "
+                            f"graph of {G} epochs", "n_rows": N, "widths": widths, "step": "one epoch"},
+        autograd={"value": N * ag_epochs / awall, "ms_per_step": awall * 1e3 / ag_epochs, "epochs": ag_epochs,
+                  "form": "DenseFunction layers composed by torch.autograd, launched from Python"},
         roofline={"bound": "alu", "achieved": achieved, "peak": PEAK["fp32"], "unit": "TFLOP/s",
                   "frac": achieved / PEAK["fp32"], "traffic": None, "traffic_unit": "bytes per launch",
-                  "kernel": "mlpk::k_dense_fwd + k_dense_dz + k_dense_wsum + k_dense_dx + k_update + torch's loss "
+                  "kernel": "mlpk::k_dense_fwd + k_mse_grad + k_dense_dz + k_dense_wsum + k_dense_dx + k_update "
                             "(per epoch)", "kernel_ms": kern * 1e3, "flops_per_launch": flops},
         final_loss=float(hist[steps - 1].item()) if steps else None, steps=steps, warmup=warmup)
     return res, dict(w=w, theta=theta, widths=widths, act=args.act)

@@ -256,6 +256,13 @@ mlp_status mlp_dense_backward(const float *X, const float *Y, const float *dY, i
  * compensated with comp [P] when comp is not NULL. */
 mlp_status mlp_update(float *theta, const float *grad, float *comp, int64_t P, float lr, void *stream);
 
+/* The error of section 2.2 as the mean squared error of outputs Y [n][K]
+ * against targets T [n][K]: loss[0] = sum (Y-T)^2 / (n K) (loss may be NULL)
+ * and dY = dL/dY = 2 (Y-T) / (n K) [n][K].  One workgroup, fixed summation
+ * order; n K <= 2^26. */
+mlp_status mlp_mse_grad(const float *Y, const float *T, int64_t n, int32_t k, float *dY, float *loss,
+                        void *stream);
+
 /* ---- measurement ---------------------------------------------------------- */
 
 /* Bytes of workspace mlp_barrier_probe needs. */

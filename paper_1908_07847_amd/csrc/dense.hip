@@ -12,6 +12,10 @@
 //   k_dense_dx        dX[r][i] = sum_o dZ[r][o] W[o][i], one thread per entry
 //   k_update          theta <- theta - lr g over a packed parameter vector,
 //                     optionally Kahan-compensated
+//   k_mse_grad        the error of section 2.2 read as the mean squared error,
+//                     L = sum (Y-T)^2 / (n K), and dL/dY = 2 (Y-T) / (n K); one
+//                     workgroup, threads strided over the entries, a fixed-order
+//                     block sum (bitwise repeatable)
 // ACT: 0 the sigmoid of Equation 1, 1 tanh.
 #include "mlp_device.hpp"
 
@@ -123,6 +127,26 @@ __global__ __launch_bounds__(256) void k_update(int64_t P, float *__restrict__ t
   if (comp) comp[q] = c;
 }
 
+__global__ __launch_bounds__(1024) void k_mse_grad(int64_t m, float scale, const float *__restrict__ Y,
+                                                   const float *__restrict__ T, float *__restrict__ dY,
+                                                   float *__restrict__ loss) {
+  __shared__ float part[16];
+  float s = 0.0f;
+  for (int64_t q = threadIdx.x; q < m; q += blockDim.x) {
+    const float e = Y[q] - T[q];
+    s = fmaf(e, e, s);
+    dY[q] = 2.0f * e * scale;
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.0f;
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) t += part[w];
+    if (loss) loss[0] = t * scale;
+  }
+}
+
 }  // namespace mlpk
 
 namespace mlph {
@@ -157,6 +181,12 @@ hipError_t launch_dense_backward(int64_t n, int din, int dout, const float *X, c
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_mse_grad(int64_t n, int k, const float *Y, const float *T, float *dY, float *loss, hipStream_t s) {
+  const int64_t m = n * k;
+  hipLaunchKernelGGL(mlpk::k_mse_grad, dim3(1), dim3(1024), 0, s, m, 1.0f / ((float)n * (float)k), Y, T, dY, loss);
+  return hipGetLastError();
 }
 
 hipError_t launch_update(int64_t P, float *theta, const float *g, float *comp, float lr, hipStream_t s) {

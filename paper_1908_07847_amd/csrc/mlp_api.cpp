@@ -479,4 +479,14 @@ mlp_status mlp_update(float *theta, const float *grad, float *comp, int64_t P, f
   return e == hipSuccess ? MLP_OK : hip_fail(e, "mlp_update launch");
 }
 
+mlp_status mlp_mse_grad(const float *Y, const float *T, int64_t n, int32_t k, float *dY, float *loss,
+                        void *stream) {
+  if (!Y || !T || !dY) return fail(MLP_ERR_ARG, "Y, T and dY must not be NULL");
+  if (n <= 0 || k <= 0 || n * (int64_t)k > ((int64_t)1 << 26)) return fail(MLP_ERR_SHAPE, "need n, k >= 1, n k <= 2^26");
+  if (!aligned4(Y) || !aligned4(T) || !aligned4(dY) || (loss && !aligned4(loss)))
+    return fail(MLP_ERR_ALIGN, "device pointers must be 4-byte aligned");
+  hipError_t e = mlph::launch_mse_grad(n, k, Y, T, dY, loss, (hipStream_t)stream);
+  return e == hipSuccess ? MLP_OK : hip_fail(e, "mlp_mse_grad launch");
+}
+
 }  // extern "C"

@@ -143,6 +143,7 @@ hipError_t launch_dense_backward(int64_t n, int din, int dout, const float *X, c
                                  const float *W, int act, float *gW, float *gb, float *dX, float *dZ,
                                  hipStream_t s);
 hipError_t launch_update(int64_t P, float *theta, const float *g, float *comp, float lr, hipStream_t s);
+hipError_t launch_mse_grad(int64_t n, int k, const float *Y, const float *T, float *dY, float *loss, hipStream_t s);
 hipError_t launch_eval_batched(const mlp_batch_item *items_dev, int n_nets, int D, int K, const float *X,
                                const float *T, const float *theta, float *loss, int32_t *correct, hipStream_t s);
 

@@ -458,6 +458,46 @@ class DeepNet:
             a = DenseFunction.apply(a, W, b, act, gW, gb)
         return a
 
+    # ---- the same epoch through the C ABI alone (no autograd): forward layer by
+    # layer, the squared-error gradient, backward layer by layer, the update
+    def _fused_buffers(self, n: int):
+        if getattr(self, "_fb_n", None) != n:
+            dev, w = self.device, self.widths
+            self._acts = [torch.empty((n, w[l + 1]), dtype=torch.float32, device=dev) for l in range(len(w) - 1)]
+            self._dacts = [torch.empty((n, w[l + 1]), dtype=torch.float32, device=dev) for l in range(len(w) - 1)]
+            self._dz = torch.empty(max(n * max(w[1:]), 4), dtype=torch.float32, device=dev)
+            self._fb_n = n
+        return self._acts, self._dacts, self._dz
+
+    def epoch_fused(self, X: torch.Tensor, T: torch.Tensor, loss_out: torch.Tensor, stream=None) -> None:
+        """One full-batch epoch (section 2.2's loop over L layers) as library
+        calls on the stream; the epoch's loss lands in loss_out[0]."""
+        n, w, L = X.shape[0], self.widths, len(self.layers)
+        acts, dacts, dz = self._fused_buffers(n)
+        s = _stream(stream)
+        a = X
+        for l, (W, b) in enumerate(self.layers):
+            act = 1 if (self.act == "tanh" and l < L - 1) else 0
+            check(lib.mlp_dense_forward(_ptr(a), n, w[l], w[l + 1], _ptr(W), _ptr(b), act, _ptr(acts[l]), s))
+            a = acts[l]
+        check(lib.mlp_mse_grad(_ptr(acts[-1]), _ptr(T), n, w[-1], _ptr(dacts[-1]), _ptr(loss_out), s))
+        for l in range(L - 1, -1, -1):
+            W, _ = self.layers[l]
+            gW, gb = self.grads[l]
+            act = 1 if (self.act == "tanh" and l < L - 1) else 0
+            xin = X if l == 0 else acts[l - 1]
+            check(lib.mlp_dense_backward(_ptr(xin), _ptr(acts[l]), _ptr(dacts[l]), n, w[l], w[l + 1], _ptr(W), act,
+                                         _ptr(gW), _ptr(gb), _ptr(dacts[l - 1]) if l > 0 else None, _ptr(dz),
+                                         dz.numel() * 4, s))
+        check(lib.mlp_update(_ptr(self.flat), _ptr(self.grad), _ptr(self.comp), self.flat.numel(), self.lr, s))
+
+    def train_fused(self, X: torch.Tensor, T: torch.Tensor, epochs: int, loss_hist: torch.Tensor | None = None):
+        hist = loss_hist if loss_hist is not None else torch.empty(max(epochs, 1), dtype=torch.float32,
+                                                                     device=self.device)
+        for e in range(epochs):
+            self.epoch_fused(X, T, hist[e:e + 1])
+        return hist[:epochs]
+
     def train(self, X: torch.Tensor, T: torch.Tensor, epochs: int, loss_hist: torch.Tensor | None = None):
         hist = loss_hist if loss_hist is not None else torch.empty(max(epochs, 1), dtype=torch.float32,
                                                                      device=self.device)
@@ -468,3 +508,33 @@ class DeepNet:
             check(lib.mlp_update(_ptr(self.flat), _ptr(self.grad), _ptr(self.comp), P, self.lr, _stream()))
             hist[e:e + 1].copy_(loss.detach())
         return hist[:epochs]
+
+
+class DeepGraph:
+    """`epochs` fused epochs of a DeepNet (library calls only) captured once in
+    a HIP graph (torch.cuda.CUDAGraph) and replayed: each replay trains the
+    net `epochs` more epochs in place; the loss of each captured epoch lands
+    in `loss` [epochs].  X, T and the net's buffers must stay in place."""
+
+    def __init__(self, net: DeepNet, X: torch.Tensor, T: torch.Tensor, epochs: int):
+        if epochs <= 0:
+            raise ValueError("epochs must be positive")
+        self.net, self.X, self.T = net, X, T
+        self.loss = torch.empty(max(epochs, 4), dtype=torch.float32, device=net.device)[:epochs]
+        net._fused_buffers(X.shape[0])
+        # one epoch outside the capture loads every kernel; the parameters are restored
+        flat0, comp0 = net.flat.detach().clone(), (net.comp.clone() if net.comp is not None else None)
+        net.epoch_fused(X, T, self.loss[:1])
+        torch.cuda.synchronize()
+        net.flat.detach().copy_(flat0)
+        if comp0 is not None:
+            net.comp.copy_(comp0)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph, capture_error_mode="thread_local"):
+            for e in range(epochs):
+                net.epoch_fused(X, T, self.loss[e:e + 1])
+
+    def replay(self) -> None:
+        self.graph.replay()
+

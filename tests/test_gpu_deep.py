@@ -70,3 +70,47 @@ def test_deep_net_training_matches_the_oracle(M, widths, act, epochs):
     lerr = normwise(hist.cpu().numpy(), ref_hist)
     say(f"  params {e:.2e}  loss history {lerr:.2e}  final loss {ref_hist[-1]:.4f}")
     assert e <= 1e-5 and lerr <= 1e-5
+
+
+def test_mse_grad_kernel(M):
+    from paper_1908_07847_amd._lib import lib
+    g = np.random.default_rng(5)
+    for n, k in ((1, 1), (120, 3), (5000, 7)):
+        Y = g.uniform(0, 1, (n, k)).astype(np.float32)
+        T = g.uniform(0, 1, (n, k)).astype(np.float32)
+        Yd, Td = torch.from_numpy(Y).cuda(), torch.from_numpy(T).cuda()
+        dY, loss = torch.empty_like(Yd), torch.empty(4, device="cuda")
+        assert lib.mlp_mse_grad(Yd.data_ptr(), Td.data_ptr(), n, k, dY.data_ptr(), loss.data_ptr(), None) == 0
+        torch.cuda.synchronize()
+        e = Y.astype(np.float64) - T
+        assert abs(float(loss[0]) - np.mean(e * e)) <= 1e-6 * np.mean(e * e) + 1e-12
+        assert normwise(dY.cpu().numpy(), 2 * e / (n * k)) <= 1e-6
+
+
+def test_fused_deep_epochs_match_the_oracle_and_replay_from_a_graph(M):
+    """DeepNet.train_fused (the epoch as library calls) against the oracle;
+    DeepGraph replays equal the same epochs run eagerly, bitwise, with eager
+    work between the replays."""
+    w = synth.single(2)
+    widths, act = [33, 24, 12, 3], "tanh"
+    theta = np.random.default_rng(3).uniform(-0.5, 0.5, oracle.deep_n_params(widths)).astype(np.float32)
+    X, T = torch.from_numpy(w["X"]).cuda(), torch.from_numpy(w["T"]).cuda()
+    net = M.DeepNet(widths, theta=theta, act=act)
+    hist = net.train_fused(X, T, 1000)
+    torch.cuda.synchronize()
+    q, ref_hist = oracle.deep_train(w["X"], w["T"], widths, theta, 0.1, 1000, act=act)
+    e, lerr = normwise(net.flat.detach().cpu().numpy(), q), normwise(hist.cpu().numpy(), ref_hist)
+    say(f"  fused deep epochs: params {e:.2e}  loss history {lerr:.2e}")
+    assert e <= 1e-5 and lerr <= 1e-5
+    G = 25
+    a = M.DeepNet(widths, theta=theta, act=act)
+    b = M.DeepNet(widths, theta=theta, act=act)
+    graph = M.DeepGraph(b, X, T, G)
+    assert np.array_equal(b.flat.detach().cpu().numpy(), theta)     # capture left the net as it was
+    lbuf = torch.empty(G, device="cuda")
+    for rep in range(3):
+        a.train_fused(X, T, G, loss_hist=lbuf)
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(a.flat, b.flat) and torch.equal(a.comp, b.comp), rep
+        assert torch.equal(graph.loss, lbuf), rep
