@@ -206,6 +206,12 @@ def bench_single(args):
                   "traffic": measured_traffic(tkey, kind), "traffic_unit": "bytes per launch", "kernel": kname,
                   "kernel_ms": kern * 1e3, "flops_per_launch": flops},
         final_loss=final_loss, repeats=reps, vs_plain=vs_plain, steps=steps, warmup=warmup)
+    if wl in (1, 2):
+        # one net is one workgroup on one of the 256 CUs: its honest denominator
+        # is one CU's share of the FP32 rate, and the per-epoch latency
+        cu_peak = PEAK["fp32"] / 256
+        res["roofline"]["one_cu"] = {"peak": cu_peak, "unit": "TFLOP/s", "frac": achieved / cu_peak,
+                                     "epoch_us": kern * 1e6 / steps}
     if wl in (4, 5):
         res["roofline"]["sync_adjusted"] = sync_adjusted(mlp, torch, flops, peak, N * steps * (D + K) * 4.0,
                                                          steps * (-(-N // batch)), kern)
