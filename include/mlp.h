@@ -32,6 +32,13 @@
  *   - Device pointers must be 4-byte aligned; X, T, the workspace and the
  *     batched item table must be 16-byte aligned.
  *   - NaN/Inf in inputs propagate; nothing checks for them on the hot path.
+ *
+ * Beyond the method, the library offers the build's own extensions, each
+ * marked where it is declared: reduced-precision operands for the two large
+ * contractions, many networks in one launch (independent rows, or one shared
+ * X), class predictions and a held-out read-out, a tanh hidden activation
+ * and momentum, one dense layer for networks with several hidden layers,
+ * and a grid-barrier probe for measurement.
  */
 #ifndef MLP_H_
 #define MLP_H_
