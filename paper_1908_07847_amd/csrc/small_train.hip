@@ -300,6 +300,12 @@ __global__ __launch_bounds__(NW * 64) void k_small_train(
 
     // ======================= wave partials to LDS
     float *pw = Part + wave * PW;
+    // this lane's base in the block, opaque to the compiler each epoch: the
+    // per-lane addresses below are then formed here (base + a wave-uniform
+    // offset) instead of being kept live across the epoch loop, where the
+    // wide instances would spill them
+    int lbase = 4 * lg * DN + l16;
+    asm volatile("" : "+v"(lbase));
 #pragma unroll
     for (int ht = 0; ht < HTM; ++ht) {
       if (ht < HT) {
@@ -307,7 +313,7 @@ __global__ __launch_bounds__(NW * 64) void k_small_train(
         for (int ft = 0; ft < 4; ++ft) {
           if (ft < FT) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) pw[(ht * 16 + 4 * lg + i) * DN + ft * 16 + l16] = gacc[ht][ft][i];
+            for (int i = 0; i < 4; ++i) pw[lbase + (ht * 16 + i) * DN + ft * 16] = gacc[ht][ft][i];
           }
         }
         // lane (output l16, group lg): hidden units 4 lg .. 4 lg + 3
