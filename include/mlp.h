@@ -270,6 +270,35 @@ mlp_status mlp_update(float *theta, const float *grad, float *comp, int64_t P, f
 mlp_status mlp_mse_grad(const float *Y, const float *T, int64_t n, int32_t k, float *dY, float *loss,
                         void *stream);
 
+/* Full-batch training of a network with several hidden layers in one launch:
+ * section 2.2's loop (feed forward layer by layer, the mean squared error,
+ * backpropagation from the top layer down using each layer's pre-update
+ * weights, then theta <- theta - lr g for every layer at once), `epochs`
+ * times, one workgroup holding the rows, activations, deltas and
+ * parameters in LDS.  The same epochs as DeepNet's per-layer calls
+ * (mlp_dense_forward, mlp_mse_grad, mlp_dense_backward, mlp_update) up to
+ * float summation order.
+ *   X          [n][widths[0]] rows, T [n][widths[n_layers]] targets
+ *   n_layers   weight layers, 1 .. 8; widths (host) [n_layers + 1], each
+ *              1 .. 1024
+ *   act        hidden layers' activation, 0: the sigmoid of Equation 1,
+ *              1: tanh; the top layer applies the sigmoid
+ *   theta      [P] parameters packed layer after layer, each as W_l
+ *              [widths[l+1]][widths[l]] then b_l [widths[l+1]]; updated
+ *              in place
+ *   comp       [P] Kahan compensation terms (updated in place), or NULL for
+ *              the plain update
+ *   loss_hist  [epochs] the error at each epoch's pre-update parameters, or
+ *              NULL
+ * Device pointers, 4-byte aligned.  MLP_ERR_UNSUPPORTED when n rows of
+ * every layer's activations, two delta arrays and 2 + RS copies of the P
+ * parameters (RS >= 1 row segments of the gradient sums) exceed 160 KiB.
+ * Bitwise repeatable.  Asynchronous on the stream; argument errors return
+ * before any launch; epochs = 0 launches nothing. */
+mlp_status mlp_deep_train(const float *X, const float *T, int64_t n, int32_t n_layers,
+                          const int32_t *widths /*host*/, int32_t act, float *theta, float *comp, float lr,
+                          int32_t epochs, float *loss_hist, void *stream);
+
 /* ---- measurement ---------------------------------------------------------- */
 
 /* Bytes of workspace mlp_barrier_probe needs. */

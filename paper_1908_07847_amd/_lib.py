@@ -55,7 +55,7 @@ BARRIER_PROBE_WS_BYTES = 2048   # MLP_BARRIER_PROBE_WS_BYTES
 SYMBOLS = ["mlp_workspace_size", "mlp_init", "mlp_destroy", "mlp_forward", "mlp_backward", "mlp_step",
            "mlp_train", "mlp_predict", "mlp_train_batched", "mlp_eval_batched", "mlp_shared_workspace_size",
            "mlp_train_shared", "mlp_barrier_probe", "mlp_set_momentum", "mlp_dense_forward", "mlp_dense_backward",
-           "mlp_update", "mlp_mse_grad",
+           "mlp_update", "mlp_mse_grad", "mlp_deep_train",
            "mlp_set_launch_hint", "mlp_status_string", "mlp_last_error"]
 
 
@@ -87,6 +87,7 @@ def _load():
     lib.mlp_dense_backward.argtypes = [vp, vp, vp, i64, i32, i32, vp, i32, vp, vp, vp, vp, ctypes.c_size_t, vp]
     lib.mlp_update.argtypes = [vp, vp, vp, i64, f32, vp]
     lib.mlp_mse_grad.argtypes = [vp, vp, i64, i32, vp, vp, vp]
+    lib.mlp_deep_train.argtypes = [vp, vp, i64, i32, ctypes.POINTER(i32), i32, vp, vp, f32, i32, vp, vp]
     for name in SYMBOLS:
         if name not in ("mlp_status_string", "mlp_last_error"):
             getattr(lib, name).restype = ctypes.c_int

@@ -11,6 +11,7 @@
 #include <string>
 
 #include "mlp.h"
+#include "deep.hpp"
 #include "mlp_device.hpp"
 #include "mlp_large.hpp"
 
@@ -487,6 +488,31 @@ mlp_status mlp_mse_grad(const float *Y, const float *T, int64_t n, int32_t k, fl
     return fail(MLP_ERR_ALIGN, "device pointers must be 4-byte aligned");
   hipError_t e = mlph::launch_mse_grad(n, k, Y, T, dY, loss, (hipStream_t)stream);
   return e == hipSuccess ? MLP_OK : hip_fail(e, "mlp_mse_grad launch");
+}
+
+mlp_status mlp_deep_train(const float *X, const float *T, int64_t n, int32_t n_layers, const int32_t *widths,
+                          int32_t act, float *theta, float *comp, float lr, int32_t epochs, float *loss_hist,
+                          void *stream) {
+  if (!X || !T || !theta || !widths) return fail(MLP_ERR_ARG, "X, T, theta and widths must not be NULL");
+  if (n_layers < 1 || n_layers > mlph::kDeepMaxLayers)
+    return fail(MLP_ERR_SHAPE, "n_layers must be in 1 .. %d", mlph::kDeepMaxLayers);
+  for (int l = 0; l <= n_layers; ++l)
+    if (widths[l] < 1 || widths[l] > mlph::kDeepMaxWidth)
+      return fail(MLP_ERR_SHAPE, "widths[%d] = %d outside 1 .. %d", l, widths[l], mlph::kDeepMaxWidth);
+  if (n <= 0) return fail(MLP_ERR_SHAPE, "n must be positive");
+  if (act != 0 && act != 1) return fail(MLP_ERR_ARG, "act must be 0 (sigmoid) or 1 (tanh)");
+  if (!(lr >= 0.0f) || lr > 1e6f) return fail(MLP_ERR_ARG, "lr must be finite and >= 0");
+  if (epochs < 0) return fail(MLP_ERR_ARG, "epochs must be >= 0");
+  const void *ptrs[] = {X, T, theta, comp, loss_hist};
+  for (const void *p : ptrs)
+    if (p && !aligned4(p)) return fail(MLP_ERR_ALIGN, "device pointers must be 4-byte aligned");
+  mlph::DeepPlan plan;
+  if (!mlph::deep_plan(n_layers, widths, n, 160 * 1024, &plan))
+    return fail(MLP_ERR_UNSUPPORTED, "rows, activations, deltas and parameters of this network do not fit in "
+                                     "one workgroup's 160 KiB of LDS");
+  if (epochs == 0) return MLP_OK;
+  hipError_t e = mlph::launch_deep_train(plan, act, X, T, theta, comp, lr, epochs, loss_hist, (hipStream_t)stream);
+  return e == hipSuccess ? MLP_OK : hip_fail(e, "mlp_deep_train launch");
 }
 
 }  // extern "C"

@@ -498,6 +498,19 @@ class DeepNet:
             self.epoch_fused(X, T, hist[e:e + 1])
         return hist[:epochs]
 
+    def train_kernel(self, X: torch.Tensor, T: torch.Tensor, epochs: int, loss_hist: torch.Tensor | None = None,
+                     stream=None):
+        """`epochs` full-batch epochs in one launch (mlp_deep_train: the net
+        resident in one workgroup's LDS); the loss of each epoch in the
+        returned [epochs] tensor."""
+        hist = loss_hist if loss_hist is not None else torch.empty(max(epochs, 1), dtype=torch.float32,
+                                                                     device=self.device)
+        w = (ctypes.c_int32 * len(self.widths))(*self.widths)
+        check(lib.mlp_deep_train(_ptr(X), _ptr(T), X.shape[0], len(self.widths) - 1, w,
+                                 1 if self.act == "tanh" else 0, _ptr(self.flat), _ptr(self.comp), self.lr,
+                                 int(epochs), _ptr(hist), _stream(stream)))
+        return hist[:epochs]
+
     def train(self, X: torch.Tensor, T: torch.Tensor, epochs: int, loss_hist: torch.Tensor | None = None):
         hist = loss_hist if loss_hist is not None else torch.empty(max(epochs, 1), dtype=torch.float32,
                                                                      device=self.device)

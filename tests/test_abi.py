@@ -189,3 +189,30 @@ def test_variant_flag_and_momentum_arguments():
     bad = L.Config(33, 16, 3, 0, 120, 0, 0.1, 16)
     assert L.lib.mlp_workspace_size(ctypes.byref(bad), ctypes.byref(n)) == L.MLP_ERR_ARG
     assert L.lib.mlp_set_momentum(None, 0.9, 0x1000) == L.MLP_ERR_ARG
+
+
+def test_deep_train_rejects_before_touching_the_device():
+    """mlp_deep_train's argument checks and its LDS-fit check run on the
+    host; epochs = 0 launches nothing."""
+    L = _lib()
+
+    def call(widths=(33, 16, 16, 3), n=120, act=0, lr=0.1, ep=10, X=0x10000, T=0x20000, th=0x30000, comp=0x40000,
+             layers=None):
+        w = (ctypes.c_int32 * len(widths))(*widths)
+        nl = len(widths) - 1 if layers is None else layers
+        return L.lib.mlp_deep_train(X, T, n, nl, w, act, th, comp, lr, ep, None, None)
+
+    assert call(X=None) == L.MLP_ERR_ARG
+    assert call(th=None) == L.MLP_ERR_ARG
+    assert call(layers=0) == L.MLP_ERR_SHAPE
+    assert call(widths=(2,) * 10) == L.MLP_ERR_SHAPE                # 9 weight layers
+    assert call(widths=(33, 0, 3)) == L.MLP_ERR_SHAPE
+    assert call(widths=(33, 1025, 3)) == L.MLP_ERR_SHAPE
+    assert call(n=0) == L.MLP_ERR_SHAPE
+    assert call(act=2) == L.MLP_ERR_ARG
+    assert call(lr=float("nan")) == L.MLP_ERR_ARG
+    assert call(ep=-1) == L.MLP_ERR_ARG
+    assert call(th=0x30002) == L.MLP_ERR_ALIGN
+    assert call(n=100000) == L.MLP_ERR_UNSUPPORTED                  # rows beyond one workgroup's LDS
+    assert call(widths=(64, 512, 64, 3)) == L.MLP_ERR_UNSUPPORTED   # parameters beyond it
+    assert call(ep=0) == L.MLP_OK

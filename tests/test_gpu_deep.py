@@ -114,3 +114,59 @@ def test_fused_deep_epochs_match_the_oracle_and_replay_from_a_graph(M):
         torch.cuda.synchronize()
         assert torch.equal(a.flat, b.flat) and torch.equal(a.comp, b.comp), rep
         assert torch.equal(graph.loss, lbuf), rep
+
+
+def _rows(n, d, k, seed):
+    g = np.random.default_rng(seed)
+    X = g.normal(size=(n, d)).astype(np.float32)
+    T = np.zeros((n, k), np.float32)
+    T[np.arange(n), g.integers(0, k, n)] = 1.0
+    return X, T
+
+
+@pytest.mark.parametrize("widths,act,epochs,rows,compensated", [
+    ([33, 16, 16, 3], "sigmoid", 1000, "w2", True),     # the two-hidden-layer net on workload 2's rows
+    ([33, 24, 12, 3], "tanh", 1000, "w2", True),
+    ([33, 20, 10, 6, 1], "tanh", 500, "w2", True),      # binary output
+    ([33, 10, 3], "sigmoid", 500, "w1", False),         # 60 rows: ragged row segments; plain update
+    ([33, 32, 16, 3], "sigmoid", 300, 200, True),       # 200 rows: fewer row segments to fit LDS
+    ([1, 1], "sigmoid", 50, 1, True),                   # one row, one unit
+    ([7, 5, 4, 3, 2, 2, 3, 2, 1], "tanh", 200, 37, True),  # the most layers
+])
+def test_one_launch_deep_training_matches_the_oracle(M, widths, act, epochs, rows, compensated):
+    """mlp_deep_train (the whole run in one workgroup) against the FP64
+    oracle's L-layer training."""
+    if rows in ("w1", "w2"):
+        w = synth.single(1 if rows == "w1" else 2)
+        X, T = w["X"], (w["T"] if widths[-1] == 3 else synth.binary_targets(w))
+    else:
+        X, T = _rows(rows, widths[0], widths[-1], rows)
+    theta = np.random.default_rng(len(widths) + epochs).uniform(-0.5, 0.5,
+                                                                 oracle.deep_n_params(widths)).astype(np.float32)
+    say(f"one-launch deep net {widths} hidden {act}: {X.shape[0]} rows, {epochs} epochs, "
+        f"{'compensated' if compensated else 'plain'} update")
+    net = M.DeepNet(widths, theta=theta, act=act, compensated=compensated)
+    hist = net.train_kernel(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(), epochs)
+    torch.cuda.synchronize()
+    q, ref_hist = oracle.deep_train(X, T, widths, theta, 0.1, epochs, act=act)
+    e = normwise(net.flat.detach().cpu().numpy(), q)
+    lerr = normwise(hist.cpu().numpy(), ref_hist)
+    say(f"  params {e:.2e}  loss history {lerr:.2e}  final loss {ref_hist[-1]:.4f}")
+    assert e <= 1e-5 and lerr <= 1e-5
+
+
+def test_one_launch_deep_training_is_repeatable_and_resumable(M):
+    """Two runs are bitwise equal; 300 epochs in one call equal 100 + 200
+    (the compensation terms carry across calls)."""
+    w = synth.single(2)
+    widths, act = [33, 16, 16, 3], "sigmoid"
+    theta = np.random.default_rng(11).uniform(-0.5, 0.5, oracle.deep_n_params(widths)).astype(np.float32)
+    X, T = torch.from_numpy(w["X"]).cuda(), torch.from_numpy(w["T"]).cuda()
+    a, b, c = (M.DeepNet(widths, theta=theta, act=act) for _ in range(3))
+    ha = a.train_kernel(X, T, 300)
+    hb = b.train_kernel(X, T, 300)
+    c.train_kernel(X, T, 100)
+    c.train_kernel(X, T, 200)
+    torch.cuda.synchronize()
+    assert torch.equal(a.flat, b.flat) and torch.equal(a.comp, b.comp) and torch.equal(ha, hb)
+    assert torch.equal(a.flat, c.flat) and torch.equal(a.comp, c.comp)
