@@ -14,8 +14,8 @@ Workloads (all synthetic, from the seeded generator):
   w5   4,194,304 x 64, 64-1024-3, minibatch 16384             step = 1 epoch (256 minibatches)
   w6   64 nets of w5's shape sharing its X (grid of 8 learning rates x 8 initialisations)
                                                                step = 1 epoch of every net
-  w2d  w2's rows through a network with two hidden layers (33-16-16-3), the dense
-       layer kernels composed by torch.autograd     step = 1 epoch
+  w2d  w2's rows through a network with two hidden layers (33-16-16-3), every
+       epoch in one launch (mlp_deep_train)            step = 1 epoch
   w2a  w2 through the differentiation path: per epoch MLPFunction (forward
        kernel), torch's MSE, the hand-written adjoint (backward kernels) and
        mlp_step, launched from Python                 step = 1 epoch
@@ -450,16 +450,25 @@ def bench_deep(args):
     net.train(X, T, warmup, loss_hist=hist)
     ag_epochs = min(steps, 200)
     awall, _ = timed(lambda: net.train(X, T, ag_epochs, loss_hist=hist), stream)
-    # timed form: the fused epoch (library calls only) replayed from a HIP graph of G epochs
+    # the per-layer library calls of one epoch replayed from a HIP graph of G epochs
     net.flat.detach().copy_(torch.from_numpy(theta))
     net.comp.zero_()
     graph = mlp.DeepGraph(net, X, T, G)
 
-    def run():
+    def run_graph():
         for r in range(steps // G):
             graph.replay()
             hist[r * G:(r + 1) * G].copy_(graph.loss)
-    wall, kern = timed(run, stream)
+    gwall, _ = timed(run_graph, stream)
+    # timed form: every epoch in one launch (mlp_deep_train)
+    net.flat.detach().copy_(torch.from_numpy(theta))
+    net.comp.zero_()
+    net.train_kernel(X, T, warmup, loss_hist=hist)
+    net.flat.detach().copy_(torch.from_numpy(theta))
+    net.comp.zero_()
+    wall, kern = timed(lambda: net.train_kernel(X, T, steps, loss_hist=hist), stream)
+    final_loss = float(hist[steps - 1].item()) if steps else None
+    reps = repeats(lambda: net.train_kernel(X, T, steps, loss_hist=hist), stream, wall, steps)
     # per sample-epoch: forward 2 w(l) w(l+1) + activation, backward 4 w(l) w(l+1) (gW and dX; dX skipped for
     # the first layer), plus the update 2P per epoch
     P = mlp.deep_n_params(widths)
@@ -469,20 +478,24 @@ def bench_deep(args):
         f += 4 * widths[l + 1]
     flops = f * N * steps + 2 * P * steps
     achieved = flops / kern / 1e12
+    cu_peak = PEAK["fp32"] / 256
     res = dict(
         metric="training samples*epochs/s", value=N * steps / wall, unit="samples*epochs/s",
         ms_per_step=wall * 1e3 / steps, dtype="f32",
         config={"workload": f"several hidden layers: N=120 x 33, {'-'.join(map(str, widths))}, full batch, hidden "
-                            f"{args.act}, sigmoid output, MSE, GD lr=0.1; per epoch the dense-layer forward, the "
-                            "squared-error gradient, the dense-layer adjoints and the update, replayed from a HIP "
-                            f"graph of {G} epochs", "n_rows": N, "widths": widths, "step": "one epoch"},
+                            f"{args.act}, sigmoid output, MSE, GD lr=0.1; every epoch in one launch "
+                            "(mlp_deep_train)", "n_rows": N, "widths": widths, "step": "one epoch"},
+        graph={"value": N * steps / gwall, "ms_per_step": gwall * 1e3 / steps,
+               "form": f"per epoch the dense-layer forward, the squared-error gradient, the dense-layer adjoints and "
+                       f"the update as library calls, replayed from a HIP graph of {G} epochs"},
         autograd={"value": N * ag_epochs / awall, "ms_per_step": awall * 1e3 / ag_epochs, "epochs": ag_epochs,
                   "form": "DenseFunction layers composed by torch.autograd, launched from Python"},
         roofline={"bound": "alu", "achieved": achieved, "peak": PEAK["fp32"], "unit": "TFLOP/s",
                   "frac": achieved / PEAK["fp32"], "traffic": None, "traffic_unit": "bytes per launch",
-                  "kernel": "mlpk::k_dense_fwd + k_mse_grad + k_dense_dz + k_dense_wsum + k_dense_dx + k_update "
-                            "(per epoch)", "kernel_ms": kern * 1e3, "flops_per_launch": flops},
-        final_loss=float(hist[steps - 1].item()) if steps else None, steps=steps, warmup=warmup)
+                  "kernel": "mlpk::k_deep_train", "kernel_ms": kern * 1e3, "flops_per_launch": flops,
+                  "one_cu": {"peak": cu_peak, "unit": "TFLOP/s", "frac": achieved / cu_peak,
+                             "epoch_us": kern * 1e6 / steps}},
+        final_loss=final_loss, repeats=reps, steps=steps, warmup=warmup)
     return res, dict(w=w, theta=theta, widths=widths, act=args.act)
 
 
