@@ -32,6 +32,24 @@ namespace mlpk {
 
 using mlph::DeepPlan;
 
+// x / d and x mod d for 0 <= x < 2^20, 1 <= d, from the float reciprocal
+// inv = 1/d: the estimate is within one of the quotient (relative error
+// below 2^-22 on a quotient below 2^20) and one correction step makes it
+// exact.  About eight VALU operations instead of an integer division.
+__device__ __forceinline__ int div_small(int x, int d, float inv, int &rem) {
+  int q = (int)((float)x * inv);
+  int r = x - q * d;
+  if (r < 0) {
+    q -= 1;
+    r += d;
+  } else if (r >= d) {
+    q += 1;
+    r -= d;
+  }
+  rem = r;
+  return q;
+}
+
 template <int ACT>
 __global__ __launch_bounds__(mlph::kDeepThreads) void k_deep_train(
     DeepPlan p, const float *__restrict__ X, const float *__restrict__ T, float *__restrict__ theta,
@@ -74,8 +92,10 @@ __global__ __launch_bounds__(mlph::kDeepThreads) void k_deep_train(
       const float *b = W + wo * wi;
       float *Y = sm + p.aoff[l + 1];
       const bool hidden = l < L - 1;
+      const float inv_n = 1.0f / (float)n;
       for (int idx = tid; idx < n * wo; idx += NT) {
-        const int o = idx / n, r = idx - o * n;
+        int r;
+        const int o = div_small(idx, n, inv_n, r);
         const float *a = A + r * si, *wr = W + o * wi;
         float z = b[o];
 #pragma unroll 8
@@ -89,8 +109,10 @@ __global__ __launch_bounds__(mlph::kDeepThreads) void k_deep_train(
     {
       const float *Y = sm + p.aoff[L], *Ts = sm + p.toff;
       float part = 0.0f;
+      const float inv_k = 1.0f / (float)K;
       for (int idx = tid; idx < n * K; idx += NT) {
-        const int r = idx / K, k = idx - r * K;
+        int k;
+        const int r = div_small(idx, K, inv_k, k);
         const float y = Y[r * sK + k], d = y - Ts[r * sK + k];
         part = fmaf(d, d, part);
         Dtop[r * sd + k] = (dscale * d) * (y * (1.0f - y));
@@ -114,10 +136,13 @@ __global__ __launch_bounds__(mlph::kDeepThreads) void k_deep_train(
       float *Dl = sm + ((l & 1) ? p.d1 : p.d0);
       const int nW = wo * (wi + 1), nG = p.RS * nW, nD = l > 0 ? n * wi : 0;
       float *G = sm + p.gr + p.poff[l];
+      const float inv_nw = 1.0f / (float)nW, inv_w1 = 1.0f / (float)(wi + 1), inv_wi = 1.0f / (float)wi;
       for (int idx = tid; idx < nG + nD; idx += NT) {
         if (idx < nG) {
           // segment sg of the row sum of parameter (o, i); i == wi is the bias
-          const int sg = idx / nW, k = idx - sg * nW, o = k / (wi + 1), i = k - o * (wi + 1);
+          int k, i;
+          const int sg = div_small(idx, nW, inv_nw, k);
+          const int o = div_small(k, wi + 1, inv_w1, i);
           const int r0 = sg * p.seg, r1 = min(n, r0 + p.seg);
           float acc = 0.0f;
           if (i < wi) {
@@ -131,7 +156,9 @@ __global__ __launch_bounds__(mlph::kDeepThreads) void k_deep_train(
           }
         } else {
           // delta of layer l's input units (a hidden layer) at row r
-          const int j = idx - nG, r = j / wi, i = j - r * wi;
+          const int j = idx - nG;
+          int i;
+          const int r = div_small(j, wi, inv_wi, i);
           const float *dr = Dn + r * sd;
           float acc = 0.0f;
 #pragma unroll 8
