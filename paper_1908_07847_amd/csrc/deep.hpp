@@ -11,11 +11,13 @@ constexpr int kDeepMaxWidth = 1024;    // units of any layer
 constexpr int kDeepThreads = 1024;
 
 // LDS plan of one network (floats).  Row strides are odd so that the lanes
-// of a wave walking rows of an activation or delta array hit distinct banks.
+// of a wave walking rows of an activation or delta array hit distinct banks,
+// and leave room after each row of a layer's input for a column of ones
+// (the bias input of the gradient's row sums).
 struct DeepPlan {
   int L, n, P, RS, seg;            // layers, rows, parameters, row segments of the gradient sums
   int w[kDeepMaxLayers + 1];       // widths
-  int sa[kDeepMaxLayers + 1];      // row stride of layer l's activations (l = 0: X)
+  int sa[kDeepMaxLayers + 1];      // row stride of layer l's activations (l = 0: X), >= w[l] + 1
   int poff[kDeepMaxLayers + 1];    // packed offset of W_l (b_l follows it); poff[L] = P
   int aoff[kDeepMaxLayers + 1];    // LDS offset of layer l's activations
   int toff, d0, d1, sd;            // targets, the two delta buffers and their row stride

@@ -73,6 +73,12 @@ __global__ __launch_bounds__(mlph::kDeepThreads) void k_deep_train(
     const int r = i / K, k = i - r * K;
     sm[p.toff + r * sK + k] = T[i];
   }
+  // a column of ones after every layer input's row: the bias is the last
+  // column of the gradient's row sums
+  for (int i = tid; i < n * L; i += NT) {
+    const int l = i / n, r = i - l * n;
+    sm[p.aoff[l] + r * p.sa[l] + p.w[l]] = 1.0f;
+  }
   for (int q = tid; q < P; q += NT) {
     sm[p.th + q] = theta[q];
     sm[p.cp + q] = compensated ? comp[q] : 0.0f;
@@ -134,26 +140,29 @@ __global__ __launch_bounds__(mlph::kDeepThreads) void k_deep_train(
       const float *W = sm + p.th + p.poff[l];
       const float *Dn = sm + (((l + 1) & 1) ? p.d1 : p.d0);
       float *Dl = sm + ((l & 1) ? p.d1 : p.d0);
-      const int nW = wo * (wi + 1), nG = p.RS * nW, nD = l > 0 ? n * wi : 0;
+      // the gradient's columns c = 0 .. wi (c = wi: the bias) in pairs (c, c + h)
+      const int h = (wi + 2) >> 1, nW = wo * h, nG = p.RS * nW, nD = l > 0 ? n * wi : 0;
       float *G = sm + p.gr + p.poff[l];
-      const float inv_nw = 1.0f / (float)nW, inv_w1 = 1.0f / (float)(wi + 1), inv_wi = 1.0f / (float)wi;
+      const float inv_nw = 1.0f / (float)nW, inv_h = 1.0f / (float)h, inv_wi = 1.0f / (float)wi;
       for (int idx = tid; idx < nG + nD; idx += NT) {
         if (idx < nG) {
-          // segment sg of the row sum of parameter (o, i); i == wi is the bias
-          int k, i;
+          // segment sg of the row sums of parameters (o, c0) and (o, c1);
+          // column wi is the bias (its input is the column of ones)
+          int k, c0;
           const int sg = div_small(idx, nW, inv_nw, k);
-          const int o = div_small(k, wi + 1, inv_w1, i);
+          const int o = div_small(k, h, inv_h, c0);
+          const int c1 = c0 + h, c1r = min(c1, wi);   // c1 = wi + 1 only when wi + 1 is odd: dropped
           const int r0 = sg * p.seg, r1 = min(n, r0 + p.seg);
-          float acc = 0.0f;
-          if (i < wi) {
+          float acc0 = 0.0f, acc1 = 0.0f;
 #pragma unroll 8
-            for (int r = r0; r < r1; ++r) acc = fmaf(Dn[r * sd + o], A[r * si + i], acc);
-            G[sg * P + o * wi + i] = acc;
-          } else {
-#pragma unroll 8
-            for (int r = r0; r < r1; ++r) acc += Dn[r * sd + o];
-            G[sg * P + wo * wi + o] = acc;
+          for (int r = r0; r < r1; ++r) {
+            const float d = Dn[r * sd + o];
+            const float *ar = A + r * si;
+            acc0 = fmaf(d, ar[c0], acc0);
+            acc1 = fmaf(d, ar[c1r], acc1);
           }
+          G[sg * P + (c0 < wi ? o * wi + c0 : wo * wi + o)] = acc0;
+          if (c1 <= wi) G[sg * P + (c1 < wi ? o * wi + c1 : wo * wi + o)] = acc1;
         } else {
           // delta of layer l's input units (a hidden layer) at row r
           const int j = idx - nG;
@@ -203,7 +212,7 @@ bool deep_plan(int L, const int32_t *widths, int64_t n, size_t lds_max, DeepPlan
   int64_t P = 0;
   for (int l = 0; l <= L; ++l) {
     q.w[l] = widths[l];
-    q.sa[l] = widths[l] | 1;
+    q.sa[l] = (widths[l] + 1) | 1;   // room for the column of ones
     q.poff[l] = (int)P;
     if (l < L) P += (int64_t)widths[l + 1] * widths[l] + widths[l + 1];
   }
