@@ -5,7 +5,7 @@
 // deltas and parameters resident in LDS.
 //
 // Per epoch, separated by workgroup barriers:
-//   forward, one phase per layer: lane (row r, unit o) forms
+//   forward, one phase per layer: lane (row r, units o and o + half) forms
 //     z = b_l[o] + sum_i A_l[r][i] W_l[o][i] and applies the hidden
 //     activation (the sigmoid of Equation 1 or tanh) or, on the top layer,
 //     the sigmoid; rows are the fast index across lanes, so the weight row
@@ -98,15 +98,23 @@ __global__ __launch_bounds__(mlph::kDeepThreads) void k_deep_train(
       const float *b = W + wo * wi;
       float *Y = sm + p.aoff[l + 1];
       const bool hidden = l < L - 1;
+      // units in pairs (o0, o0 + hO) of one row: the row's inputs load once
+      const int hO = (wo + 1) >> 1;
       const float inv_n = 1.0f / (float)n;
-      for (int idx = tid; idx < n * wo; idx += NT) {
+      for (int idx = tid; idx < n * hO; idx += NT) {
         int r;
-        const int o = div_small(idx, n, inv_n, r);
-        const float *a = A + r * si, *wr = W + o * wi;
-        float z = b[o];
+        const int o0 = div_small(idx, n, inv_n, r);
+        const int o1 = o0 + hO, o1r = min(o1, wo - 1);   // o1 = wo only when wo is odd: dropped
+        const float *a = A + r * si, *w0 = W + o0 * wi, *w1 = W + o1r * wi;
+        float z0 = b[o0], z1 = b[o1r];
 #pragma unroll 8
-        for (int i = 0; i < wi; ++i) z = fmaf(a[i], wr[i], z);
-        Y[r * so + o] = (hidden && ACT == 1) ? tanhf(z) : sigmoid(z);
+        for (int i = 0; i < wi; ++i) {
+          const float av = a[i];
+          z0 = fmaf(av, w0[i], z0);
+          z1 = fmaf(av, w1[i], z1);
+        }
+        Y[r * so + o0] = (hidden && ACT == 1) ? tanhf(z0) : sigmoid(z0);
+        if (o1 < wo) Y[r * so + o1] = (hidden && ACT == 1) ? tanhf(z1) : sigmoid(z1);
       }
       __syncthreads();
     }
