@@ -39,6 +39,17 @@ def build(force: bool = True) -> str:
     return _SO
 
 
+def build_timing(out_dir: str) -> str:
+    """The same sources compiled for timing on the host that runs them:
+    -O3 -march=native (the checker build above stays portable and free of
+    FMA contraction).  Built where it runs, never shipped between hosts."""
+    out = os.path.join(out_dir, "liboracle_native.so")
+    cmd = ["gcc", "-O3", "-march=native", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-w", "-o", out] + \
+        _SRCS + ["-lm"]
+    subprocess.run(cmd, check=True)
+    return out
+
+
 def _load():
     global _lib
     if _lib is not None:
@@ -63,6 +74,7 @@ def _bind(path: str):
     lib.ora_train_many.argtypes = [i32, ctypes.c_void_p, ctypes.c_void_p, P, ctypes.c_void_p,
                                    ctypes.c_void_p, i32, i32, P, P, P, i32, P, i32]
     lib.ora_max_threads.restype = i32
+    lib.ora_set_threads.argtypes = [i32]
     lib.ora_round_format.argtypes = [dbl, i32, i32, dbl]
     lib.ora_round_format.restype = dbl
     lib.ora_round_bf16.argtypes = [dbl]
@@ -234,6 +246,12 @@ def train_many(items, X, T, theta_packed, d: int, k: int, epochs: int, threads: 
 
 def max_threads() -> int:
     return int(_load().ora_max_threads())
+
+
+def set_threads(threads: int) -> None:
+    """Threads for the oracle's shared loops (<= 0: all processors).  Results
+    do not depend on it."""
+    _load().ora_set_threads(int(threads))
 
 
 def round_bf16(v: float) -> float:

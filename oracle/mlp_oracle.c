@@ -28,7 +28,11 @@
  *     slice uses its own m.
  *
  * Everything is plain float64 loops with no blocking or reordering: the
- * order of operations is the order of the method.
+ * order of operations is the order of the method.  On large inputs the
+ * independent outputs of a loop (rows of the forward pass and of delta1,
+ * entries of a gradient) are shared among OpenMP threads; each output is
+ * still formed by the same loop in the same order, so the result does not
+ * depend on the thread count (bit for bit; tested).
  */
 #include <math.h>
 #include <stdint.h>
@@ -38,12 +42,18 @@
 #include <omp.h>
 #endif
 
+/* Loops with at least this much work are shared among threads (inside
+ * ora_train_many, which runs one net per thread, nested regions stay on
+ * their thread). */
+#define ORA_PAR(work) ((int64_t)(work) >= ((int64_t)1 << 18))
+
 /* Equation 1. exp(-z) overflowing to +inf gives 0, the correct limit. */
 static double sigmoid(double z) { return 1.0 / (1.0 + exp(-z)); }
 
 /* Feed-forward pass (section 2.2): A = sigma(X W1^T + b1), Y = sigma(A W2^T + b2). */
 void ora_forward(int64_t n, int d, int h, int k, const double *X, const double *W1,
                  const double *b1, const double *W2, const double *b2, double *A, double *Y) {
+#pragma omp parallel for schedule(static) if (ORA_PAR(n * h * d))
   for (int64_t r = 0; r < n; ++r) {
     for (int j = 0; j < h; ++j) {
       double z = b1[j];
@@ -88,6 +98,7 @@ void ora_backward(int64_t n, int d, int h, int k, const double *X, const double 
       double y = Y[r * k + o];
       delta2[r * k + o] = dY[r * k + o] * y * (1.0 - y);
     }
+#pragma omp parallel for schedule(static) if (ORA_PAR(n * h * k))
   for (int64_t r = 0; r < n; ++r)
     for (int j = 0; j < h; ++j) {
       double s = 0.0;
@@ -96,6 +107,7 @@ void ora_backward(int64_t n, int d, int h, int k, const double *X, const double 
       delta1[r * h + j] = s * a * (1.0 - a);
     }
   for (int o = 0; o < k; ++o) {
+#pragma omp parallel for schedule(static) if (ORA_PAR(n * h))
     for (int j = 0; j < h; ++j) {
       double s = 0.0;
       for (int64_t r = 0; r < n; ++r) s += delta2[r * k + o] * A[r * h + j];
@@ -105,6 +117,7 @@ void ora_backward(int64_t n, int d, int h, int k, const double *X, const double 
     for (int64_t r = 0; r < n; ++r) s += delta2[r * k + o];
     gb2[o] = s;
   }
+#pragma omp parallel for schedule(static) if (ORA_PAR(n * h * d))
   for (int j = 0; j < h; ++j) {
     for (int i = 0; i < d; ++i) {
       double s = 0.0;
@@ -116,6 +129,7 @@ void ora_backward(int64_t n, int d, int h, int k, const double *X, const double 
     gb1[j] = s;
   }
   if (dX) {
+#pragma omp parallel for schedule(static) if (ORA_PAR(n * h * d))
     for (int64_t r = 0; r < n; ++r)
       for (int i = 0; i < d; ++i) {
         double s = 0.0;
@@ -214,5 +228,14 @@ int ora_max_threads(void) {
   return omp_get_max_threads();
 #else
   return 1;
+#endif
+}
+
+/* Threads for the shared loops of later calls (<= 0: the OpenMP default). */
+void ora_set_threads(int threads) {
+#ifdef _OPENMP
+  omp_set_num_threads(threads > 0 ? threads : omp_get_num_procs());
+#else
+  (void)threads;
 #endif
 }

@@ -30,6 +30,9 @@
  *                            |Y-T| <= 1 and sigma(1-sigma) <= 1/4.
  *                            That bound is formed in float32, left to right.
  * With prec 0 no operand is rounded and the result equals mlp_oracle.c.
+ * Large loops share their independent outputs among OpenMP threads, each
+ * output formed by the same loop in the same order (thread-count
+ * independent, bit for bit; the amax is a maximum, exact in any order).
  */
 #include <math.h>
 #include <stdint.h>
@@ -69,6 +72,8 @@ static double q_op(double v, int prec, int sexp) {
 }
 
 static double sigmoid(double z) { return 1.0 / (1.0 + exp(-z)); }
+
+#define ORA_PAR(work) ((int64_t)(work) >= ((int64_t)1 << 18))
 
 /* Round n values to the operand format of prec with scale 2^sexp (e4m3). */
 void ora_round_array(int prec, int sexp, const double *in, double *out, int64_t n) {
@@ -144,6 +149,7 @@ void ora_train_lowp(int64_t n, int d, int h, int k, int64_t batch, const double 
       }
       for (int64_t q = 0; q < (int64_t)h * d; ++q) W1q[q] = q_op(W1[q], prec, ew);
       /* feed forward */
+#pragma omp parallel for schedule(static) if (ORA_PAR(m * h * d))
       for (int64_t r = 0; r < m; ++r) {
         for (int j = 0; j < h; ++j) {
           double z = 0.0;
@@ -166,6 +172,7 @@ void ora_train_lowp(int64_t n, int d, int h, int k, int64_t batch, const double 
         }
       acc += L / ((double)m * (double)k);
       double amax_d1 = 0.0;
+#pragma omp parallel for schedule(static) reduction(max : amax_d1) if (ORA_PAR(m * h * k))
       for (int64_t r = 0; r < m; ++r)
         for (int j = 0; j < h; ++j) {
           double sum = 0.0;
@@ -179,6 +186,7 @@ void ora_train_lowp(int64_t n, int d, int h, int k, int64_t batch, const double 
       for (int64_t q = 0; q < m * h; ++q) delta1q[q] = q_op(delta1[q], prec, ed);
       /* gradients */
       for (int o = 0; o < k; ++o) {
+#pragma omp parallel for schedule(static) if (ORA_PAR(m * h))
         for (int j = 0; j < h; ++j) {
           double sum = 0.0;
           for (int64_t r = 0; r < m; ++r) sum += delta2[r * k + o] * A[r * h + j];
@@ -188,6 +196,7 @@ void ora_train_lowp(int64_t n, int d, int h, int k, int64_t batch, const double 
         for (int64_t r = 0; r < m; ++r) sum += delta2[r * k + o];
         gb2[o] = sum;
       }
+#pragma omp parallel for schedule(static) if (ORA_PAR(m * h * d))
       for (int j = 0; j < h; ++j) {
         for (int i = 0; i < d; ++i) {
           double sum = 0.0;

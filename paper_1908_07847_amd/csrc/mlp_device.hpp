@@ -11,11 +11,18 @@ constexpr int kWave = 64;
 constexpr int kLayerMaxOut = 16;  // outputs supported by the generic layer kernels
 
 // Logistic sigmoid (Equation 1) from the hardware base-2 exponential and
-// reciprocal.  e^-z = 2^(-z log2 e); the product -z log2 e is carried in two
-// parts (its rounded value and the exact rounding error from an FMA, plus
-// the tail of log2 e), so the exponent keeps ~48 bits and the result is
-// within a few float ulps of the exact sigmoid (checked against float64 in
-// the tests).  One Newton step sharpens the hardware reciprocal.  For
+// reciprocal.  e^-z = 2^(-z log2 e).  Published methods used:
+//  - log2 e held as a two-part constant, a high part plus its tail, in the
+//    manner of Cody and Waite's argument reduction (Cody & Waite, "Software
+//    Manual for the Elementary Functions", 1980);
+//  - the rounding error of the product -z * L_HI obtained exactly with one
+//    FMA, the error-free transformation TwoProductFMA (Ogita, Rump & Oishi,
+//    "Accurate sum and dot product", SIAM J. Sci. Comput. 2005);
+//  - 2^(th + tl) = 2^th (1 + tl ln 2) to first order in the small tail tl;
+//  - one Newton-Raphson iteration r <- r + r (1 - d r) on the hardware
+//    reciprocal of d = 1 + e^-z.
+// The exponent so keeps ~48 bits and the result is within a few float ulps
+// of the exact sigmoid (checked against float64 in the tests).  For
 // z < -87 the exponent is clamped at 2^126 (sigma ~ 1e-38 instead of 0).
 __device__ __forceinline__ float sigmoid_e(float z, float &e_out) {
   const float L_HI = 1.44269502162933349609375f;    // float(log2 e)

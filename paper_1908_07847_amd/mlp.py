@@ -8,6 +8,7 @@ host beyond argument marshalling.
 from __future__ import annotations
 
 import ctypes
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -96,6 +97,10 @@ class Net:
         check(lib.mlp_init(ctypes.byref(h), ctypes.byref(self.cfg), self.params_c(), _ptr(self.comp),
                            _ptr(self.ws), self.ws_bytes))
         self._h = h
+        # the handle is released by a finalizer that holds its own reference
+        # to mlp_destroy, so it runs (once) at collection or at interpreter
+        # exit, before module globals are torn down
+        self._finalizer = weakref.finalize(self, lib.mlp_destroy, h)
         self.velocity = None
         if momentum:
             self.set_momentum(momentum)
@@ -111,11 +116,11 @@ class Net:
             self.velocity = None
         check(lib.mlp_set_momentum(self._h, float(mu), _ptr(self.velocity)))
 
-    def __del__(self):
-        h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib.mlp_destroy(h)
-            self._h = None
+    def close(self) -> None:
+        """Release the library handle now (host memory only); idempotent."""
+        fin = getattr(self, "_finalizer", None)
+        if fin is not None:
+            fin()
 
     def params_c(self) -> Params:
         return Params(self.W1.data_ptr(), self.b1.data_ptr(), self.W2.data_ptr(), self.b2.data_ptr())

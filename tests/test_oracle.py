@@ -369,3 +369,22 @@ def test_classes_of_one_output_threshold_at_one_half():
     V = np.array([[0.2], [0.5], [0.5000001], [0.99]])
     assert oracle.classes(V).tolist() == [0, 0, 1, 1]
     assert oracle.classes(np.array([[0.1, 0.7, 0.7], [0.3, 0.2, 0.1]])).tolist() == [1, 0]
+
+
+@pytest.mark.parametrize("prec", [None, "bf16", "e4m3"])
+def test_oracle_results_do_not_depend_on_the_thread_count(prec):
+    """The shared loops only split independent outputs among threads: one
+    thread and several give the same bits (minibatch shape above the
+    sharing threshold)."""
+    w = synth.single(4, n_rows=4096, hidden=64)
+    p = Params.of(w["theta"])
+    runs = []
+    for threads in (1, max(2, oracle.max_threads())):
+        oracle.set_threads(threads)
+        if prec is None:
+            q, h = oracle.train(w["X"], w["T"], p, lr=0.1, epochs=1, batch=2048)
+        else:
+            q, h, _ = oracle.train_lowp(w["X"], w["T"], p, lr=0.1, epochs=1, batch=2048, prec=prec)
+        runs.append((q.flat(), h))
+    oracle.set_threads(0)
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
