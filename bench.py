@@ -1,17 +1,25 @@
 """Training throughput of the one-hidden-layer sigmoid MLP trainer on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload w2] [--prec fp32]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload w5] [--prec fp32]
 
 The metric is training samples*epochs/s: rows processed by full training
 steps (forward, error, backpropagation, gradient-descent update; arxiv
 1908.07847 section 2.2) per second, with inputs already resident in HBM.
 
+Default (the headline): w5 in float32 -- N = 4,194,304 rows x 64 features, a
+64-1024-3 net, minibatches of 16384 rows (256 per epoch), K epochs (default
+5).  A step is one epoch, run as one launch of the persistent trainer (the
+launches continue one training run: parameters and the compensation carry
+over); W untimed launches of one epoch come first.  The same K epochs are
+then timed in the bf16 and e4m3 operand forms (field `forms`, each with
+`vs_plain` = its rate over the float32 run); `--forms none` skips them.
+
 Workloads (all synthetic, from the seeded generator):
   w1   60 rows x 33 features, 33-10-3 net, full batch           step = 1 epoch
-  w2   120 rows x 33 features, 33-16-3 net, full batch (default) step = 1 epoch
+  w2   120 rows x 33 features, 33-16-3 net, full batch           step = 1 epoch
   w3   4096 independent nets, H~U{4..64}, 40..120 rows each    step = 1 epoch of every net
   w4   1,048,576 x 33, 33-256-3, minibatch 4096               step = 1 epoch (256 minibatches)
-  w5   4,194,304 x 64, 64-1024-3, minibatch 16384             step = 1 epoch (256 minibatches)
+  w5   4,194,304 x 64, 64-1024-3, minibatch 16384 (default)   step = 1 epoch (256 minibatches)
   w6   64 nets of w5's shape sharing its X (grid of 8 learning rates x 8 initialisations)
                                                                step = 1 epoch of every net
   w2d  w2's rows through a network with two hidden layers (33-16-16-3), every
@@ -22,15 +30,14 @@ Workloads (all synthetic, from the seeded generator):
   p4   class predictions (mlp_predict: forward pass + argmax + correct count) on
        w4's 1,048,576 rows with its 33-256-3 net     metric: predicted rows/s
 w4/w5 take --prec fp32|bf16|e4m3, w6 fp32|bf16 (operand precision of the two contractions).
-The timed region is one training call of K steps (one kernel launch).  The
-JSON line carries the roofline of that kernel, timed with HIP events on the
-stream it runs on, and the FP64 CPU oracle's throughput on a bounded sample
-of the same workload on the host cores.  Also reported: `repeats` (median and
-minimum per step over the timed run and five more runs of the same K steps,
-when one run takes under 1.5 s) and `vs_plain` (the chosen form's rate over
-the plain single-network FP32 kernel's on the same GPU: w3 against one launch
-per net on a sample of its nets, w4/w5 bf16/e4m3 against their FP32 runs, w6
-against one net of its shape).
+The JSON line carries the roofline of the timed kernel (HIP events on the
+stream it runs on; flops per launch are the method's algorithmic flops,
+4DH + 6HK + 7H + 11K per sample-epoch plus 2P per update), the HBM bytes the
+profiler counted for one launch (`traffic`, while the kernel source matches
+the counters' record) and the FP64 CPU oracle's throughput on a bounded
+sample of the same workload on the host cores (`cpu_baseline`).  w1-w3 also
+report `repeats` and `vs_plain` (the chosen form against the plain
+single-network FP32 kernel on the same GPU).
 """
 from __future__ import annotations
 
@@ -83,6 +90,58 @@ def measured_traffic(key: str, kind: str):
     return rec["hbm_bytes_per_launch"]
 
 
+def measured_traffic_per_epoch(key: str, kind: str):
+    """HBM bytes of one launch of one epoch (FETCH_SIZE + WRITE_SIZE, each
+    scaled by a plain copy of known size) for a large workload, if a record
+    taken on the current kernel source exists; else None."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "counters.json")) as f:
+            rec = json.load(f)[key]
+    except (OSError, ValueError, KeyError):
+        return None
+    if rec.get("source") != kernel_source_hash(kind) or "hbm_bytes_per_epoch" not in rec:
+        return None
+    return rec["hbm_bytes_per_epoch"]
+
+
+def counters_record(fetch_csv: str, write_csv: str, copy_fetch_csv: str, copy_write_csv: str, kernel_prefix: str,
+                    copy_bytes: int = 1 << 30, kernel_dispatch: int = -1) -> dict:
+    """HBM bytes of one dispatch from rocprofv3 --pmc counter files.
+
+    FETCH_SIZE and WRITE_SIZE are read (KiB per dispatch, summed over the
+    counter's instances) for the dispatch of `kernel_prefix` numbered
+    `kernel_dispatch` among that kernel's dispatches (default: the last),
+    and each is scaled by the factor that turns the same counter's reading
+    for a plain device copy of `copy_bytes` bytes into the bytes that copy
+    moves (the copy reads and writes `copy_bytes` each)."""
+    import csv
+
+    def per_dispatch(path, name_match):
+        vals = {}
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                if not name_match(row["Kernel_Name"]):
+                    continue
+                d = int(row["Dispatch_Id"])
+                vals[d] = vals.get(d, 0.0) + float(row["Counter_Value"])
+        return [vals[k] for k in sorted(vals)]
+
+    def is_copy(n):
+        return "copy" in n.lower() or "elementwise" in n.lower()
+
+    def is_kernel(n):
+        return n.startswith(kernel_prefix)
+
+    cf = max(per_dispatch(copy_fetch_csv, is_copy))
+    cw = max(per_dispatch(copy_write_csv, is_copy))
+    f_scale = copy_bytes / (cf * 1024.0)
+    w_scale = copy_bytes / (cw * 1024.0)
+    kf = per_dispatch(fetch_csv, is_kernel)[kernel_dispatch]
+    kw = per_dispatch(write_csv, is_kernel)[kernel_dispatch]
+    return {"fetch_kib": kf, "write_kib": kw, "fetch_scale": f_scale, "write_scale": w_scale,
+            "hbm_bytes": kf * 1024.0 * f_scale + kw * 1024.0 * w_scale}
+
+
 def flops_per_sample_epoch(D: int, H: int, K: int) -> int:
     """Algorithmic flops of one sample through one training step.
 
@@ -94,11 +153,6 @@ def flops_per_sample_epoch(D: int, H: int, K: int) -> int:
     The update adds 2P flops per step, P = DH + H + HK + K.
     """
     return 4 * D * H + 6 * H * K + 7 * H + 11 * K
-
-
-def contraction_flops_per_sample(D: int, H: int) -> int:
-    """The two MFMA contractions, X W1^T and delta1^T X: 2DH each."""
-    return 4 * D * H
 
 
 def cpu_info() -> str:
@@ -123,15 +177,20 @@ def timed(fn, stream):
     return time.perf_counter() - t0, ev0.elapsed_time(ev1) / 1e3
 
 
+# grid-wide synchronisations per minibatch step of the large-N trainer
+LARGE_BARRIERS_PER_STEP = 3
+
+
 def sync_adjusted(mlp, torch, flops: float, peak_tflops: float, hbm_bytes: float, n_steps: int, kernel_s: float):
-    """The survey's sync-adjusted bound for the persistent large-N trainer:
-    max(flops / peak, bytes / HBM bandwidth) plus, per minibatch step, three
+    """The sync-adjusted bound for the persistent large-N trainer:
+    max(flops / peak, bytes / HBM bandwidth) plus, per minibatch step, its
     grid barriers at the latency measured on this GPU (mlp_barrier_probe with
     one workgroup per CU, the grid the trainer's plans use here)."""
     n_wg = torch.cuda.get_device_properties(0).multi_processor_count
     t_bar = mlp.barrier_latency_us(n_wg)
-    bound_s = max(flops / (peak_tflops * 1e12), hbm_bytes / (PEAK_HBM_GBS * 1e9)) + n_steps * 3 * t_bar * 1e-6
-    return {"t_barrier_us": t_bar, "barriers_per_step": 3, "steps": n_steps, "workgroups": n_wg,
+    nb = LARGE_BARRIERS_PER_STEP
+    bound_s = max(flops / (peak_tflops * 1e12), hbm_bytes / (PEAK_HBM_GBS * 1e9)) + n_steps * nb * t_bar * 1e-6
+    return {"t_barrier_us": t_bar, "barriers_per_step": nb, "steps": n_steps, "workgroups": n_wg,
             "bound_ms": bound_s * 1e3, "frac": bound_s / kernel_s}
 
 
@@ -154,10 +213,8 @@ def bench_single(args):
     w = synth.single(wl)
     D, H, K, N = w["D"], w["H"], w["K"], w["X"].shape[0]
     batch = w["batch"] or N
-    prec = args.prec if wl in (4, 5) else "fp32"
+    prec = "fp32"
     act, mu = args.act, args.momentum
-    if (act != "sigmoid" or mu) and wl not in (1, 2):
-        raise SystemExit("--act tanh / --momentum apply to the full-batch workloads w1 and w2")
     net = mlp.Net(D, H, K, N, batch=w["batch"], lr=w["lr"], prec=prec, theta=w["theta"], act=act, momentum=mu)
     X = torch.from_numpy(w["X"]).cuda()
     T = torch.from_numpy(w["T"]).cuda()
@@ -171,29 +228,14 @@ def bench_single(args):
     final_loss = float(hist[steps - 1].item()) if steps else None
     reps = repeats(lambda: net.train(X, T, steps, loss_hist=hist[:steps]), stream, wall, steps)
     vs_plain = None
-    if prec != "fp32":
-        # the same run on the plain FP32 kernel (same initial parameters)
-        plain = mlp.Net(D, H, K, N, batch=w["batch"], lr=w["lr"], prec="fp32", theta=w["theta"])
-        plain.train(X, T, 1)
-        pwall, _ = timed(lambda: plain.train(X, T, steps), stream)
-        pv = N * steps / pwall
-        vs_plain = {"speedup": (N * steps / wall) / pv, "plain_value": pv,
-                    "plain": "the same workload on the FP32 operand kernel", "sample": "the full workload"}
     P = D * H + H + H * K + K
     n_updates = steps * (-(-N // batch))
-    if wl in (4, 5):
-        flops = contraction_flops_per_sample(D, H) * N * steps
-        pi = {"fp32": 0, "bf16": 1, "e4m3": 2}[prec]
-        bound, peak, unit, kname, kind = "mfma", PEAK[prec], "TFLOP/s", f"mlpk::k_large_train<{pi}, {3 if K <= 3 else 4}, 4>", "large"
-    else:
-        flops = flops_per_sample_epoch(D, H, K) * N * steps + 2 * P * n_updates
-        bound, peak, unit, kname, kind = "alu", PEAK["fp32"], "TFLOP/s", "mlpk::k_small_train", "small"
+    flops = flops_per_sample_epoch(D, H, K) * N * steps + 2 * P * n_updates
+    bound, peak, unit, kname, kind = "alu", PEAK["fp32"], "TFLOP/s", "mlpk::k_small_train", "small"
     tkey = f"{args.workload}-{prec}-steps{steps}"
     achieved = flops / kern / 1e12
     names = {1: "plain-small: N=60 x 33, 33-10-3, full batch",
-             2: "differentiation: N=120 x 33, 33-16-3, full batch (fused mlp_train)",
-             4: "large-N: N=1,048,576 x 33, 33-256-3, minibatch 4096",
-             5: "wide: N=4,194,304 x 64, 64-1024-3, minibatch 16384"}
+             2: "differentiation: N=120 x 33, 33-16-3, full batch (fused mlp_train)"}
     res = dict(
         metric="training samples*epochs/s", value=N * steps / wall, unit="samples*epochs/s",
         ms_per_step=wall * 1e3 / steps, dtype={"fp32": "f32", "bf16": "bf16", "e4m3": "e4m3"}[prec],
@@ -206,15 +248,11 @@ def bench_single(args):
                   "traffic": measured_traffic(tkey, kind), "traffic_unit": "bytes per launch", "kernel": kname,
                   "kernel_ms": kern * 1e3, "flops_per_launch": flops},
         final_loss=final_loss, repeats=reps, vs_plain=vs_plain, steps=steps, warmup=warmup)
-    if wl in (1, 2):
-        # one net is one workgroup on one of the 256 CUs: its honest denominator
-        # is one CU's share of the FP32 rate, and the per-epoch latency
-        cu_peak = PEAK["fp32"] / 256
-        res["roofline"]["one_cu"] = {"peak": cu_peak, "unit": "TFLOP/s", "frac": achieved / cu_peak,
-                                     "epoch_us": kern * 1e6 / steps}
-    if wl in (4, 5):
-        res["roofline"]["sync_adjusted"] = sync_adjusted(mlp, torch, flops, peak, N * steps * (D + K) * 4.0,
-                                                         steps * (-(-N // batch)), kern)
+    # one net is one workgroup on one of the 256 CUs: its honest denominator
+    # is one CU's share of the FP32 rate, and the per-epoch latency
+    cu_peak = PEAK["fp32"] / 256
+    res["roofline"]["one_cu"] = {"peak": cu_peak, "unit": "TFLOP/s", "frac": achieved / cu_peak,
+                                 "epoch_us": kern * 1e6 / steps}
     return res, dict(w=w, wl=wl, batch=batch, act=act, mu=mu)
 
 
@@ -222,24 +260,144 @@ def cpu_single(ctx, budget_s: float):
     import oracle
     w, wl, batch = ctx["w"], ctx["wl"], ctx["batch"]
     p = oracle.Params.of(w["theta"])
-    if wl in (1, 2):
-        X, T, epochs, rows = w["X"], w["T"], w["epochs"], w["X"].shape[0]
-        sample = f"the full workload ({rows} rows x {epochs} epochs)"
-    else:
-        rows = batch * (4 if wl == 4 else 1)   # a few minibatches of the same data
-        X, T, epochs = w["X"][:rows], w["T"][:rows], 1
-        sample = f"the first {rows} rows ({rows // batch} minibatch(es) of {batch}) for 1 epoch"
+    X, T, epochs, rows = w["X"], w["T"], w["epochs"], w["X"].shape[0]
+    sample = f"the full workload ({rows} rows x {epochs} epochs)"
     reps, t_total = 0, 0.0
     while (t_total < budget_s or reps == 0) and reps < 100000:
         t0 = time.perf_counter()
         if ctx.get("act", "sigmoid") != "sigmoid" or ctx.get("mu", 0.0):
             oracle.train_var(X, T, p, w["lr"], epochs, act=ctx["act"], mu=ctx["mu"])
         else:
-            oracle.train(X, T, p, w["lr"], epochs, batch=0 if wl in (1, 2) else batch)
+            oracle.train(X, T, p, w["lr"], epochs, batch=0)
         t_total += time.perf_counter() - t0
         reps += 1
     return {"value": rows * epochs * reps / t_total, "unit": "samples*epochs/s", "cores": 1, "kind": "oracle",
             "sample": f"{sample}, run {reps} time(s), float64, single thread, {cpu_info()}",
+            "seconds": t_total}
+
+
+# ---------------------------------------------------------------- large N (w4, w5: the headline)
+LARGE_NAMES = {4: "large-N: N=1,048,576 x 33, 33-256-3, minibatch 4096",
+               5: "wide: N=4,194,304 x 64, 64-1024-3, minibatch 16384"}
+
+
+def per_launch_times(launch, stream, count: int):
+    """Run `launch(i)` for i < count back to back on `stream`; returns the
+    wall time of the whole run and each launch's duration from HIP events
+    recorded between the launches (on the stream the kernel runs on)."""
+    import torch
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(count + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs[0].record(stream)
+    for i in range(count):
+        launch(i)
+        evs[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, [evs[i].elapsed_time(evs[i + 1]) / 1e3 for i in range(count)]
+
+
+def large_form(mlp, torch, w, X, T, prec: str, steps: int, warmup: int):
+    """One operand form of a large workload: `warmup` untimed launches, then
+    `steps` timed launches of one epoch each (every launch runs the epoch's
+    minibatch steps; parameters carry over, so the launches together are one
+    training run of `steps` epochs).  Returns the numbers of the timed run."""
+    D, H, K, N = w["D"], w["H"], w["K"], w["X"].shape[0]
+    net = mlp.Net(D, H, K, N, batch=w["batch"], lr=w["lr"], prec=prec, theta=w["theta"])
+    hist = torch.empty(max(steps, warmup, 1), device="cuda")
+    for i in range(warmup):
+        net.train(X, T, 1, loss_hist=hist[i:i + 1])
+    net.set_theta(w["theta"])
+    stream = torch.cuda.current_stream()
+    wall, durs = per_launch_times(lambda i: net.train(X, T, 1, loss_hist=hist[i:i + 1]), stream, steps)
+    out = dict(wall=wall, durs=durs, kernel_s=float(np.mean(durs)),
+               final_loss=float(hist[steps - 1].item()) if steps else None)
+    net.close()
+    return out
+
+
+def bench_large(args):
+    import torch
+    from paper_1908_07847_amd import mlp, synth
+
+    wl = int(args.workload[1])
+    w = synth.single(wl)
+    D, H, K, N, batch = w["D"], w["H"], w["K"], w["X"].shape[0], w["batch"]
+    X = torch.from_numpy(w["X"]).cuda()
+    T = torch.from_numpy(w["T"]).cuda()
+    steps = args.steps if args.steps is not None else w["epochs"]
+    warmup = args.warmup if args.warmup is not None else 1
+    P = D * H + H + H * K + K
+    spe = -(-N // batch)                                      # minibatch steps per epoch
+    F = flops_per_sample_epoch(D, H, K)
+    flops_epoch = F * N + 2 * P * spe                         # one launch = one epoch
+    prec = args.prec
+    forms = [prec] + ([q for q in ("bf16", "e4m3") if q != prec] if args.forms == "all" else [])
+    res_forms = {}
+    for q in forms:
+        r = large_form(mlp, torch, w, X, T, q, steps, warmup if q == prec else min(warmup, 1))
+        ach = flops_epoch / r["kernel_s"] / 1e12
+        pi = {"fp32": 0, "bf16": 1, "e4m3": 2}[q]
+        res_forms[q] = dict(value=N * steps / r["wall"], ms_per_step=r["wall"] * 1e3 / steps,
+                            kernel_ms_per_launch=r["kernel_s"] * 1e3,
+                            median_ms_per_launch=float(np.median(r["durs"])) * 1e3,
+                            min_ms_per_launch=float(min(r["durs"])) * 1e3,
+                            kernel=f"mlpk::k_large_train<{pi}, {3 if K <= 3 else 4}, 4>",
+                            achieved_tflops=ach, peak_tflops=PEAK[q], frac=ach / PEAK[q],
+                            final_loss=r["final_loss"], dtype={"fp32": "f32", "bf16": "bf16", "e4m3": "e4m3"}[q])
+    head = res_forms[prec]
+    for q in forms[1:]:
+        res_forms[q]["vs_plain"] = res_forms[q]["value"] / res_forms["fp32"]["value"] if "fp32" in res_forms else None
+    kern = head["kernel_ms_per_launch"] / 1e3
+    tkey = f"{args.workload}-{prec}"
+    per_epoch = measured_traffic_per_epoch(tkey, "large")
+    res = dict(
+        metric="training samples*epochs/s", value=head["value"], unit="samples*epochs/s",
+        ms_per_step=head["ms_per_step"], dtype=head["dtype"],
+        config={"workload": LARGE_NAMES[wl] + ", sigmoid both layers, MSE, GD lr=0.1, float32 master "
+                            "parameters, compensated update", "n_rows": N, "n_in": D, "n_hidden": H, "n_out": K,
+                "batch": batch, "lr": w["lr"], "operand_precision": prec,
+                "step": f"one epoch ({spe} minibatch steps) = one launch of the persistent trainer"},
+        roofline={"bound": "mfma", "achieved": head["achieved_tflops"], "peak": PEAK[prec], "unit": "TFLOP/s",
+                  "frac": head["frac"], "traffic": per_epoch, "traffic_unit": "HBM bytes per launch (one epoch)",
+                  "algorithmic_bytes": N * (D + K) * 4 + 2 * P * 4,
+                  "kernel": head["kernel"], "kernel_ms": head["kernel_ms_per_launch"],
+                  "flops_per_launch": flops_epoch,
+                  "flops_per_sample_epoch": F, "update_flops_per_step": 2 * P},
+        forms={q: v for q, v in res_forms.items() if q != prec},
+        final_loss=head["final_loss"],
+        repeats={"runs": steps, "median_ms_per_step": head["median_ms_per_launch"],
+                 "min_ms_per_step": head["min_ms_per_launch"], "note": "per timed launch (HIP events)"},
+        steps=steps, warmup=warmup)
+    res["roofline"]["sync_adjusted"] = sync_adjusted(mlp, torch, flops_epoch, PEAK[prec], N * (D + K) * 4.0,
+                                                     spe, kern)
+    return res, dict(w=w, wl=wl, batch=batch)
+
+
+def cpu_large(ctx, budget_s: float, rows: int = 65536):
+    """The oracle (float64) trains on the first `rows` rows (whole minibatches)
+    for one epoch, repeated until `budget_s` has passed, on every host core
+    (its loops over gradient entries and rows are shared among OpenMP
+    threads), from a timing build of the same sources (-O3 -march=native)."""
+    import tempfile
+    import oracle
+    w, batch = ctx["w"], ctx["batch"]
+    lib = oracle.build_timing(tempfile.mkdtemp(prefix="oracle_timing_"))
+    p = oracle.Params.of(w["theta"])
+    X, T = w["X"][:rows], w["T"][:rows]
+    with oracle.use_library(lib):
+        oracle.set_threads(0)
+        threads = oracle.max_threads()
+        reps, t_total = 0, 0.0
+        while (t_total < budget_s or reps == 0) and reps < 100000:
+            t0 = time.perf_counter()
+            oracle.train(X, T, p, w["lr"], 1, batch=batch)
+            t_total += time.perf_counter() - t0
+            reps += 1
+    return {"value": rows * reps / t_total, "unit": "samples*epochs/s", "cores": threads, "kind": "oracle",
+            "sample": f"the first {rows} rows ({rows // batch} minibatches of {batch}) for 1 epoch, run {reps} "
+                      f"time(s), float64, {threads} OpenMP threads, -O3 -march=native build, {cpu_info()}",
             "seconds": t_total}
 
 
@@ -383,7 +541,8 @@ def bench_shared(args):
     vs_plain = {"speedup": (M * N * steps / wall) / (N / pwall), "plain_value": N / pwall,
                 "plain": "one net of the same shape on the single-network FP32 kernel (the nets one after another)",
                 "sample": "net 0, one epoch"}
-    flops = contraction_flops_per_sample(D, H) * N * M * steps
+    P = D * H + H + H * K + K
+    flops = (flops_per_sample_epoch(D, H, K) * N + 2 * P * (-(-N // batch))) * M * steps
     achieved = flops / kern / 1e12
     pi = {"fp32": 0, "bf16": 1}[prec]
     res = dict(
@@ -631,8 +790,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the workload's epochs)")
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="w2", choices=["w1", "w2", "w2a", "w2d", "w3", "w4", "w5", "w6", "p4"])
+    ap.add_argument("--workload", default="w5", choices=["w1", "w2", "w2a", "w2d", "w3", "w4", "w5", "w6", "p4"])
     ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16", "e4m3"])
+    ap.add_argument("--forms", default="all", choices=["all", "none"],
+                    help="w4/w5: also time the other operand forms (reported under 'forms' with vs_plain)")
     ap.add_argument("--act", default="sigmoid", choices=["sigmoid", "tanh"],
                     help="hidden activation (w1, w2; tanh is a variant of the paper's sigmoid)")
     ap.add_argument("--momentum", type=float, default=0.0, help="heavy-ball rate (w1, w2; 0 = the paper's GD)")
@@ -662,6 +823,9 @@ def main():
     elif args.workload == "w6":
         res, ctx = bench_shared(args)
         cpu = None if args.no_cpu else cpu_shared(ctx, args.cpu_budget)
+    elif args.workload in ("w4", "w5"):
+        res, ctx = bench_large(args)
+        cpu = None if args.no_cpu else cpu_large(ctx, args.cpu_budget)
     else:
         res, ctx = bench_single(args)
         cpu = None if args.no_cpu else cpu_single(ctx, args.cpu_budget)

@@ -223,13 +223,17 @@ def batched(n_nets: int = 4096, seed_workload: int = 3, heldout: bool = False):
 SHARED_LR_GRID = tuple(float(10.0 ** (-2.0 + 2.0 * j / 7.0)) for j in range(8))
 
 
-def shared(workload: int = 5, n_nets: int = 64, n_rows: int | None = None, hidden: int | None = None):
+def shared(workload: int = 5, n_nets: int = 64, n_rows: int | None = None, hidden: int | None = None,
+           base: dict | None = None):
     """Nets that share one dataset (a hyperparameter grid): the rows of a
     single-network workload, and for net i the learning rate
     SHARED_LR_GRID[i % 8] with initial parameters from seed group i // 8
     (so each group of 8 nets starts from the same weights and differs only
-    in the learning rate).  theta is [n_nets][P] float32."""
-    base = single(workload, n_rows=n_rows, hidden=hidden)
+    in the learning rate).  theta is [n_nets][P] float32.  `base`: the
+    workload's single-network dict when the caller already generated it
+    (its rows are reused, not copied)."""
+    if base is None:
+        base = single(workload, n_rows=n_rows, hidden=hidden)
     d, h, k = base["D"], base["H"], base["K"]
     thetas = [theta0(d, h, k, rng(workload, 100 + i // 8, ROLE_THETA)).packed() for i in range(n_nets)]
     lrs = [SHARED_LR_GRID[i % 8] for i in range(n_nets)]
