@@ -31,7 +31,12 @@
  *     thread-local message for the last failure.
  *   - Device pointers must be 4-byte aligned; X, T, the workspace and the
  *     batched item table must be 16-byte aligned.
- *   - NaN/Inf in inputs propagate; nothing checks for them on the hot path.
+ *   - NaN/Inf in inputs propagate; nothing checks for them on the hot path
+ *     unless the configuration sets MLP_F_CHECK_FINITE.
+ *   - Errors that only the device can see (a grid-wide wait of the
+ *     minibatch trainer that gave up, the finite check) are written to a
+ *     status block at the head of the training workspace; mlp_query_status
+ *     and mlp_workspace_status synchronise the stream and report them.
  *
  * Beyond the method, the library offers the build's own extensions, each
  * marked where it is declared: reduced-precision operands for the two large
@@ -57,7 +62,11 @@ typedef enum {
   MLP_ERR_ALIGN = 3,       /* device pointer not 16-byte aligned */
   MLP_ERR_WORKSPACE = 4,   /* workspace missing or too small */
   MLP_ERR_UNSUPPORTED = 5, /* valid request no kernel here implements */
-  MLP_ERR_HIP = 6          /* the HIP runtime reported an error */
+  MLP_ERR_HIP = 6,         /* the HIP runtime reported an error */
+  MLP_ERR_TIMEOUT = 7,     /* a grid-wide wait of the last training launch
+                            * gave up (see mlp_set_wait_limit): parameters
+                            * and losses of that launch are not valid */
+  MLP_ERR_NONFINITE = 8    /* MLP_F_CHECK_FINITE found a NaN or infinity */
 } mlp_status;
 
 /* Operand precision of the two large contractions (X W1^T and delta1^T X).
@@ -71,6 +80,15 @@ enum {
   /* Compensated (Kahan) float32 parameter update, using the caller's
    * compensation buffer.  Same update, computed more exactly. */
   MLP_F_COMPENSATED = 1u,
+  /* Accepted for interface completeness: every kernel here reduces in a
+   * fixed order, so results are bitwise repeatable with or without it. */
+  MLP_F_DETERMINISTIC = 2u,
+  /* After each mlp_train / mlp_train_shared launch, scan the trained
+   * parameters (and loss_hist, when given) for NaN or infinity; a hit is
+   * reported as MLP_ERR_NONFINITE by mlp_query_status /
+   * mlp_workspace_status.  One extra pass over the parameters; off the
+   * training loop. */
+  MLP_F_CHECK_FINITE = 4u,
   /* Hidden neurons apply tanh (derivative 1 - tanh^2) instead of the
    * sigmoid of Equation 1; the output neurons stay sigmoid.  A variant of
    * section 2.2's network (the paper's neurons are all sigmoid), honoured by
@@ -151,6 +169,29 @@ mlp_status mlp_step(mlp_net *net, mlp_params grads, float lr, void *stream);
  * then b epochs is bitwise equal to training a+b epochs. */
 mlp_status mlp_train(mlp_net *net, const float *X, const float *T, int32_t epochs,
                      float *loss_hist, void *stream);
+
+/* Status of the last mlp_train launch on this handle's workspace: waits for
+ * the stream, then returns MLP_ERR_TIMEOUT if a grid-wide wait of the
+ * minibatch / large-shape trainer gave up (the launch then ended early in
+ * every workgroup; loss_hist entries from the failing epoch on are NaN and
+ * the parameters may hold a partial update), MLP_ERR_NONFINITE if the
+ * finite check (MLP_F_CHECK_FINITE) found a NaN or infinity, else MLP_OK.
+ * Valid until the next training launch on the same workspace. */
+mlp_status mlp_query_status(mlp_net *net, void *stream);
+
+/* The same for a caller-held training workspace (mlp_train_shared, or a
+ * handle's workspace): waits for the stream and reads the status block at
+ * the workspace's head.  ws_bytes >= 2048, workspace 16-byte aligned. */
+mlp_status mlp_workspace_status(const void *workspace, size_t ws_bytes, void *stream);
+
+/* Longest time one grid-wide wait of the minibatch / large-shape trainer
+ * (and of mlp_barrier_probe) may take before it gives up, in microseconds
+ * of the device's constant-rate wall clock; process-wide, read at launch.
+ * Negative: the default, 5 s.  0: a wait that is not already satisfied
+ * gives up at once (for testing the failure path).  A launch whose wait
+ * gives up ends early in every workgroup -- nothing hangs -- and reports
+ * MLP_ERR_TIMEOUT through mlp_query_status / mlp_workspace_status. */
+mlp_status mlp_set_wait_limit(int64_t microseconds);
 
 /* Class predictions: the network outputs Y = sigma(sigma(X W1^T + b1) W2^T
  * + b2) of section 2.2 read as a class, the index of the largest output
@@ -233,7 +274,8 @@ mlp_status mlp_shared_workspace_size(const mlp_config *cfg /*host*/, int32_t n_n
  *   comp       [n_nets][P] compensation terms (needed iff MLP_F_COMPENSATED)
  *   loss_hist  [n_nets][epochs] per-epoch losses as in mlp_train, or NULL
  *   workspace  >= mlp_shared_workspace_size bytes, 16-byte aligned; its
- *              contents on entry do not matter
+ *              contents on entry do not matter; its head holds the
+ *              launch's status block (mlp_workspace_status)
  * Results of net i equal mlp_train of net i alone up to float summation
  * order; for a fixed device and n_nets they are bitwise repeatable. */
 mlp_status mlp_train_shared(const mlp_config *cfg /*host*/, int32_t n_nets, const float *lr /*host*/,
@@ -314,12 +356,28 @@ mlp_status mlp_deep_train(const float *X, const float *T, int64_t n, int32_t n_l
  *   n_workgroups  1 .. the device's CU count
  *   rounds        0 .. 1,000,000
  *   workspace     >= MLP_BARRIER_PROBE_WS_BYTES device bytes, 16-byte
- *                 aligned; overwritten (barrier counters).  A barrier that
- *                 does not complete within its spin limit sets the 32-bit
- *                 word at index 16 to nonzero instead of hanging.
+ *                 aligned; overwritten (barrier counters).  A barrier wait
+ *                 that does not complete within the wait limit
+ *                 (mlp_set_wait_limit) sets the 32-bit word at index 16 to
+ *                 nonzero and ends the launch instead of hanging;
+ *                 mlp_workspace_status reports it.
  * Asynchronous on the stream; argument errors return before any launch. */
 mlp_status mlp_barrier_probe(int32_t n_workgroups, int32_t rounds, void *workspace, size_t ws_bytes,
                              void *stream);
+
+/* Accuracy probe of the matrix-core contraction the minibatch trainer runs
+ * for its two large products (measurement, no part of training):
+ *   C[M][N] = sum over k < Kd of A[M][Kd] B[N][Kd]
+ * on the instruction the trainer uses for operand precision prec (float32:
+ * 16x16x4 steps; bf16 and e4m3: 16x16x32 steps), with its operand layout and
+ * its chained float32 accumulation over k.  A and B hold float32 values that
+ * the kernel converts to the format (round to nearest even; e4m3 saturates
+ * at +-448, no scale); values already representable convert exactly, so C
+ * then differs from the exact sum only by the matrix core's own summation.
+ * M, N multiples of 16 (<= 4096), Kd a multiple of 32 (<= 2^20); device
+ * pointers, 4-byte aligned, row-major; C is overwritten. */
+mlp_status mlp_mfma_probe(int32_t prec, const float *A, const float *B, float *C, int32_t M, int32_t N,
+                          int32_t Kd, void *stream);
 
 /* ---- launch-shape hints -------------------------------------------------- */
 

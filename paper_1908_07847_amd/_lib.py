@@ -10,9 +10,12 @@ import ctypes
 import os
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libmlp.so")
+# MLP_LIBRARY names another build of the same library (the host-sanitizer
+# build the ABI tests run against); default: the in-tree libmlp.so.
+LIB_PATH = os.environ.get("MLP_LIBRARY") or os.path.join(_PKG, "libmlp.so")
 
-MLP_OK, MLP_ERR_ARG, MLP_ERR_SHAPE, MLP_ERR_ALIGN, MLP_ERR_WORKSPACE, MLP_ERR_UNSUPPORTED, MLP_ERR_HIP = range(7)
+(MLP_OK, MLP_ERR_ARG, MLP_ERR_SHAPE, MLP_ERR_ALIGN, MLP_ERR_WORKSPACE, MLP_ERR_UNSUPPORTED, MLP_ERR_HIP,
+ MLP_ERR_TIMEOUT, MLP_ERR_NONFINITE) = range(9)
 PREC = {"fp32": 0, "bf16": 1, "e4m3": 2}
 MLP_F_COMPENSATED = 1
 SMALL_MAX_ROWS, SMALL_MAX_HIDDEN, SMALL_MAX_IN, SMALL_MAX_OUT = 128, 64, 48, 4
@@ -49,14 +52,14 @@ class LaunchHint(ctypes.Structure):
 assert ctypes.sizeof(BatchItem) == 32 and ctypes.sizeof(Config) == 40 and ctypes.sizeof(LaunchHint) == 16
 
 # Every symbol include/mlp.h declares.
-F_COMPENSATED, F_TANH_HIDDEN = 1, 8   # mlp_config flags
+F_COMPENSATED, F_DETERMINISTIC, F_CHECK_FINITE, F_TANH_HIDDEN = 1, 2, 4, 8   # mlp_config flags
 BARRIER_PROBE_WS_BYTES = 2048   # MLP_BARRIER_PROBE_WS_BYTES
 
 SYMBOLS = ["mlp_workspace_size", "mlp_init", "mlp_destroy", "mlp_forward", "mlp_backward", "mlp_step",
            "mlp_train", "mlp_predict", "mlp_train_batched", "mlp_eval_batched", "mlp_shared_workspace_size",
            "mlp_train_shared", "mlp_barrier_probe", "mlp_set_momentum", "mlp_dense_forward", "mlp_dense_backward",
-           "mlp_update", "mlp_mse_grad", "mlp_deep_train",
-           "mlp_set_launch_hint", "mlp_status_string", "mlp_last_error"]
+           "mlp_update", "mlp_mse_grad", "mlp_deep_train", "mlp_query_status", "mlp_workspace_status",
+           "mlp_set_wait_limit", "mlp_mfma_probe", "mlp_set_launch_hint", "mlp_status_string", "mlp_last_error"]
 
 
 def _load():
@@ -88,6 +91,10 @@ def _load():
     lib.mlp_update.argtypes = [vp, vp, vp, i64, f32, vp]
     lib.mlp_mse_grad.argtypes = [vp, vp, i64, i32, vp, vp, vp]
     lib.mlp_deep_train.argtypes = [vp, vp, i64, i32, ctypes.POINTER(i32), i32, vp, vp, f32, i32, vp, vp]
+    lib.mlp_query_status.argtypes = [vp, vp]
+    lib.mlp_workspace_status.argtypes = [vp, ctypes.c_size_t, vp]
+    lib.mlp_set_wait_limit.argtypes = [i64]
+    lib.mlp_mfma_probe.argtypes = [i32, vp, vp, vp, i32, i32, i32, vp]
     for name in SYMBOLS:
         if name not in ("mlp_status_string", "mlp_last_error"):
             getattr(lib, name).restype = ctypes.c_int

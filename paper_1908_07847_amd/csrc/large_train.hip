@@ -55,7 +55,8 @@ struct LargeArgs {
   float *lossp;      // [Gi][M] partial squared errors
   float *amax;       // [2][G] W1 amax partials, [2][G] delta1 amax partials, [G] |X|
   float *acc;        // [M]: epoch loss accumulators
-  unsigned *bar;     // grid-barrier counters (see GridSync)
+  unsigned *bar;     // grid-barrier counters and status words (see GridSync)
+  uint64_t wait_limit;  // wall-clock ticks a grid-barrier wait may take
   int64_t N, b;
   int D, H, Hp, K, Gi, Gj, M, RBP, epochs, steps_per_epoch;
   float lr[kMaxNets];  // learning rate of each net
@@ -68,13 +69,23 @@ struct LargeArgs {
 // contents visible device-wide (one agent-scope release per XCD instead of
 // one per workgroup) and bumps the global count; everyone waits for the
 // global count and then acquires.  Counters only grow: the k-th barrier waits
-// for k arrivals per member.  A spin limit turns a barrier that never
-// completes into a sticky error flag instead of a hang.
+// for k arrivals per member.
 //
-// Counter block (unsigned, 16 apart so each sits on its own 64-byte line):
-//   [0] XCD-leader arrivals, [16] error flag, [16*(2+x)] arrivals on XCD x,
-//   [16*(10+x)] members on XCD x, [16*18] registrations.
-constexpr int kBarWords = 16 * 19;
+// Every wait is bounded in time: a wait that is still unsatisfied after
+// `limit` ticks of the constant-rate wall clock sets the sticky give-up word
+// and returns false, and every other wait returns false as soon as it sees
+// that word.  The trainer then leaves its step loop in every workgroup (no
+// workgroup waits on one that has left), so a grid that cannot complete a
+// barrier ends with an error the host can read instead of hanging.
+//
+// Counter block (unsigned, 16 apart so each sits on its own 64-byte line),
+// at the head of the workspace:
+//   [0] XCD-leader arrivals, [16] give-up word (the status the host reads),
+//   [16*(2+x)] arrivals on XCD x, [16*(10+x)] members on XCD x,
+//   [16*18] registrations, [16*19] non-finite word (finite check).
+constexpr int kBarWords = 16 * 20;
+constexpr int kGiveUpWord = 16;
+constexpr int kNonFiniteWord = 16 * 19;
 
 __device__ __forceinline__ unsigned xcc_id() {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -87,36 +98,48 @@ __device__ __forceinline__ unsigned xcc_id() {
 struct GridSync {
   unsigned *bar;
   unsigned x, members, n_xcd, k;
+  uint64_t limit;  // wall-clock ticks one wait may take
   __device__ bool spin(unsigned *ctr, unsigned target) {
+    // the clock is first read at the first check (64 spins in), off the
+    // path of a barrier that completes quickly
+    uint64_t t0 = 0;
+    bool timing = false;
     unsigned spins = 0;
     while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       __builtin_amdgcn_s_sleep(1);
-      if ((++spins & 1023u) == 0) {
-        if (__hip_atomic_load(bar + 16, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
-        if (spins > (1u << 22)) {
-          __hip_atomic_store(bar + 16, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if ((++spins & 63u) == 0 || limit == 0) {
+        if (__hip_atomic_load(bar + kGiveUpWord, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+        const uint64_t now = wall_clock64();
+        if (!timing) {
+          t0 = now;
+          timing = true;
+        }
+        if (now - t0 >= limit) {
+          __hip_atomic_store(bar + kGiveUpWord, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           return false;
         }
       }
     }
     return true;
   }
-  // every workgroup registers its XCD once (thread 0 only)
-  __device__ void init(unsigned *b, unsigned G) {
+  // every workgroup registers its XCD once (thread 0 only); false: gave up
+  __device__ bool init(unsigned *b, unsigned G, uint64_t wait_limit) {
     bar = b;
+    limit = wait_limit;
     x = xcc_id();
     k = 0;
     __hip_atomic_fetch_add(bar + 16 * (10 + x), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_fetch_add(bar + 16 * 18, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    spin(bar + 16 * 18, G);
+    const bool ok = spin(bar + 16 * 18, G);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     members = __hip_atomic_load(bar + 16 * (10 + x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     n_xcd = 0;
     for (int q = 0; q < 8; ++q)
       n_xcd += __hip_atomic_load(bar + 16 * (10 + q), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0u;
+    return ok;
   }
-  // thread 0 only, between two __syncthreads
-  __device__ void arrive_and_wait() {
+  // thread 0 only, between two __syncthreads; false: gave up
+  __device__ bool arrive_and_wait() {
     k += 1;
     const unsigned old =
         __hip_atomic_fetch_add(bar + 16 * (2 + x), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -124,8 +147,9 @@ struct GridSync {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    spin(bar, k * n_xcd);
+    const bool ok = spin(bar, k * n_xcd);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return ok;
   }
 };
 
@@ -302,18 +326,23 @@ __global__ __launch_bounds__(kLT, NHM <= 2 ? 2 : 1) void k_large_train(LargeArgs
   char *dstb = smb + L.dst();
   float *red = reinterpret_cast<float *>(smb + L.red());
 
+  // ok_s: 0 once a grid-barrier wait of this workgroup has given up
+  __shared__ int ok_s;
   GridSync gs;
-  if (tid == 0) gs.init(a.bar, (unsigned)G);
+  if (tid == 0) ok_s = gs.init(a.bar, (unsigned)G, a.wait_limit) ? 1 : 0;
   __syncthreads();
-  auto barrier = [&]() {
+  bool ok = ok_s != 0;
+  // false when the barrier gave up (uniform over the workgroup)
+  auto barrier = [&]() -> bool {
     __syncthreads();  // this workgroup's stores are complete (in L2) before it arrives
-    if (tid == 0) gs.arrive_and_wait();
+    if (tid == 0 && !gs.arrive_and_wait()) ok_s = 0;
     __syncthreads();
+    return ok_s != 0;
   };
 
   // ---- one-time: dataset amax of |X| for the e4m3 X scale
   int ex = 0;
-  if (PREC == 2) {
+  if (PREC == 2 && ok) {
     float m = 0.0f;
     const int64_t nx = a.N * D;
     for (int64_t q = (int64_t)bid * kLT + tid; q < nx; q += (int64_t)G * kLT) m = fmaxf(m, fabsf(a.X[q]));
@@ -321,7 +350,7 @@ __global__ __launch_bounds__(kLT, NHM <= 2 ? 2 : 1) void k_large_train(LargeArgs
     if (lane == 0) red[wave] = m;
     __syncthreads();
     if (tid == 0) a.amax[4 * G + bid] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
-    barrier();
+    ok = barrier();
     float mm = 0.0f;
     for (int g = 0; g < G; ++g) mm = fmaxf(mm, a.amax[4 * G + g]);
     ex = e4m3_scale_exp(mm);
@@ -426,7 +455,8 @@ __global__ __launch_bounds__(kLT, NHM <= 2 ? 2 : 1) void k_large_train(LargeArgs
   __syncthreads();
 
   const int total_steps = a.epochs * a.steps_per_epoch;
-  for (int step = 0; step < total_steps; ++step) {
+  int step = 0;
+  for (; ok && step < total_steps; ++step) {
     const int e = step / a.steps_per_epoch, sidx = step - e * a.steps_per_epoch;
     const int64_t r0 = (int64_t)sidx * a.b;
     const int64_t m = min((int64_t)a.b, a.N - r0);      // rows in this minibatch
@@ -696,7 +726,7 @@ __global__ __launch_bounds__(kLT, NHM <= 2 ? 2 : 1) void k_large_train(LargeArgs
         for (int c0 = 0; c0 < RBP; c0 += kRC)
           z2_chunk(c0, [&](int rr, int k, float v) { a.z2p[(rowbase + c0 + rr) * 4 + k] = v; });
       }
-      barrier();
+      if (!barrier()) { ok = false; break; }
     }
 
     // ================================================================ phase 2
@@ -922,7 +952,7 @@ __global__ __launch_bounds__(kLT, NHM <= 2 ? 2 : 1) void k_large_train(LargeArgs
               fmaxf(fmaxf(red[8], red[9]), fmaxf(red[10], red[11]));
       }
     }
-    barrier();
+    if (!barrier()) { ok = false; break; }
 
     // ================================================================ phase 3
     // Sum the Gi partials of this workgroup's slice of the parameters (of all
@@ -1000,7 +1030,14 @@ __global__ __launch_bounds__(kLT, NHM <= 2 ? 2 : 1) void k_large_train(LargeArgs
         }
       }
     }
-    barrier();
+    if (!barrier()) { ok = false; break; }
+  }
+  // a wait gave up: every workgroup has left the step loop; the losses of
+  // the epoch that failed and of every later epoch are NaN (the parameters
+  // may hold a partial update; the host reads the give-up word)
+  if (!ok && bid < a.M && tid == 0 && a.loss_hist) {
+    const int e0 = min(step, total_steps - 1) / a.steps_per_epoch;
+    for (int e = max(e0, 0); e < a.epochs; ++e) a.loss_hist[(int64_t)bid * a.epochs + e] = __builtin_nanf("");
   }
 }
 
@@ -1013,15 +1050,68 @@ __global__ void k_zero_u32(unsigned *p, int n) {
 // time over its rounds is the latency one barrier adds to a step when every
 // workgroup arrives together (the trainer pays three per step, plus the
 // wait for its slowest workgroup).
-__global__ __launch_bounds__(kLT) void k_barrier_probe(unsigned *bar, int rounds) {
+__global__ __launch_bounds__(kLT) void k_barrier_probe(unsigned *bar, int rounds, uint64_t wait_limit) {
+  __shared__ int ok_s;
   GridSync gs;
-  if (threadIdx.x == 0) gs.init(bar, gridDim.x);
+  if (threadIdx.x == 0) ok_s = gs.init(bar, gridDim.x, wait_limit) ? 1 : 0;
   __syncthreads();
-  for (int r = 0; r < rounds; ++r) {
+  for (int r = 0; r < rounds && ok_s; ++r) {
     __syncthreads();
-    if (threadIdx.x == 0) gs.arrive_and_wait();
+    if (threadIdx.x == 0 && !gs.arrive_and_wait()) ok_s = 0;
     __syncthreads();
   }
+}
+
+// Finite check (MLP_F_CHECK_FINITE): a nonzero word `flag` if any of
+// a[0..na) or b[0..nb) is NaN or infinite.  Every writer stores the same
+// value, so the race between writers is harmless.
+__global__ void k_check_finite(const float *a, int64_t na, const float *b, int64_t nb, unsigned *flag) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < na + nb; i += stride) {
+    const float v = i < na ? a[i] : b[i - na];
+    bad |= !__builtin_isfinite(v);
+  }
+  if (bad) *flag = 1u;
+}
+
+// Contraction probe: C[m][n] = sum_k A[m][k] B[n][k] on the matrix-core
+// instruction the trainer uses for the operand format PREC, with the same
+// operand layout and the same chained float32 accumulation over k (steps of
+// 4 for float32, 32 for bf16 / e4m3).  Operands arrive as float32 values and
+// are converted to the format (exact when the caller passes representable
+// values), so the result differs from the exact sum only by the matrix
+// core's own summation.  One wave per 16 x 16 tile of C.
+template <int PREC>
+__global__ __launch_bounds__(64) void k_mfma_probe(const float *A, const float *B, float *C, int M, int N, int Kd) {
+  const int lane = threadIdx.x, l16 = lane & 15, lg = lane >> 4;
+  const int tiles_n = N / 16;
+  const int tm = blockIdx.x / tiles_n, tn = blockIdx.x - tm * tiles_n;
+  const float *a = A + (int64_t)(tm * 16 + l16) * Kd;
+  const float *b = B + (int64_t)(tn * 16 + l16) * Kd;
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  if (PREC == 0) {
+    for (int k0 = 0; k0 < Kd; k0 += 4) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[k0 + lg], b[k0 + lg], acc, 0, 0, 0);
+  } else if (PREC == 1) {
+    for (int k0 = 0; k0 < Kd; k0 += 32) {
+      bf16x8 av, bv;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        av[j] = (__bf16)a[k0 + 8 * lg + j];
+        bv[j] = (__bf16)b[k0 + 8 * lg + j];
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+    }
+  } else {
+    for (int k0 = 0; k0 < Kd; k0 += 32) {
+      const float *pa = a + k0 + 8 * lg, *pb = b + k0 + 8 * lg;
+      const long av = (long)pack_e4m3x4(pa[0], pa[1], pa[2], pa[3]) | ((long)pack_e4m3x4(pa[4], pa[5], pa[6], pa[7]) << 32);
+      const long bv = (long)pack_e4m3x4(pb[0], pb[1], pb[2], pb[3]) | ((long)pack_e4m3x4(pb[4], pb[5], pb[6], pb[7]) << 32);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bv, acc, 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) C[(int64_t)(tm * 16 + 4 * lg + i) * N + tn * 16 + l16] = acc[i];
 }
 
 }  // namespace mlpk
@@ -1033,6 +1123,20 @@ namespace {
 constexpr int kMaxRowBlocks = 256, kMaxHiddenBlocks = 16;
 constexpr size_t kLdsLimit = 160 * 1024;
 int g_grid_rows = 0, g_grid_hidden = 0;  // launch hint (0: automatic)
+constexpr int64_t kDefaultWaitUs = 5000000;  // a grid-barrier wait gives up after 5 s
+int64_t g_wait_us = kDefaultWaitUs;
+
+// Microseconds -> ticks of the device's constant-rate wall clock.
+uint64_t wait_ticks(std::string *err, bool *ok) {
+  int dev = 0, khz = 0;
+  *ok = hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0;
+  if (!*ok) {
+    *err = "could not read the device wall-clock rate";
+    return 0;
+  }
+  return (uint64_t)g_wait_us * (uint64_t)khz / 1000u;
+}
 
 struct Plan {
   int Gi, Gj, Hp, RBP;
@@ -1068,9 +1172,11 @@ int min_hidden_blocks(int H) {
   return Gj;
 }
 
-// Workspace layout (bytes, 256-aligned pieces).
+// Workspace layout (bytes, 256-aligned pieces).  The barrier counters and
+// status words come first, so the status of the last launch sits at a fixed
+// place (mlp_workspace_status reads it).
 struct WsLayout {
-  size_t z2p, gp, lossp, amax, acc, bar, total;
+  size_t bar, z2p, gp, lossp, amax, acc, total;
 };
 
 WsLayout ws_layout(const mlp_config &c, int M, int Gi, int Gj) {
@@ -1080,12 +1186,13 @@ WsLayout ws_layout(const mlp_config &c, int M, int Gi, int Gj) {
   auto up = [](size_t v) { return (v + 255) / 256 * 256; };
   WsLayout w{};
   size_t o = 0;
+  static_assert(sizeof(unsigned) * mlpk::kBarWords <= kStatusBytes, "status block");
+  w.bar = o; o += kStatusBytes;
   w.z2p = o; o += up(sizeof(float) * (size_t)M * Gj * bp * 4);
   w.gp = o; o += up(sizeof(float) * (size_t)Gi * M * P);
   w.lossp = o; o += up(sizeof(float) * (size_t)Gi * M);
   w.amax = o; o += up(sizeof(float) * (size_t)5 * Gi * M * Gj);
   w.acc = o; o += up(sizeof(float) * (size_t)(M + 4));
-  w.bar = o; o += up(sizeof(unsigned) * mlpk::kBarWords);
   w.total = o;
   return w;
 }
@@ -1142,6 +1249,8 @@ void set_large_grid_hint(int row_blocks, int hidden_blocks) {
   g_grid_rows = row_blocks;
   g_grid_hidden = hidden_blocks;
 }
+
+void set_wait_limit_us(int64_t us) { g_wait_us = us < 0 ? kDefaultWaitUs : us; }
 
 // The kernel instance: operand type, output count (3 or 4), hidden tiles per
 // wave (2 when two workgroups share a CU, else 4).
@@ -1238,6 +1347,9 @@ mlp_status large_train(const mlp_config &c, int n_nets, const float *lrs, const 
   a.epochs = epochs;
   a.steps_per_epoch = (int)((c.n_rows + b - 1) / b);
   for (int i = 0; i < n_nets; ++i) a.lr[i] = lrs ? lrs[i] : c.lr;
+  bool tick_ok = false;
+  a.wait_limit = wait_ticks(err, &tick_ok);
+  if (!tick_ok) return MLP_ERR_HIP;
 
   hipLaunchKernelGGL(mlpk::k_zero_u32, dim3(1), dim3(256), 0, s, a.bar, mlpk::kBarWords);
   hipError_t e = hipGetLastError();
@@ -1258,6 +1370,48 @@ mlp_status large_train(const mlp_config &c, int n_nets, const float *lrs, const 
   void *args[] = {&a};
   e = hipLaunchCooperativeKernel(kern, dim3(G), dim3(mlpk::kLT), args, (unsigned)pl.lds, s);
   if (e != hipSuccess) { *err = std::string("cooperative launch: ") + hipGetErrorString(e); return MLP_ERR_HIP; }
+  if (c.flags & MLP_F_CHECK_FINITE) {
+    const int64_t P = D * H + H + H * K + K;
+    hipLaunchKernelGGL(mlpk::k_check_finite, dim3(256), dim3(256), 0, s, (const float *)theta.W1, P * n_nets,
+                       (const float *)loss_hist, loss_hist ? (int64_t)epochs * n_nets : (int64_t)0,
+                       a.bar + mlpk::kNonFiniteWord);
+    e = hipGetLastError();
+    if (e != hipSuccess) { *err = std::string("finite check: ") + hipGetErrorString(e); return MLP_ERR_HIP; }
+  }
+  return MLP_OK;
+}
+
+hipError_t launch_check_finite(const float *a, int64_t na, const float *b, int64_t nb, void *status_block,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(mlpk::k_check_finite, dim3(256), dim3(256), 0, s, a, na, b, nb,
+                     static_cast<unsigned *>(status_block) + mlpk::kNonFiniteWord);
+  return hipGetLastError();
+}
+
+hipError_t launch_clear_status(void *status_block, hipStream_t s) {
+  hipLaunchKernelGGL(mlpk::k_zero_u32, dim3(1), dim3(256), 0, s, static_cast<unsigned *>(status_block),
+                     mlpk::kBarWords);
+  return hipGetLastError();
+}
+
+mlp_status read_status(const void *status_block, hipStream_t s, std::string *err) {
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) { *err = std::string("stream synchronize: ") + hipGetErrorString(e); return MLP_ERR_HIP; }
+  unsigned w[2] = {0u, 0u};
+  e = hipMemcpy(&w[0], static_cast<const unsigned *>(status_block) + mlpk::kGiveUpWord, sizeof(unsigned),
+                hipMemcpyDeviceToHost);
+  if (e == hipSuccess)
+    e = hipMemcpy(&w[1], static_cast<const unsigned *>(status_block) + mlpk::kNonFiniteWord, sizeof(unsigned),
+                  hipMemcpyDeviceToHost);
+  if (e != hipSuccess) { *err = std::string("status read: ") + hipGetErrorString(e); return MLP_ERR_HIP; }
+  if (w[0]) {
+    *err = "a grid-barrier wait of the last training launch gave up: its parameters and losses are not valid";
+    return MLP_ERR_TIMEOUT;
+  }
+  if (w[1]) {
+    *err = "the finite check found a NaN or infinite parameter or loss after the last training launch";
+    return MLP_ERR_NONFINITE;
+  }
   return MLP_OK;
 }
 
@@ -1266,12 +1420,24 @@ mlp_status barrier_probe(int n_wg, int rounds, void *ws, hipStream_t s, std::str
   hipLaunchKernelGGL(mlpk::k_zero_u32, dim3(1), dim3(256), 0, s, bar, mlpk::kBarWords);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) { *err = hipGetErrorString(e); return MLP_ERR_HIP; }
-  void *args[] = {&bar, &rounds};
+  bool tick_ok = false;
+  uint64_t limit = wait_ticks(err, &tick_ok);
+  if (!tick_ok) return MLP_ERR_HIP;
+  void *args[] = {&bar, &rounds, &limit};
   e = hipLaunchCooperativeKernel((const void *)mlpk::k_barrier_probe, dim3(n_wg), dim3(mlpk::kLT), args, 0, s);
   if (e != hipSuccess) { *err = std::string("cooperative launch: ") + hipGetErrorString(e); return MLP_ERR_HIP; }
   return MLP_OK;
 }
 
 size_t barrier_probe_workspace_bytes() { return sizeof(unsigned) * mlpk::kBarWords; }
+
+hipError_t launch_mfma_probe(int prec, const float *A, const float *B, float *C, int M, int N, int Kd,
+                             hipStream_t s) {
+  const dim3 grid((unsigned)((M / 16) * (N / 16)));
+  if (prec == MLP_FP32) hipLaunchKernelGGL(mlpk::k_mfma_probe<0>, grid, dim3(64), 0, s, A, B, C, M, N, Kd);
+  else if (prec == MLP_BF16) hipLaunchKernelGGL(mlpk::k_mfma_probe<1>, grid, dim3(64), 0, s, A, B, C, M, N, Kd);
+  else hipLaunchKernelGGL(mlpk::k_mfma_probe<2>, grid, dim3(64), 0, s, A, B, C, M, N, Kd);
+  return hipGetLastError();
+}
 
 }  // namespace mlph

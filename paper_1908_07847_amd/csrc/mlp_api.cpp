@@ -63,7 +63,7 @@ mlp_status check_config(const mlp_config *c) {
     return fail(MLP_ERR_SHAPE, "n_in / n_hidden above 2^20");
   if (c->prec != MLP_FP32 && c->prec != MLP_BF16 && c->prec != MLP_FP8_E4M3)
     return fail(MLP_ERR_ARG, "unknown precision %d", c->prec);
-  if (c->flags & ~(uint32_t)(MLP_F_COMPENSATED | MLP_F_TANH_HIDDEN))
+  if (c->flags & ~(uint32_t)(MLP_F_COMPENSATED | MLP_F_DETERMINISTIC | MLP_F_CHECK_FINITE | MLP_F_TANH_HIDDEN))
     return fail(MLP_ERR_ARG, "unknown flag bits 0x%x", c->flags);
   if (!(c->lr >= 0.0f) || c->lr > 1e6f) return fail(MLP_ERR_ARG, "lr must be finite and >= 0");
   return MLP_OK;
@@ -104,6 +104,8 @@ const char *mlp_status_string(mlp_status s) {
     case MLP_ERR_WORKSPACE: return "workspace missing or too small";
     case MLP_ERR_UNSUPPORTED: return "unsupported request";
     case MLP_ERR_HIP: return "HIP runtime error";
+    case MLP_ERR_TIMEOUT: return "a grid-wide wait gave up";
+    case MLP_ERR_NONFINITE: return "non-finite parameter or loss";
   }
   return "unknown status";
 }
@@ -134,7 +136,7 @@ mlp_status mlp_workspace_size(const mlp_config *cfg, size_t *bytes) {
   mlp_status s = check_config(cfg);
   if (s != MLP_OK) return s;
   if (!bytes) return fail(MLP_ERR_ARG, "bytes is NULL");
-  size_t need = backward_ws_bytes(*cfg);
+  size_t need = mlph::kStatusBytes + backward_ws_bytes(*cfg);
   if (!small_path(*cfg)) {
     size_t lw = 0;
     s = mlph::large_workspace_bytes(*cfg, 1, &lw);
@@ -226,12 +228,14 @@ mlp_status mlp_backward(mlp_net *net, const float *X, const float *A, const floa
   for (const void *p : ptrs)
     if (p && !aligned4(p)) return fail(MLP_ERR_ALIGN, "device pointers must be 4-byte aligned");
   if (!aligned16(X)) return fail(MLP_ERR_ALIGN, "X must be 16-byte aligned");
-  if (!net->ws || net->ws_bytes < backward_ws_bytes(c))
-    return fail(MLP_ERR_WORKSPACE, "backward needs %zu workspace bytes", backward_ws_bytes(c));
+  if (!net->ws || net->ws_bytes < mlph::kStatusBytes + backward_ws_bytes(c))
+    return fail(MLP_ERR_WORKSPACE, "backward needs %zu workspace bytes",
+                mlph::kStatusBytes + backward_ws_bytes(c));
   const int64_t ws_rows = std::min<int64_t>(c.n_rows, mlph::kBackwardChunk);
+  // the workspace's head holds the status block of training launches
+  float *scratch = reinterpret_cast<float *>(static_cast<char *>(net->ws) + mlph::kStatusBytes);
   hipError_t e = mlph::launch_backward(n, ws_rows, c.n_in, c.n_hidden, c.n_out, X, A, Y, dY, T,
-                                       net->theta, grads, dX, loss, (float *)net->ws, act_of(c),
-                                       (hipStream_t)stream);
+                                       net->theta, grads, dX, loss, scratch, act_of(c), (hipStream_t)stream);
   return e == hipSuccess ? MLP_OK : hip_fail(e, "mlp_backward launch");
 }
 
@@ -275,10 +279,17 @@ mlp_status mlp_train(mlp_net *net, const float *X, const float *T, int32_t epoch
     if (act_of(c) && mlph::small_lds_bytes((int)c.n_rows, (int)H, (int)D, 512, net->velocity != nullptr) >
                          160 * 1024)
       return fail(MLP_ERR_UNSUPPORTED, "the tanh variant's 8-wave plan does not fit in LDS at this shape");
-    hipError_t e = mlph::launch_small_train(nullptr, one, 1, (int)D, (int)K, (int)c.n_rows, (int)H,
-                                            X, T, p.W1, net->comp, epochs, loss_hist, act_of(c), net->mu,
-                                            net->velocity, threads, (hipStream_t)stream);
-    return e == hipSuccess ? MLP_OK : hip_fail(e, "mlp_train (small) launch");
+    hipError_t e = mlph::launch_clear_status(net->ws, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "mlp_train status block");
+    e = mlph::launch_small_train(nullptr, one, 1, (int)D, (int)K, (int)c.n_rows, (int)H, X, T, p.W1, net->comp,
+                                 epochs, loss_hist, act_of(c), net->mu, net->velocity, threads, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "mlp_train (small) launch");
+    if (c.flags & MLP_F_CHECK_FINITE) {
+      e = mlph::launch_check_finite(p.W1, n_params(D, H, K), loss_hist, loss_hist ? epochs : 0, net->ws,
+                                    (hipStream_t)stream);
+      if (e != hipSuccess) return hip_fail(e, "mlp_train finite check");
+    }
+    return MLP_OK;
   }
   if (act_of(c) != 0 || net->velocity)
     return fail(MLP_ERR_UNSUPPORTED, "the large-N trainer (minibatches or large shapes) trains the sigmoid "
@@ -428,6 +439,36 @@ mlp_status mlp_barrier_probe(int32_t n_workgroups, int32_t rounds, void *workspa
   if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
   if (n_workgroups > ncu) return fail(MLP_ERR_ARG, "n_workgroups %d above the %d CUs", n_workgroups, ncu);
   return mlph::barrier_probe(n_workgroups, rounds, workspace, (hipStream_t)stream, &g_last_error);
+}
+
+mlp_status mlp_mfma_probe(int32_t prec, const float *A, const float *B, float *C, int32_t M, int32_t N,
+                          int32_t Kd, void *stream) {
+  if (prec != MLP_FP32 && prec != MLP_BF16 && prec != MLP_FP8_E4M3) return fail(MLP_ERR_ARG, "unknown precision %d", prec);
+  if (!A || !B || !C) return fail(MLP_ERR_ARG, "A, B and C must not be NULL");
+  if (M <= 0 || N <= 0 || Kd <= 0 || M % 16 || N % 16 || Kd % 32 || M > 4096 || N > 4096 || Kd > (1 << 20))
+    return fail(MLP_ERR_SHAPE, "M, N multiples of 16 up to 4096 and Kd a multiple of 32 up to 2^20 required");
+  if (!aligned4(A) || !aligned4(B) || !aligned4(C)) return fail(MLP_ERR_ALIGN, "device pointers must be 4-byte aligned");
+  hipError_t e = mlph::launch_mfma_probe(prec, A, B, C, M, N, Kd, (hipStream_t)stream);
+  return e == hipSuccess ? MLP_OK : hip_fail(e, "mlp_mfma_probe launch");
+}
+
+mlp_status mlp_set_wait_limit(int64_t microseconds) {
+  mlph::set_wait_limit_us(microseconds);
+  return MLP_OK;
+}
+
+mlp_status mlp_workspace_status(const void *workspace, size_t ws_bytes, void *stream) {
+  if (!workspace) return fail(MLP_ERR_ARG, "workspace is NULL");
+  if (ws_bytes < mlph::kStatusBytes)
+    return fail(MLP_ERR_WORKSPACE, "a training workspace holds at least %zu bytes", mlph::kStatusBytes);
+  if (!aligned16(workspace)) return fail(MLP_ERR_ALIGN, "workspace must be 16-byte aligned");
+  const mlp_status s = mlph::read_status(workspace, (hipStream_t)stream, &g_last_error);
+  return s;
+}
+
+mlp_status mlp_query_status(mlp_net *net, void *stream) {
+  if (!net) return fail(MLP_ERR_ARG, "net is NULL");
+  return mlp_workspace_status(net->ws, net->ws_bytes, stream);
 }
 
 mlp_status mlp_set_momentum(mlp_net *net, float mu, float *velocity) {

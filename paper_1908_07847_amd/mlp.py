@@ -69,10 +69,12 @@ class Net:
 
     def __init__(self, n_in: int, n_hidden: int, n_out: int, n_rows: int, *, batch: int = 0,
                  lr: float = 0.1, prec: str = "fp32", compensated: bool = True, theta=None,
-                 act: str = "sigmoid", momentum: float = 0.0, device="cuda"):
+                 act: str = "sigmoid", momentum: float = 0.0, check_finite: bool = False, device="cuda"):
         """act: the hidden activation, "sigmoid" (the paper's) or "tanh";
         momentum: heavy-ball rate mu (0, the paper's plain descent), with a
-        zeroed velocity buffer `self.velocity` owned by the net."""
+        zeroed velocity buffer `self.velocity` owned by the net;
+        check_finite: MLP_F_CHECK_FINITE (status() reports NaN/Inf after
+        training)."""
         self.D, self.H, self.K = int(n_in), int(n_hidden), int(n_out)
         self.n_rows, self.batch, self.lr, self.prec = int(n_rows), int(batch), float(lr), prec
         self.device = torch.device(device)
@@ -87,7 +89,8 @@ class Net:
         if act not in ("sigmoid", "tanh"):
             raise ValueError(f"unknown hidden activation {act!r}")
         self.act = act
-        flags = (_lib.MLP_F_COMPENSATED if compensated else 0) | (_lib.F_TANH_HIDDEN if act == "tanh" else 0)
+        flags = (_lib.MLP_F_COMPENSATED if compensated else 0) | (_lib.F_TANH_HIDDEN if act == "tanh" else 0) | \
+            (_lib.F_CHECK_FINITE if check_finite else 0)
         self.cfg = Config(self.D, self.H, self.K, _lib.PREC[prec], self.n_rows, self.batch, self.lr, flags)
         nbytes = ctypes.c_size_t(0)
         check(lib.mlp_workspace_size(ctypes.byref(self.cfg), ctypes.byref(nbytes)))
@@ -172,6 +175,34 @@ class Net:
         check(lib.mlp_train(self._h, _ptr(X), _ptr(T), int(epochs), _ptr(loss_hist) if record_loss else None,
                             _stream(stream)))
         return loss_hist
+
+
+    def status(self, stream=None) -> int:
+        """mlp_query_status: waits for the stream and returns the status of
+        the last training launch (MLP_OK, MLP_ERR_TIMEOUT or
+        MLP_ERR_NONFINITE) without raising."""
+        return int(lib.mlp_query_status(self._h, _stream(stream)))
+
+
+def workspace_status(workspace: torch.Tensor, stream=None) -> int:
+    """mlp_workspace_status of a training workspace (mlp_train_shared)."""
+    return int(lib.mlp_workspace_status(_ptr(workspace), int(workspace.numel() * workspace.element_size()),
+                                        _stream(stream)))
+
+
+def mfma_probe(prec: str, A: torch.Tensor, B: torch.Tensor, stream=None) -> torch.Tensor:
+    """mlp_mfma_probe: C = A B^T on the trainer's matrix-core instruction for
+    operand precision `prec` (A [M][Kd], B [N][Kd] float32 on the device)."""
+    M, Kd = A.shape
+    N = B.shape[0]
+    C = torch.empty((M, N), dtype=torch.float32, device=A.device)
+    check(lib.mlp_mfma_probe(_lib.PREC[prec], _ptr(A), _ptr(B), _ptr(C), int(M), int(N), int(Kd), _stream(stream)))
+    return C
+
+
+def set_wait_limit(microseconds: int) -> None:
+    """mlp_set_wait_limit: longest grid-barrier wait (negative: the default)."""
+    check(lib.mlp_set_wait_limit(int(microseconds)))
 
 
 def theta_packed(theta) -> np.ndarray:
@@ -270,7 +301,8 @@ def shared_workspace_size(n_in: int, n_hidden: int, n_out: int, n_rows: int, bat
 
 def train_shared(X: torch.Tensor, T: torch.Tensor, theta: torch.Tensor, lrs, epochs: int, n_hidden: int, *,
                  batch: int, prec: str = "fp32", comp: torch.Tensor | None = None,
-                 loss_hist: torch.Tensor | None = None, workspace: torch.Tensor | None = None, stream=None):
+                 loss_hist: torch.Tensor | None = None, workspace: torch.Tensor | None = None, stream=None,
+                 check_finite: bool = False):
     """mlp_train_shared: theta [n_nets][P] (float32, packed per net) trains in
     place on the shared X [N][D], T [N][K]; lrs holds one learning rate per
     net; comp (same shape as theta, or None) selects the compensated update.
@@ -279,7 +311,7 @@ def train_shared(X: torch.Tensor, T: torch.Tensor, theta: torch.Tensor, lrs, epo
     N, D = X.shape
     K = T.shape[1]
     cfg = Config(int(D), int(n_hidden), int(K), _lib.PREC[prec], int(N), int(batch), float(lrs[0]),
-                 _lib.MLP_F_COMPENSATED if comp is not None else 0)
+                 (_lib.MLP_F_COMPENSATED if comp is not None else 0) | (_lib.F_CHECK_FINITE if check_finite else 0))
     nbytes = ctypes.c_size_t(0)
     check(lib.mlp_shared_workspace_size(ctypes.byref(cfg), M, ctypes.byref(nbytes)))
     ws = workspace if workspace is not None else torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8,

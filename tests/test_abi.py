@@ -32,7 +32,7 @@ def test_struct_sizes_match_header():
 
 def test_status_strings():
     L = _lib()
-    for s in range(7):
+    for s in range(9):
         assert L.lib.mlp_status_string(s)
     assert L.lib.mlp_status_string(99) == b"unknown status"
 
@@ -216,3 +216,23 @@ def test_deep_train_rejects_before_touching_the_device():
     assert call(n=100000) == L.MLP_ERR_UNSUPPORTED                  # rows beyond one workgroup's LDS
     assert call(widths=(64, 512, 64, 3)) == L.MLP_ERR_UNSUPPORTED   # parameters beyond it
     assert call(ep=0) == L.MLP_OK
+
+
+def test_status_and_check_flags_on_the_host():
+    """MLP_F_DETERMINISTIC and MLP_F_CHECK_FINITE are accepted, the status
+    query rejects a missing, short or misaligned workspace before any HIP
+    call, and the wait limit is a plain host setting."""
+    L = _lib()
+    n = ctypes.c_size_t(0)
+    for flags in (L.F_DETERMINISTIC, L.F_CHECK_FINITE, L.F_COMPENSATED | L.F_CHECK_FINITE | L.F_DETERMINISTIC):
+        c = L.Config(33, 16, 3, 0, 120, 0, 0.1, flags)
+        assert L.lib.mlp_workspace_size(ctypes.byref(c), ctypes.byref(n)) == L.MLP_OK
+        assert n.value >= 2048                     # the status block at the workspace's head
+    assert L.lib.mlp_workspace_status(None, 4096, None) == L.MLP_ERR_ARG
+    assert L.lib.mlp_workspace_status(0x10000, 1024, None) == L.MLP_ERR_WORKSPACE
+    assert L.lib.mlp_workspace_status(0x10004, 4096, None) == L.MLP_ERR_ALIGN
+    assert L.lib.mlp_query_status(None, None) == L.MLP_ERR_ARG
+    assert L.lib.mlp_set_wait_limit(0) == L.MLP_OK
+    assert L.lib.mlp_set_wait_limit(-1) == L.MLP_OK   # back to the default
+    assert L.lib.mlp_status_string(L.MLP_ERR_TIMEOUT) == b"a grid-wide wait gave up"
+    assert L.lib.mlp_status_string(L.MLP_ERR_NONFINITE) == b"non-finite parameter or loss"
