@@ -343,7 +343,7 @@ def bench_large(args):
                             kernel_ms_per_launch=r["kernel_s"] * 1e3,
                             median_ms_per_launch=float(np.median(r["durs"])) * 1e3,
                             min_ms_per_launch=float(min(r["durs"])) * 1e3,
-                            kernel=f"mlpk::k_large_train<{pi}, {3 if K <= 3 else 4}, 4>",
+                            kernel=f"mlpk::k_large_train<{pi}, {3 if K <= 3 else 4}>",
                             achieved_tflops=ach, peak_tflops=PEAK[q], frac=ach / PEAK[q],
                             final_loss=r["final_loss"], dtype={"fp32": "f32", "bf16": "bf16", "e4m3": "e4m3"}[q])
     head = res_forms[prec]
@@ -554,7 +554,7 @@ def bench_shared(args):
                 "compensated_update": True, "operand_precision": prec, "step": "one epoch of every net"},
         roofline={"bound": "mfma", "achieved": achieved, "peak": PEAK[prec], "unit": "TFLOP/s",
                   "frac": achieved / PEAK[prec], "traffic": measured_traffic(f"w6-{prec}-steps{steps}", "large"),
-                  "traffic_unit": "bytes per launch", "kernel": f"mlpk::k_large_train<{pi}, 3, 4>",
+                  "traffic_unit": "bytes per launch", "kernel": f"mlpk::k_large_train<{pi}, 3>",
                   "kernel_ms": kern * 1e3, "flops_per_launch": flops},
         final_loss_mean=final_loss_mean, repeats={"runs": 1, "median_ms_per_step": wall * 1e3 / steps,
                                                   "min_ms_per_step": wall * 1e3 / steps},

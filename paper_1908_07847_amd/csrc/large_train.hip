@@ -5,7 +5,9 @@
 //
 // Work of one step (minibatch of m <= b rows) is split over a Gi x Gj grid
 // of workgroups: workgroup (i, j) owns row block i (RB = b / Gi rows) and
-// hidden block j (HB = Hp / Gj units; each of its 4 waves owns HB/4).  The
+// hidden block j (HB = Hp / Gj units, at most 256).  The block's 16-unit
+// hidden tiles are dealt round-robin to the workgroup's 8 waves (two per
+// SIMD, so one wave's matrix-core work overlaps the other's vector work).  The
 // two large contractions run on MFMA:
 //   z1 = X W1^T           M = rows,   N = hidden,   K = features
 //   gW1 = delta1^T X      M = hidden, N = features, K = rows
@@ -41,7 +43,9 @@ namespace mlpk {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kLT = 256;     // threads per workgroup (4 waves)
+constexpr int kNW = 8;       // waves per workgroup (two per SIMD)
+constexpr int kLT = 64 * kNW;  // threads per workgroup
+constexpr int kNHM = 2;      // most 16-unit hidden tiles per wave (hidden blocks <= 256 units)
 constexpr int kRC = 32;      // rows per chunk
 constexpr int kMaxD = 64;    // features
 constexpr int kMaxK = 4;     // outputs
@@ -228,7 +232,6 @@ struct Ops<0> {
   static constexpr int KSTEP = 4;
   typedef float elem;
   static constexpr int XROW = 66;   // LDS row stride (floats) of X rows and W1 rows
-  static constexpr int DST = 16;    // delta1 staging: [32 rows][16]
 };
 // bf16 / e4m3: 8 operands per lane per 16x16x32 step.
 template <>
@@ -237,7 +240,6 @@ struct Ops<1> {
   typedef __bf16 elem;
   static constexpr int XROW = 72;   // bf16 elements per X / W1 row (64 + pad)
   static constexpr int XTP = 8;     // pad of a transposed X row (RB rows + pad)
-  static constexpr int DST = 40;    // delta1 staging: [16 hidden][32 rows + pad]
 };
 template <>
 struct Ops<2> {
@@ -245,7 +247,6 @@ struct Ops<2> {
   typedef uint8_t elem;
   static constexpr int XROW = 80;   // bytes per X / W1 row (64 + pad)
   static constexpr int XTP = 16;
-  static constexpr int DST = 48;
 };
 
 // LDS plan (bytes), shared by host and device.
@@ -264,19 +265,14 @@ struct LLayout {
   __host__ __device__ int w2() const { return b1() + HB * 4; }
   __host__ __device__ int d2() const { return w2() + kMaxK * HB * 4; }
   __host__ __device__ int z2w() const { return d2() + RB * 16; }
-  __host__ __device__ int dst() const { return z2w() + 2 * 4 * kRC * 16; }   // two chunk buffers
-  __host__ __device__ int red() const {
-    return dst() + 4 * (PREC == 0 ? kRC * 16 * 4 : 16 * Ops<(PREC == 0 ? 1 : PREC)>::DST * esz);
-  }
+  __host__ __device__ int red() const { return z2w() + 2 * kNW * kRC * 16; }   // two chunk buffers
   __host__ __device__ int total() const { return red() + 64 * 4; }
 };
 
 // KO: outputs the loops run over (K <= KO <= kMaxK; 3 for the usual K = 3).
-// NHM: most 16-unit hidden tiles per wave (4: hidden blocks of up to 256
-// units, one workgroup per CU; 2: blocks of up to 128 units, compiled for
-// two workgroups per CU so two waves share each SIMD).
-template <int PREC, int KO, int NHM>
-__global__ __launch_bounds__(kLT, NHM <= 2 ? 2 : 1) void k_large_train(LargeArgs a) {
+template <int PREC, int KO>
+__global__ __launch_bounds__(kLT, 1) void k_large_train(LargeArgs a) {
+  constexpr int NHM = kNHM;
   using O = Ops<PREC>;
   using E = typename O::elem;
   constexpr int XROW = O::XROW;
@@ -299,11 +295,14 @@ __global__ __launch_bounds__(kLT, NHM <= 2 ? 2 : 1) void k_large_train(LargeArgs
   }
   const int net = gc / a.Gj, gj = gc - net * a.Gj;
   const int D = a.D, H = a.H, K = a.K;
-  const int HB = a.Hp / a.Gj, HW = HB / 4, NHB = HW / 16;
+  // hidden tiles of the block: tile t (units 16 t .. 16 t + 15) belongs to
+  // wave t % kNW as its local tile t / kNW; this wave owns NHB of them
+  const int HB = a.Hp / a.Gj, NT = HB / 16, NHB = (NT - wave + kNW - 1) / kNW;
   const int RB = (int)(a.b / a.Gi);     // rows of this workgroup's block
   const int RBP = a.RBP;                // rows staged in LDS at a time (divides RB)
   const int NPc = RB / RBP;             // pieces of the block
-  const int h0 = gj * HB + wave * HW;     // first hidden unit of this wave
+  // first unit (within the block) of this wave's local tile hb
+  auto tile_unit = [&](int hb) { return (hb * kNW + wave) * 16; };
   const int64_t P = (int64_t)D * H + H + (int64_t)H * K + K;
   const int64_t PT = P * a.M;           // parameters of all nets
   const int64_t oB1 = (int64_t)D * H, oW2 = oB1 + H, oB2 = oW2 + (int64_t)H * K;
@@ -323,8 +322,31 @@ __global__ __launch_bounds__(kLT, NHM <= 2 ? 2 : 1) void k_large_train(LargeArgs
   float *w2s = reinterpret_cast<float *>(smb + L.w2());
   float *d2s = reinterpret_cast<float *>(smb + L.d2());
   float *z2w = reinterpret_cast<float *>(smb + L.z2w());
-  char *dstb = smb + L.dst();
   float *red = reinterpret_cast<float *>(smb + L.red());
+  // Workgroup max / sum of one value per wave (lane 0's), through
+  // red[slot .. slot + 7], in a fixed order; every thread gets the result.
+  auto wg_reduce_max = [&](float v, int slot) {
+    for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, kWave));
+    if (lane == 0) red[slot + wave] = v;
+    __syncthreads();
+    float m = red[slot];
+#pragma unroll
+    for (int w = 1; w < kNW; ++w) m = fmaxf(m, red[slot + w]);
+    return m;
+  };
+  auto wg_reduce_sum = [&](float v, int slot) {
+    v = wave_sum(v);
+    if (lane == 0) red[slot + wave] = v;
+    __syncthreads();
+    float t[kNW];
+#pragma unroll
+    for (int w = 0; w < kNW; ++w) t[w] = red[slot + w];
+#pragma unroll
+    for (int st = 1; st < kNW; st *= 2)
+#pragma unroll
+      for (int w = 0; w < kNW; w += 2 * st) t[w] += t[w + st];
+    return t[0];
+  };
 
   // ok_s: 0 once a grid-barrier wait of this workgroup has given up
   __shared__ int ok_s;
@@ -346,10 +368,8 @@ __global__ __launch_bounds__(kLT, NHM <= 2 ? 2 : 1) void k_large_train(LargeArgs
     float m = 0.0f;
     const int64_t nx = a.N * D;
     for (int64_t q = (int64_t)bid * kLT + tid; q < nx; q += (int64_t)G * kLT) m = fmaxf(m, fabsf(a.X[q]));
-    for (int off = 32; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, kWave));
-    if (lane == 0) red[wave] = m;
-    __syncthreads();
-    if (tid == 0) a.amax[4 * G + bid] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    m = wg_reduce_max(m, 0);
+    if (tid == 0) a.amax[4 * G + bid] = m;
     ok = barrier();
     float mm = 0.0f;
     for (int g = 0; g < G; ++g) mm = fmaxf(mm, a.amax[4 * G + g]);
@@ -471,10 +491,7 @@ __global__ __launch_bounds__(kLT, NHM <= 2 ? 2 : 1) void k_large_train(LargeArgs
       if (step == 0) {
         float mw = 0.0f;
         for (int64_t q = tid; q < (int64_t)H * D; q += kLT) mw = fmaxf(mw, fabsf(th[q]));
-        for (int off = 32; off >= 1; off >>= 1) mw = fmaxf(mw, __shfl_xor(mw, off, kWave));
-        if (lane == 0) red[wave] = mw;
-        __syncthreads();
-        ew = e4m3_scale_exp(fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3])));
+        ew = e4m3_scale_exp(wg_reduce_max(mw, 0));
         __syncthreads();
         // first step: the bound max_h sum_k |W2[k][h]| / (8 m K), in float32, left to right
         float bound = 0.0f;
@@ -491,17 +508,8 @@ __global__ __launch_bounds__(kLT, NHM <= 2 ? 2 : 1) void k_large_train(LargeArgs
           mw = fmaxf(mw, a.amax[par * G + g]);              // written by the previous update
           md = fmaxf(md, a.amax[2 * G + (par ^ 1) * G + g]);  // previous step's delta1
         }
-        for (int off = 32; off >= 1; off >>= 1) {
-          mw = fmaxf(mw, __shfl_xor(mw, off, kWave));
-          md = fmaxf(md, __shfl_xor(md, off, kWave));
-        }
-        if (lane == 0) {
-          red[24 + wave] = mw;
-          red[28 + wave] = md;
-        }
-        __syncthreads();
-        mw = fmaxf(fmaxf(red[24], red[25]), fmaxf(red[26], red[27]));
-        md = fmaxf(fmaxf(red[28], red[29]), fmaxf(red[30], red[31]));
+        mw = wg_reduce_max(mw, 24);
+        md = wg_reduce_max(md, 32);
         ew = e4m3_scale_exp(mw);
         ed = e4m3_scale_exp(md);
       }
@@ -515,7 +523,7 @@ __global__ __launch_bounds__(kLT, NHM <= 2 ? 2 : 1) void k_large_train(LargeArgs
     {
       // b1 and W2 of the hidden block: (1 + kMaxK) HB <= 5 kLT values,
       // loaded together with the first batch of W1
-      constexpr int kBW = (1 + kMaxK) * 256 / kLT;
+      constexpr int kBW = ((1 + kMaxK) * 256 + kLT - 1) / kLT;
       float bw[kBW];
 #pragma unroll
       for (int u = 0; u < kBW; ++u) {
@@ -569,7 +577,7 @@ __global__ __launch_bounds__(kLT, NHM <= 2 ? 2 : 1) void k_large_train(LargeArgs
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
           const bool on = hb < NHB && 32 * ks < DK;
-          const int o = on ? (wave * HW + hb * 16 + l16) * XROW + 8 * lg + 32 * ks : 0;
+          const int o = on ? (tile_unit(hb) + l16) * XROW + 8 * lg + 32 * ks : 0;
           if (PREC == 1) {
             const bf16x8 v = *reinterpret_cast<const bf16x8 *>(reinterpret_cast<const __bf16 *>(w1s) + o);
             const bf16x8 zero = {};
@@ -594,7 +602,7 @@ __global__ __launch_bounds__(kLT, NHM <= 2 ? 2 : 1) void k_large_train(LargeArgs
         for (int hb = 0; hb < NHM; ++hb) {
           f32x4 z0 = {0.f, 0.f, 0.f, 0.f}, z1v = {0.f, 0.f, 0.f, 0.f};
           if (hb < NHB) {
-            const float *wb = reinterpret_cast<const float *>(w1s) + (wave * HW + hb * 16 + l16) * XROW + lg;
+            const float *wb = reinterpret_cast<const float *>(w1s) + (tile_unit(hb) + l16) * XROW + lg;
 #pragma unroll
             for (int st = 0; st < 16; ++st) {
               if (4 * st < DK) {
@@ -674,7 +682,7 @@ __global__ __launch_bounds__(kLT, NHM <= 2 ? 2 : 1) void k_large_train(LargeArgs
 #pragma unroll
       for (int hb = 0; hb < NHM; ++hb) {
         if (hb >= NHB) continue;
-        const int hl = wave * HW + hb * 16 + l16;
+        const int hl = tile_unit(hb) + l16;
         const float bias = b1s[hl];
         float w2v[KO];
 #pragma unroll
@@ -700,7 +708,7 @@ __global__ __launch_bounds__(kLT, NHM <= 2 ? 2 : 1) void k_large_train(LargeArgs
       // consecutive chunks alternate between two buffers, so one barrier per
       // chunk separates the writes of a buffer from the reads of its
       // previous contents (two chunks back)
-      float *zw = z2w + ((c0 / kRC) & 1) * (4 * kRC * 4);
+      float *zw = z2w + ((c0 / kRC) & 1) * (kNW * kRC * 4);
       if (l16 == 0) {
 #pragma unroll
         for (int rs = 0; rs < 2; ++rs)
@@ -712,8 +720,15 @@ __global__ __launch_bounds__(kLT, NHM <= 2 ? 2 : 1) void k_large_train(LargeArgs
       __syncthreads();
       for (int q = tid; q < kRC * 4; q += kLT) {
         const int rr = q >> 2, k = q & 3;
-        out(rr, k, (zw[(0 * kRC + rr) * 4 + k] + zw[(1 * kRC + rr) * 4 + k]) +
-                       (zw[(2 * kRC + rr) * 4 + k] + zw[(3 * kRC + rr) * 4 + k]));
+        // waves in pairs, then pairs of pairs (a fixed tree)
+        float v[kNW];
+#pragma unroll
+        for (int w = 0; w < kNW; ++w) v[w] = zw[(w * kRC + rr) * 4 + k];
+#pragma unroll
+        for (int st = 1; st < kNW; st *= 2)
+#pragma unroll
+          for (int w = 0; w < kNW; w += 2 * st) v[w] += v[w + st];
+        out(rr, k, v[0]);
       }
     };
 
@@ -811,18 +826,57 @@ __global__ __launch_bounds__(kLT, NHM <= 2 ? 2 : 1) void k_large_train(LargeArgs
       if (gj == 0)
         for (int rr = lane; rr < RBP; rr += 64) gb2 += d2s[rr * 4 + wave];
 
-      // recompute a, form delta1, accumulate gW1 (MFMA), gb1, gW2
+      // recompute a, form delta1, accumulate gW1 (MFMA), gb1, gW2.  delta1
+      // feeds the gW1 contraction straight from registers: the chunk's rows
+      // are summed in the order the z1 accumulator holds them (lane group lg
+      // has rows 4 lg + i and 16 + 4 lg + i of the chunk), and the X operand
+      // is read for the same rows.
       for (int c0 = 0; c0 < RBP; c0 += kRC) {
       f32x4 zt[NHM][2];
       z1_tiles(c0, zt);
+      // X operands of this chunk's gW1 contraction, shared by the wave's tiles:
+      // float32 [rs][i][fb] = X[c0 + 16 rs + 4 lg + i][16 fb + l16]; bf16 /
+      // e4m3 [fb] = X[rows c0 + 4 lg .. +3, then c0 + 16 + 4 lg .. +3][16 fb + l16]
+      float xg[2][4][4];
+      bf16x8 xgb[4];
+      long xge[4];
+      if (PREC == 0) {
+#pragma unroll
+        for (int rs = 0; rs < 2; ++rs)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int fb = 0; fb < 4; ++fb)
+              xg[rs][i][fb] = fb < NFB ? reinterpret_cast<const float *>(xr)[(c0 + 16 * rs + 4 * lg + i) * XROW +
+                                                                            16 * fb + l16]
+                                       : 0.0f;
+      } else if (PREC == 1) {
+#pragma unroll
+        for (int fb = 0; fb < 4; ++fb) {
+          const __bf16 *p = reinterpret_cast<const __bf16 *>(xt) + (16 * fb + l16) * XTS + c0 + 4 * lg;
+          typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+          const bf16x4 lo = fb < NFB ? *reinterpret_cast<const bf16x4 *>(p) : bf16x4{};
+          const bf16x4 hi = fb < NFB ? *reinterpret_cast<const bf16x4 *>(p + 16) : bf16x4{};
+          xgb[fb] = bf16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+        }
+      } else {
+#pragma unroll
+        for (int fb = 0; fb < 4; ++fb) {
+          const uint8_t *p = reinterpret_cast<const uint8_t *>(xt) + (16 * fb + l16) * XTS + c0 + 4 * lg;
+          const uint32_t lo = fb < NFB ? *reinterpret_cast<const uint32_t *>(p) : 0u;
+          const uint32_t hi = fb < NFB ? *reinterpret_cast<const uint32_t *>(p + 16) : 0u;
+          xge[fb] = (long)((uint64_t)lo | ((uint64_t)hi << 32));
+        }
+      }
 #pragma unroll
       for (int hb = 0; hb < NHM; ++hb) {
         if (hb < NHB) {
-          const int hl = wave * HW + hb * 16 + l16;
+          const int hl = tile_unit(hb) + l16;
           const float bias = b1s[hl];
           float w2v[KO];
 #pragma unroll
           for (int k = 0; k < KO; ++k) w2v[k] = w2s[k * HB + hl];
+          float d1v[2][4];
 #pragma unroll
           for (int rs = 0; rs < 2; ++rs) {
             const f32x4 z = zt[hb][rs];
@@ -841,54 +895,41 @@ __global__ __launch_bounds__(kLT, NHM <= 2 ? 2 : 1) void k_large_train(LargeArgs
               }
               const float d1 = bp * slope;
               gb1[hb] += d1;
-              // stage delta1 in the operand layout of the gW1 contraction
-              if (PREC == 0) {
-                reinterpret_cast<float *>(dstb)[wave * kRC * 16 + rr * 16 + l16] = d1;
-              } else if (PREC == 1) {
-                reinterpret_cast<__bf16 *>(dstb)[(wave * 16 + l16) * Ops<1>::DST + rr] = (__bf16)d1;
-              } else {
-                d1max = fmaxf(d1max, fabsf(d1));
-                float q = fminf(fmaxf(d1 * sd, -448.f), 448.f);
-                const int pk = __builtin_amdgcn_cvt_pk_fp8_f32(q, 0.0f, 0, false);
-                reinterpret_cast<uint8_t *>(dstb)[(wave * 16 + l16) * Ops<2>::DST + rr] = (uint8_t)pk;
-              }
+              d1v[rs][i] = d1;
+              if (PREC == 2) d1max = fmaxf(d1max, fabsf(d1));
             }
           }
-          // gW1[hidden block][feature blocks] += delta1^T X over the chunk's rows
+          // gW1[tile][feature blocks] += delta1^T X over the chunk's rows
           if (PREC == 0) {
-            const float *da = reinterpret_cast<const float *>(dstb) + wave * kRC * 16 + lg * 16 + l16;
-            const float *xb = reinterpret_cast<const float *>(xr) + (c0 + lg) * XROW + l16;
 #pragma unroll
             for (int fb = 0; fb < 4; ++fb) {
               if (fb < NFB) {
                 f32x4 g = gacc[hb][fb];
-                for (int k0 = 0; k0 < kRC; k0 += 4)
-                  g = __builtin_amdgcn_mfma_f32_16x16x4f32(da[k0 * 16], xb[k0 * XROW + fb * 16], g, 0, 0, 0);
+#pragma unroll
+                for (int rs = 0; rs < 2; ++rs)
+#pragma unroll
+                  for (int i = 0; i < 4; ++i)
+                    g = __builtin_amdgcn_mfma_f32_16x16x4f32(d1v[rs][i], xg[rs][i][fb], g, 0, 0, 0);
                 gacc[hb][fb] = g;
               }
             }
           } else if (PREC == 1) {
-            const __bf16 *da = reinterpret_cast<const __bf16 *>(dstb) + (wave * 16 + l16) * Ops<1>::DST + 8 * lg;
-            const bf16x8 av = *reinterpret_cast<const bf16x8 *>(da);
+            bf16x8 av;
 #pragma unroll
-            for (int fb = 0; fb < 4; ++fb) {
-              if (fb < NFB) {
-                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(
-                    reinterpret_cast<const __bf16 *>(xt) + (fb * 16 + l16) * XTS + c0 + 8 * lg);
-                gacc[hb][fb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, gacc[hb][fb], 0, 0, 0);
-              }
+            for (int j = 0; j < 4; ++j) {
+              av[j] = (__bf16)d1v[0][j];
+              av[4 + j] = (__bf16)d1v[1][j];
             }
+#pragma unroll
+            for (int fb = 0; fb < 4; ++fb)
+              if (fb < NFB) gacc[hb][fb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, xgb[fb], gacc[hb][fb], 0, 0, 0);
           } else {
-            const uint8_t *da = reinterpret_cast<const uint8_t *>(dstb) + (wave * 16 + l16) * Ops<2>::DST + 8 * lg;
-            const long av = *reinterpret_cast<const long *>(da);
+            const long av =
+                (long)((uint64_t)pack_e4m3x4(d1v[0][0] * sd, d1v[0][1] * sd, d1v[0][2] * sd, d1v[0][3] * sd) |
+                       ((uint64_t)pack_e4m3x4(d1v[1][0] * sd, d1v[1][1] * sd, d1v[1][2] * sd, d1v[1][3] * sd) << 32));
 #pragma unroll
-            for (int fb = 0; fb < 4; ++fb) {
-              if (fb < NFB) {
-                const long bv = *reinterpret_cast<const long *>(
-                    reinterpret_cast<const uint8_t *>(xt) + (fb * 16 + l16) * XTS + c0 + 8 * lg);
-                gacc[hb][fb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bv, gacc[hb][fb], 0, 0, 0);
-              }
-            }
+            for (int fb = 0; fb < 4; ++fb)
+              if (fb < NFB) gacc[hb][fb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, xge[fb], gacc[hb][fb], 0, 0, 0);
           }
         }
       }
@@ -897,11 +938,9 @@ __global__ __launch_bounds__(kLT, NHM <= 2 ? 2 : 1) void k_large_train(LargeArgs
 
     // loss and gb2 partials of this net's row block (hidden block 0 only)
     if (gj == 0) {
-      for (int off = 32; off >= 1; off >>= 1) sq += __shfl_xor(sq, off, kWave);
       for (int off = 32; off >= 1; off >>= 1) gb2 += __shfl_xor(gb2, off, kWave);
-      if (lane == 0) red[wave] = sq;
-      __syncthreads();
-      if (tid == 0) a.lossp[(int64_t)gi * a.M + net] = (red[0] + red[1]) + (red[2] + red[3]);
+      sq = wg_reduce_sum(sq, 0);
+      if (tid == 0) a.lossp[(int64_t)gi * a.M + net] = sq;
       if (lane == 0 && wave < K) a.gp[(int64_t)gi * PT + (int64_t)net * P + oB2 + wave] = gb2;
     }
 
@@ -917,7 +956,7 @@ __global__ __launch_bounds__(kLT, NHM <= 2 ? 2 : 1) void k_large_train(LargeArgs
             if (fb < NFB) {
 #pragma unroll
               for (int i = 0; i < 4; ++i) {
-                const int h = h0 + hb * 16 + 4 * lg + i, d = fb * 16 + l16;
+                const int h = gj * HB + tile_unit(hb) + 4 * lg + i, d = fb * 16 + l16;
                 if (h < H && d < D) gpi[(int64_t)h * D + d] = gacc[hb][fb][i] * gscale;
               }
             }
@@ -933,7 +972,7 @@ __global__ __launch_bounds__(kLT, NHM <= 2 ? 2 : 1) void k_large_train(LargeArgs
             t += __shfl_xor(t, 32, kWave);
             w[k] = t;
           }
-          const int h = h0 + hb * 16 + l16;
+          const int h = gj * HB + tile_unit(hb) + l16;
           if (lg == 0 && h < H) {
             gpi[oB1 + h] = v;
 #pragma unroll
@@ -943,13 +982,8 @@ __global__ __launch_bounds__(kLT, NHM <= 2 ? 2 : 1) void k_large_train(LargeArgs
         }
       }
       if (PREC == 2) {
-        for (int off = 32; off >= 1; off >>= 1) d1max = fmaxf(d1max, __shfl_xor(d1max, off, kWave));
-        __syncthreads();
-        if (lane == 0) red[8 + wave] = d1max;
-        __syncthreads();
-        if (tid == 0)
-          a.amax[2 * G + (step & 1) * G + bid] =
-              fmaxf(fmaxf(red[8], red[9]), fmaxf(red[10], red[11]));
+        d1max = wg_reduce_max(d1max, 8);
+        if (tid == 0) a.amax[2 * G + (step & 1) * G + bid] = d1max;
       }
     }
     if (!barrier()) { ok = false; break; }
@@ -989,7 +1023,7 @@ __global__ __launch_bounds__(kLT, NHM <= 2 ? 2 : 1) void k_large_train(LargeArgs
         return sum;
       };
       if (np <= 64) {
-        const int g0 = (a.Gi * wave) / 4, g1 = (a.Gi * (wave + 1)) / 4;
+        const int g0 = (a.Gi * wave) / kNW, g1 = (a.Gi * (wave + 1)) / kNW;
         float w = 0.0f, c = 0.0f, sum = 0.0f;
         if (lane < np) {
           if (wave == 0) {
@@ -1000,8 +1034,16 @@ __global__ __launch_bounds__(kLT, NHM <= 2 ? 2 : 1) void k_large_train(LargeArgs
         }
         z2w[wave * 64 + lane] = sum;
         __syncthreads();
-        if (wave == 0 && lane < np)
-          update(p0 + lane, w, c, (z2w[lane] + z2w[64 + lane]) + (z2w[128 + lane] + z2w[192 + lane]));
+        if (wave == 0 && lane < np) {
+          float v[kNW];
+#pragma unroll
+          for (int w8 = 0; w8 < kNW; ++w8) v[w8] = z2w[w8 * 64 + lane];
+#pragma unroll
+          for (int st = 1; st < kNW; st *= 2)
+#pragma unroll
+            for (int w8 = 0; w8 < kNW; w8 += 2 * st) v[w8] += v[w8 + st];
+          update(p0 + lane, w, c, v[0]);
+        }
       } else {
         for (int q = tid; q < np; q += kLT) {
           const float w = a.theta[p0 + q], c = a.comp ? a.comp[p0 + q] : 0.0f;
@@ -1009,11 +1051,8 @@ __global__ __launch_bounds__(kLT, NHM <= 2 ? 2 : 1) void k_large_train(LargeArgs
         }
       }
       if (PREC == 2) {
-        for (int off = 32; off >= 1; off >>= 1) wmax = fmaxf(wmax, __shfl_xor(wmax, off, kWave));
-        if (lane == 0) red[16 + wave] = wmax;
-        __syncthreads();
-        if (tid == 0)
-          a.amax[((step + 1) & 1) * G + bid] = fmaxf(fmaxf(red[16], red[17]), fmaxf(red[18], red[19]));
+        wmax = wg_reduce_max(wmax, 16);
+        if (tid == 0) a.amax[((step + 1) & 1) * G + bid] = wmax;
       }
       if (bid < a.M && wave == 0) {
         // workgroup n keeps net n's loss: lanes take every 64th row block,
@@ -1140,7 +1179,6 @@ uint64_t wait_ticks(std::string *err, bool *ok) {
 
 struct Plan {
   int Gi, Gj, Hp, RBP;
-  int per_cu;   // workgroups per CU the grid needs (1 or 2)
   size_t lds;
 };
 
@@ -1229,17 +1267,13 @@ static bool plan_for(const mlp_config &c, int M, int n_cu, Plan *pl, std::string
   if (Hp / Gj > 256) { *why = "hidden block above 256 units"; return false; }
   if (Gi > max_row_blocks(M, Gj) || Gj > kMaxHiddenBlocks) { *why = "grid above the workspace plan"; return false; }
   if (b % Gi != 0 || (b / Gi) % 32 != 0) { *why = "rows per block must be a multiple of 32"; return false; }
-  // a grid of more workgroups than CUs runs two per CU: hidden blocks of at
-  // most 128 units (two tiles per wave) and half the LDS each
+  // one workgroup (8 waves) per CU
   const int G = Gi * M * Gj;
-  const int per_cu = (G + n_cu - 1) / n_cu;
-  if (per_cu > 2) { *why = "grid above two workgroups per CU"; return false; }
-  if (per_cu == 2 && Hp / Gj > 128) { *why = "two workgroups per CU need hidden blocks of at most 128 units"; return false; }
+  if (G > n_cu) { *why = "grid above one workgroup per CU"; return false; }
   pl->Gi = Gi;
   pl->Gj = Gj;
   pl->Hp = Hp;
-  pl->per_cu = per_cu;
-  pl->RBP = piece_rows(c.prec, Hp / Gj, (int)(b / Gi), kLdsLimit / per_cu);
+  pl->RBP = piece_rows(c.prec, Hp / Gj, (int)(b / Gi), kLdsLimit);
   if (pl->RBP == 0) { *why = "no row piece of the block fits the LDS"; return false; }
   pl->lds = lds_for(c.prec, Hp / Gj, pl->RBP);
   return true;
@@ -1252,18 +1286,12 @@ void set_large_grid_hint(int row_blocks, int hidden_blocks) {
 
 void set_wait_limit_us(int64_t us) { g_wait_us = us < 0 ? kDefaultWaitUs : us; }
 
-// The kernel instance: operand type, output count (3 or 4), hidden tiles per
-// wave (2 when two workgroups share a CU, else 4).
-static const void *kernel_for(int prec, bool k3, bool two) {
+// The kernel instance: operand type and output count (3 or 4).
+static const void *kernel_for(int prec, bool k3) {
   using namespace mlpk;
-  if (prec == MLP_FP32)
-    return two ? (k3 ? (const void *)k_large_train<0, 3, 2> : (const void *)k_large_train<0, 4, 2>)
-               : (k3 ? (const void *)k_large_train<0, 3, 4> : (const void *)k_large_train<0, 4, 4>);
-  if (prec == MLP_BF16)
-    return two ? (k3 ? (const void *)k_large_train<1, 3, 2> : (const void *)k_large_train<1, 4, 2>)
-               : (k3 ? (const void *)k_large_train<1, 3, 4> : (const void *)k_large_train<1, 4, 4>);
-  return two ? (k3 ? (const void *)k_large_train<2, 3, 2> : (const void *)k_large_train<2, 4, 2>)
-             : (k3 ? (const void *)k_large_train<2, 3, 4> : (const void *)k_large_train<2, 4, 4>);
+  if (prec == MLP_FP32) return k3 ? (const void *)k_large_train<0, 3> : (const void *)k_large_train<0, 4>;
+  if (prec == MLP_BF16) return k3 ? (const void *)k_large_train<1, 3> : (const void *)k_large_train<1, 4>;
+  return k3 ? (const void *)k_large_train<2, 3> : (const void *)k_large_train<2, 4>;
 }
 
 mlp_status large_workspace_bytes(const mlp_config &c, int n_nets, size_t *bytes) {
@@ -1355,7 +1383,7 @@ mlp_status large_train(const mlp_config &c, int n_nets, const float *lrs, const 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) { *err = hipGetErrorString(e); return MLP_ERR_HIP; }
 
-  const void *kern = kernel_for(c.prec, c.n_out <= 3, pl.per_cu == 2);
+  const void *kern = kernel_for(c.prec, c.n_out <= 3);
   e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.lds);
   if (e != hipSuccess) { *err = std::string("hipFuncSetAttribute: ") + hipGetErrorString(e); return MLP_ERR_HIP; }
   int per_cu = 0;

@@ -79,16 +79,14 @@ def large_key(n_in: int, n_hidden: int, batch: int, prec: str) -> str:
 
 def large_candidates(n_hidden: int, batch: int, n_cu: int):
     """(Gi, Gj) grids the large trainer accepts for this shape: hidden blocks
-    of 64..256 units and row blocks of >= 32 rows with at most one workgroup
-    per CU, or hidden blocks of at most 128 units with two per CU."""
+    of 64..256 units and row blocks of >= 32 rows, one workgroup per CU."""
     out = []
     gj = 1
     while gj <= 16:
         hb = -(-n_hidden // (64 * gj)) * 64
         if 64 <= hb <= 256 or (gj == 1 and hb <= 256):
-            per_cu = 2 if hb <= 128 else 1
             gi = 1
-            while gi * gj <= per_cu * n_cu and gi <= 256:
+            while gi * gj <= n_cu and gi <= 256:
                 if batch % gi == 0 and (batch // gi) % 32 == 0:
                     out.append((gi, gj))
                 gi *= 2

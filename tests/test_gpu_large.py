@@ -171,14 +171,15 @@ def test_lowp_single_step_matches_emulating_oracle(M, prec):
     operands the same way.  W2, b1, b2 (and the loss) do not depend on any rounding
     decision the two sides could take differently: 1e-5.  W1 may differ where a
     delta1 operand sits on a rounding tie (see rounding_flip_bound), plus the
-    float32 summation of the gradient (1e-6 of the sum of |terms|)."""
+    summation of the gradient (acc_rel of the sum of |terms|)."""
     lr = 0.1
-    # float32 summation error of one contraction, relative to the sum of |terms|:
-    # bf16 products are summed in IEEE float32 (a few ulps over the short MFMA
-    # chains); the e4m3 MFMA's internal sum measured ~7.5e-6 (gfx950, 32-term dot
-    # products of e4m3 values against exact float64), so its bound is 1e-5 and
-    # the rounding-free updates inherit it through the hidden pre-activation.
-    acc_rel = {"bf16": 1e-6, "e4m3": 1e-5}[prec]
+    # summation error of one contraction relative to the sum of |terms|, as
+    # measured and bounded in test_gpu_mfma_accuracy.py: bf16 products are
+    # exact and summed in float32 (a few ulps over the short chains); the e4m3
+    # instruction's own sum stays below E4M3_TRAINER_BOUND = 5e-5 for operands
+    # distributed like these, and the rounding-free updates inherit it
+    # through the hidden pre-activation.
+    acc_rel = {"bf16": 1e-6, "e4m3": 5e-5}[prec]
     tol = {"bf16": TOL, "e4m3": 5e-5}[prec]
     for wl, n, batch in [(4, 4096, 4096), (5, 16384, 16384)]:
         w = synth.single(wl, n_rows=n)
@@ -261,13 +262,14 @@ def test_wide_workload_65536_row_subset_error_vs_exact_oracle(M):
 
 
 @pytest.mark.parametrize("wl,n,batch,grid,prec,tol", [
-    (4, 8 * 4096, 4096, (128, 4), "fp32", TOL),
-    (5, 2 * 16384, 16384, (64, 8), "fp32", TOL),
-    (5, 2 * 16384, 16384, (64, 8), "bf16", 1e-3)])
-def test_two_workgroups_per_cu_grids_keep_parity(M, wl, n, batch, grid, prec, tol):
-    """Grids of more workgroups than CUs run two per CU (hidden blocks of at
-    most 128 units, half the LDS each); results still match the oracle (bf16
-    within its many-step sanity gate)."""
+    (4, 8 * 4096, 4096, (64, 4), "fp32", TOL),     # 64-unit hidden blocks: half the waves own no tile
+    (4, 8 * 4096, 4096, (32, 1), "fp32", TOL),     # one 256-unit hidden block: two tiles per wave
+    (5, 2 * 16384, 16384, (32, 8), "fp32", TOL),   # 512-row blocks staged in LDS in pieces
+    (5, 2 * 16384, 16384, (32, 8), "bf16", 1e-3)])
+def test_hinted_grids_keep_parity(M, wl, n, batch, grid, prec, tol):
+    """Grids other than the automatic one (set through the launch hint the
+    autotuner uses) still match the oracle (bf16 within its many-step
+    sanity gate)."""
     w = synth.single(wl, n_rows=n)
     M.set_launch_hint(large_grid=grid)
     try:

@@ -17,8 +17,8 @@ def test_large_candidates_respect_the_kernel_limits(tune, h, batch):
         hb = -(-h // (64 * gj)) * 64
         assert hb <= 256
         assert batch % gi == 0 and (batch // gi) % 32 == 0
-        # one workgroup per CU, or two when hidden blocks are at most 128 units
-        assert gi * gj <= 256 or (gi * gj <= 512 and hb <= 128)
+        # one workgroup per CU
+        assert gi * gj <= 256
 
 
 def test_keys_bucket_shapes(tune):
