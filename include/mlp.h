@@ -389,12 +389,14 @@ mlp_status mlp_mfma_probe(int32_t prec, const float *A, const float *B, float *C
  *                        128, 256 or 512 (fewer are used when the larger
  *                        count's LDS plan would not fit);
  *   large_row_blocks,    the Gi x Gj grid of the large-N trainer (row blocks
- *   large_hidden_blocks  of >= 32 rows, hidden blocks of <= 256 units). */
+ *   large_hidden_blocks  of >= 32 rows, hidden blocks of <= 256 units);
+ *   large_waves          waves per workgroup of the large-N trainer, 4 or 8
+ *                        (0: 8 for hidden blocks of 256 units, else 4). */
 typedef struct {
   int32_t small_threads;
   int32_t large_row_blocks;
   int32_t large_hidden_blocks;
-  int32_t reserved; /* must be 0 */
+  int32_t large_waves;
 } mlp_launch_hint;
 
 mlp_status mlp_set_launch_hint(const mlp_launch_hint *hint /*host; NULL resets*/);

@@ -46,7 +46,7 @@ class BatchItem(ctypes.Structure):
 
 class LaunchHint(ctypes.Structure):
     _fields_ = [("small_threads", ctypes.c_int32), ("large_row_blocks", ctypes.c_int32),
-                ("large_hidden_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("large_hidden_blocks", ctypes.c_int32), ("large_waves", ctypes.c_int32)]
 
 
 assert ctypes.sizeof(BatchItem) == 32 and ctypes.sizeof(Config) == 40 and ctypes.sizeof(LaunchHint) == 16

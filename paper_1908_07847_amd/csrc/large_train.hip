@@ -43,9 +43,8 @@ namespace mlpk {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kNW = 8;       // waves per workgroup (two per SIMD)
-constexpr int kLT = 64 * kNW;  // threads per workgroup
-constexpr int kNHM = 2;      // most 16-unit hidden tiles per wave (hidden blocks <= 256 units)
+constexpr int kMaxNW = 8;    // most waves per workgroup (the LDS plan is sized for it)
+constexpr int kProbeLT = 256;  // threads per workgroup of the barrier probe
 constexpr int kRC = 32;      // rows per chunk
 constexpr int kMaxD = 64;    // features
 constexpr int kMaxK = 4;     // outputs
@@ -187,6 +186,7 @@ __device__ __forceinline__ uint8_t e4m3_byte(float v) {
 constexpr int kStageU = 16;  // loads in flight per thread while staging
 constexpr int kPre = 16;     // X elements per thread prefetched a step ahead
 constexpr int kRedU = 32;    // partial-gradient loads in flight per thread
+constexpr int kUpdU = 4;     // parameters per thread per batch when there are at most 4 partials
 
 // q / D for 0 <= q < 2^16 and 1 <= D <= 64 with md = ceil(2^22 / D): the
 // error md*D - 2^22 <= D - 1 keeps q*md / 2^22 below the next integer.
@@ -204,20 +204,20 @@ __device__ __forceinline__ float load_if(const float *p, const float *safe, bool
 }
 
 // Copy n contiguous floats src[0..n) through registers: each thread loads
-// U elements (stride kLT) before storing any, so a batch costs one memory
-// round trip.  store(q, v) places element q.
-template <int U, typename F>
+// U elements (stride LT, the workgroup's thread count) before storing any,
+// so a batch costs one memory round trip.  store(q, v) places element q.
+template <int U, int LT, typename F>
 __device__ __forceinline__ void stage_flat(const float *src, int n, int tid, F &&store) {
-  for (int base = 0; base < n; base += U * kLT) {
+  for (int base = 0; base < n; base += U * LT) {
     float v[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int q = base + u * kLT + tid;
+      const int q = base + u * LT + tid;
       v[u] = load_if(src + q, src, q < n);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int q = base + u * kLT + tid;
+      const int q = base + u * LT + tid;
       if (q < n) store(q, v[u]);
     }
   }
@@ -265,14 +265,17 @@ struct LLayout {
   __host__ __device__ int w2() const { return b1() + HB * 4; }
   __host__ __device__ int d2() const { return w2() + kMaxK * HB * 4; }
   __host__ __device__ int z2w() const { return d2() + RB * 16; }
-  __host__ __device__ int red() const { return z2w() + 2 * kNW * kRC * 16; }   // two chunk buffers
+  __host__ __device__ int red() const { return z2w() + 2 * kMaxNW * kRC * 16; }   // two chunk buffers
   __host__ __device__ int total() const { return red() + 64 * 4; }
 };
 
 // KO: outputs the loops run over (K <= KO <= kMaxK; 3 for the usual K = 3).
-template <int PREC, int KO>
-__global__ __launch_bounds__(kLT, 1) void k_large_train(LargeArgs a) {
-  constexpr int NHM = kNHM;
+// NW: waves per workgroup, 4 (one per SIMD) or 8 (two per SIMD, so one
+// wave's matrix-core work overlaps the other's vector work); a wave owns at
+// most NHM = 16 / NW hidden tiles (hidden blocks of at most 256 units).
+template <int PREC, int KO, int NW>
+__global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
+  constexpr int kNW = NW, kLT = 64 * NW, NHM = 16 / NW;
   using O = Ops<PREC>;
   using E = typename O::elem;
   constexpr int XROW = O::XROW;
@@ -379,9 +382,9 @@ __global__ __launch_bounds__(kLT, 1) void k_large_train(LargeArgs a) {
 
   // ---- X staging.  A piece of a step's row block (RBP rows) is a
   // contiguous run of X (RBP x D floats); rows past the end of a short last
-  // minibatch are zero.  For piece 0 the first kPre * kLT elements go
-  // through registers (loaded one step ahead, during the previous update);
-  // everything else is staged directly.
+  // minibatch are zero.  Piece 0 of the next step is loaded and stored
+  // during the update phase (its first kPre * kLT elements through registers
+  // loaded before the partial sums); other pieces are staged directly.
   const int XTS = L.xts();
   const uint32_t mdD = ((1u << 22) + (uint32_t)D - 1) / (uint32_t)D;
   auto block_rows = [&](int st, int pc, int64_t &rb0_, int &rows_) {
@@ -428,7 +431,7 @@ __global__ __launch_bounds__(kLT, 1) void k_large_train(LargeArgs a) {
   auto load_unit = [&](const float *src, int rows_, int u, float *v) {
     const int r8 = div_by(u, mdD), c = u - r8 * D, rr = r8 * 8;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = load_if(src + (int64_t)(rr + j) * D + c, a.X, u < n_units && rr + j < rows_);
+    for (int j = 0; j < 8; ++j) v[j] = load_if(src + ((rr + j) * D + c), a.X, u < n_units && rr + j < rows_);
   };
   auto load_x = [&](int st, float (&v)[kPre]) {
     int64_t rb0_;
@@ -534,7 +537,7 @@ __global__ __launch_bounds__(kLT, 1) void k_large_train(LargeArgs a) {
       }
       const int hv = max(0, min(HB, H - gj * HB));          // real hidden units here
       const float *w1src = th + (int64_t)gj * HB * D;
-      stage_flat<kStageU>(w1src, hv * D, tid, [&](int q, float v) {
+      stage_flat<kStageU, kLT>(w1src, hv * D, tid, [&](int q, float v) {
         const int hl = div_by(q, mdD), c = q - hl * D;
         const int o = hl * XROW + c;
         if (PREC == 0) reinterpret_cast<float *>(w1s)[o] = v;
@@ -548,9 +551,9 @@ __global__ __launch_bounds__(kLT, 1) void k_large_train(LargeArgs a) {
         else if (q < (1 + kMaxK) * HB) w2s[q - HB] = bw[u];
       }
     }
-    // ---- this step's row block of X: the part prefetched into registers
-    // during the previous step's update, then the rest (if any) directly.
-    if (step == 0) load_x(step, xpre);
+    // ---- this step's row block of X (its first piece): staged during the
+    // previous step's update, except at the first step
+    load_x(step, xpre);
     store_x(step, 0, &xpre);
     int cur_piece = 0;   // piece of the row block held in LDS
     auto stage_piece = [&](int pc) {
@@ -738,8 +741,9 @@ __global__ __launch_bounds__(kLT, 1) void k_large_train(LargeArgs a) {
       for (int pc = 0; pc < NPc; ++pc) {
         stage_piece(pc);
         const int64_t rowbase = (int64_t)gc * a.b + (int64_t)gi * RB + (int64_t)pc * RBP;
+        float *zrow = a.z2p + rowbase * 4;   // this piece's rows (uniform base, 32-bit offsets)
         for (int c0 = 0; c0 < RBP; c0 += kRC)
-          z2_chunk(c0, [&](int rr, int k, float v) { a.z2p[(rowbase + c0 + rr) * 4 + k] = v; });
+          z2_chunk(c0, [&](int rr, int k, float v) { zrow[(c0 + rr) * 4 + k] = v; });
       }
       if (!barrier()) { ok = false; break; }
     }
@@ -780,13 +784,14 @@ __global__ __launch_bounds__(kLT, 1) void k_large_train(LargeArgs a) {
         // piece; every load (b2, targets, the Gj partials) is issued before
         // the first use
         constexpr int kIt = 512 * 4 / kLT;
+        const float *tb = a.T + (rb0 + prow0) * K;   // the piece's targets
         float zv[kIt], tv[kIt];
 #pragma unroll
         for (int it = 0; it < kIt; ++it) {
           const int q = tid + it * kLT, rr = q >> 2, k = q & 3;
           const bool on = q < RBP * 4 && k < K && rr < prows;
           zv[it] = load_if(th + oB2 + k, th, on);
-          tv[it] = load_if(a.T + (rb0 + prow0 + rr) * K + k, a.T, on);
+          tv[it] = load_if(tb + (rr * K + k), a.T, on);
         }
         if (split) {
           const float *zb = a.z2p + ((int64_t)(net * a.Gj) * a.b + (int64_t)gi * RB + prow0) * 4;
@@ -957,7 +962,7 @@ __global__ __launch_bounds__(kLT, 1) void k_large_train(LargeArgs a) {
 #pragma unroll
               for (int i = 0; i < 4; ++i) {
                 const int h = gj * HB + tile_unit(hb) + 4 * lg + i, d = fb * 16 + l16;
-                if (h < H && d < D) gpi[(int64_t)h * D + d] = gacc[hb][fb][i] * gscale;
+                if (h < H && d < D) gpi[h * D + d] = gacc[hb][fb][i] * gscale;
               }
             }
           }
@@ -993,8 +998,8 @@ __global__ __launch_bounds__(kLT, 1) void k_large_train(LargeArgs a) {
     // nets) in a fixed order and update the master copy.  Lanes run over
     // parameters (coalesced reads of each partial row); with few parameters
     // per workgroup the four waves split the partials and meet in LDS.
-    // next step's X rows: loads in flight while the partials are summed
-    if (step + 1 < total_steps) load_x(step + 1, xpre);
+    // next step's X rows: loads in flight while the partials are summed,
+    // stored into LDS (free during the update) before the barrier
     {
       const int64_t per = (PT + G - 1) / G;
       const int64_t p0 = (int64_t)bid * per;
@@ -1009,20 +1014,23 @@ __global__ __launch_bounds__(kLT, 1) void k_large_train(LargeArgs a) {
       };
       // sum of partials g in [g0, g1) of parameter p, in increasing g; the
       // loads of a batch are all issued before the first add
+      // (32-bit offsets from the workspace's uniform base: Gi PT < 2^30)
       auto psum = [&](int64_t p, int g0, int g1) {
-        const float *src = a.gp + p;
+        const uint32_t pq = (uint32_t)p, ptq = (uint32_t)PT;
         float sum = 0.0f;
         for (int gb = g0; gb < g1; gb += kRedU) {
           float v[kRedU];
 #pragma unroll
-          for (int u = 0; u < kRedU; ++u) v[u] = (gb + u < g1) ? src[(int64_t)(gb + u) * PT] : 0.0f;
+          for (int u = 0; u < kRedU; ++u) v[u] = (gb + u < g1) ? a.gp[pq + (uint32_t)(gb + u) * ptq] : 0.0f;
 #pragma unroll
           for (int u = 0; u < kRedU; ++u)
             if (gb + u < g1) sum += v[u];
         }
         return sum;
       };
-      if (np <= 64) {
+      if (np <= 64 && a.Gi >= kNW) {
+        // few parameters, many partials: the waves split the partials and
+        // meet in LDS (fixed tree)
         const int g0 = (a.Gi * wave) / kNW, g1 = (a.Gi * (wave + 1)) / kNW;
         float w = 0.0f, c = 0.0f, sum = 0.0f;
         if (lane < np) {
@@ -1044,7 +1052,35 @@ __global__ __launch_bounds__(kLT, 1) void k_large_train(LargeArgs a) {
             for (int w8 = 0; w8 < kNW; w8 += 2 * st) v[w8] += v[w8 + st];
           update(p0 + lane, w, c, v[0]);
         }
+      } else if (a.Gi <= 4) {
+        // many parameters, at most 4 partials each (nets sharing X): kUpdU
+        // parameters per thread per batch, all their loads issued together
+        for (int q0 = 0; q0 < np; q0 += kUpdU * kLT) {
+          float w[kUpdU], c[kUpdU], v[kUpdU][4];
+#pragma unroll
+          for (int u = 0; u < kUpdU; ++u) {
+            const int q = q0 + u * kLT + tid;
+            const bool on = q < np;
+            const int64_t pp = p0 + (on ? q : 0);
+            w[u] = a.theta[pp];
+            c[u] = a.comp ? a.comp[pp] : 0.0f;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) v[u][g] = load_if(a.gp + (int64_t)g * PT + pp, a.gp, g < a.Gi);
+          }
+#pragma unroll
+          for (int u = 0; u < kUpdU; ++u) {
+            const int q = q0 + u * kLT + tid;
+            if (q < np) {
+              float sum = v[u][0];
+#pragma unroll
+              for (int g = 1; g < 4; ++g)
+                if (g < a.Gi) sum += v[u][g];
+              update(p0 + q, w[u], c[u], sum);
+            }
+          }
+        }
       } else {
+        // one parameter per thread, all of its partials in flight at once
         for (int q = tid; q < np; q += kLT) {
           const float w = a.theta[p0 + q], c = a.comp ? a.comp[p0 + q] : 0.0f;
           update(p0 + q, w, c, psum(p0 + q, 0, a.Gi));
@@ -1089,7 +1125,7 @@ __global__ void k_zero_u32(unsigned *p, int n) {
 // time over its rounds is the latency one barrier adds to a step when every
 // workgroup arrives together (the trainer pays three per step, plus the
 // wait for its slowest workgroup).
-__global__ __launch_bounds__(kLT) void k_barrier_probe(unsigned *bar, int rounds, uint64_t wait_limit) {
+__global__ __launch_bounds__(kProbeLT) void k_barrier_probe(unsigned *bar, int rounds, uint64_t wait_limit) {
   __shared__ int ok_s;
   GridSync gs;
   if (threadIdx.x == 0) ok_s = gs.init(bar, gridDim.x, wait_limit) ? 1 : 0;
@@ -1161,7 +1197,7 @@ namespace {
 
 constexpr int kMaxRowBlocks = 256, kMaxHiddenBlocks = 16;
 constexpr size_t kLdsLimit = 160 * 1024;
-int g_grid_rows = 0, g_grid_hidden = 0;  // launch hint (0: automatic)
+int g_grid_rows = 0, g_grid_hidden = 0, g_waves = 0;  // launch hint (0: automatic)
 constexpr int64_t kDefaultWaitUs = 5000000;  // a grid-barrier wait gives up after 5 s
 int64_t g_wait_us = kDefaultWaitUs;
 
@@ -1179,6 +1215,7 @@ uint64_t wait_ticks(std::string *err, bool *ok) {
 
 struct Plan {
   int Gi, Gj, Hp, RBP;
+  int nw;   // waves per workgroup (4 or 8)
   size_t lds;
 };
 
@@ -1267,31 +1304,38 @@ static bool plan_for(const mlp_config &c, int M, int n_cu, Plan *pl, std::string
   if (Hp / Gj > 256) { *why = "hidden block above 256 units"; return false; }
   if (Gi > max_row_blocks(M, Gj) || Gj > kMaxHiddenBlocks) { *why = "grid above the workspace plan"; return false; }
   if (b % Gi != 0 || (b / Gi) % 32 != 0) { *why = "rows per block must be a multiple of 32"; return false; }
-  // one workgroup (8 waves) per CU
+  // one workgroup per CU: 8 waves (two tiles each) for 256-unit hidden
+  // blocks, else 4
   const int G = Gi * M * Gj;
   if (G > n_cu) { *why = "grid above one workgroup per CU"; return false; }
   pl->Gi = Gi;
   pl->Gj = Gj;
   pl->Hp = Hp;
+  pl->nw = g_waves ? g_waves : (Hp / Gj >= 256 ? 8 : 4);
   pl->RBP = piece_rows(c.prec, Hp / Gj, (int)(b / Gi), kLdsLimit);
   if (pl->RBP == 0) { *why = "no row piece of the block fits the LDS"; return false; }
   pl->lds = lds_for(c.prec, Hp / Gj, pl->RBP);
   return true;
 }
 
-void set_large_grid_hint(int row_blocks, int hidden_blocks) {
+void set_large_grid_hint(int row_blocks, int hidden_blocks, int waves) {
   g_grid_rows = row_blocks;
   g_grid_hidden = hidden_blocks;
+  g_waves = waves;
 }
 
 void set_wait_limit_us(int64_t us) { g_wait_us = us < 0 ? kDefaultWaitUs : us; }
 
-// The kernel instance: operand type and output count (3 or 4).
-static const void *kernel_for(int prec, bool k3) {
+// The kernel instance: operand type, output count (3 or 4), waves.
+template <int NW>
+static const void *kernel_nw(int prec, bool k3) {
   using namespace mlpk;
-  if (prec == MLP_FP32) return k3 ? (const void *)k_large_train<0, 3> : (const void *)k_large_train<0, 4>;
-  if (prec == MLP_BF16) return k3 ? (const void *)k_large_train<1, 3> : (const void *)k_large_train<1, 4>;
-  return k3 ? (const void *)k_large_train<2, 3> : (const void *)k_large_train<2, 4>;
+  if (prec == MLP_FP32) return k3 ? (const void *)k_large_train<0, 3, NW> : (const void *)k_large_train<0, 4, NW>;
+  if (prec == MLP_BF16) return k3 ? (const void *)k_large_train<1, 3, NW> : (const void *)k_large_train<1, 4, NW>;
+  return k3 ? (const void *)k_large_train<2, 3, NW> : (const void *)k_large_train<2, 4, NW>;
+}
+static const void *kernel_for(int prec, bool k3, int nw) {
+  return nw == 8 ? kernel_nw<8>(prec, k3) : kernel_nw<4>(prec, k3);
 }
 
 mlp_status large_workspace_bytes(const mlp_config &c, int n_nets, size_t *bytes) {
@@ -1383,11 +1427,11 @@ mlp_status large_train(const mlp_config &c, int n_nets, const float *lrs, const 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) { *err = hipGetErrorString(e); return MLP_ERR_HIP; }
 
-  const void *kern = kernel_for(c.prec, c.n_out <= 3);
+  const void *kern = kernel_for(c.prec, c.n_out <= 3, pl.nw);
   e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.lds);
   if (e != hipSuccess) { *err = std::string("hipFuncSetAttribute: ") + hipGetErrorString(e); return MLP_ERR_HIP; }
   int per_cu = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, mlpk::kLT, pl.lds);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * pl.nw, pl.lds);
   if (e != hipSuccess) { *err = std::string("occupancy query: ") + hipGetErrorString(e); return MLP_ERR_HIP; }
   const int G = pl.Gi * n_nets * pl.Gj;
   if (per_cu * n_cu < G) {
@@ -1396,7 +1440,7 @@ mlp_status large_train(const mlp_config &c, int n_nets, const float *lrs, const 
     return MLP_ERR_UNSUPPORTED;
   }
   void *args[] = {&a};
-  e = hipLaunchCooperativeKernel(kern, dim3(G), dim3(mlpk::kLT), args, (unsigned)pl.lds, s);
+  e = hipLaunchCooperativeKernel(kern, dim3(G), dim3(64 * pl.nw), args, (unsigned)pl.lds, s);
   if (e != hipSuccess) { *err = std::string("cooperative launch: ") + hipGetErrorString(e); return MLP_ERR_HIP; }
   if (c.flags & MLP_F_CHECK_FINITE) {
     const int64_t P = D * H + H + H * K + K;
@@ -1452,7 +1496,8 @@ mlp_status barrier_probe(int n_wg, int rounds, void *ws, hipStream_t s, std::str
   uint64_t limit = wait_ticks(err, &tick_ok);
   if (!tick_ok) return MLP_ERR_HIP;
   void *args[] = {&bar, &rounds, &limit};
-  e = hipLaunchCooperativeKernel((const void *)mlpk::k_barrier_probe, dim3(n_wg), dim3(mlpk::kLT), args, 0, s);
+  e = hipLaunchCooperativeKernel((const void *)mlpk::k_barrier_probe, dim3(n_wg), dim3(mlpk::kProbeLT), args, 0,
+                                 s);
   if (e != hipSuccess) { *err = std::string("cooperative launch: ") + hipGetErrorString(e); return MLP_ERR_HIP; }
   return MLP_OK;
 }

@@ -115,7 +115,7 @@ const char *mlp_last_error(void) { return g_last_error.c_str(); }
 mlp_status mlp_set_launch_hint(const mlp_launch_hint *hint) {
   if (!hint) {
     g_hint = mlp_launch_hint{};
-    mlph::set_large_grid_hint(0, 0);
+    mlph::set_large_grid_hint(0, 0, 0);
     return MLP_OK;
   }
   const int t = hint->small_threads;
@@ -126,9 +126,10 @@ mlp_status mlp_set_launch_hint(const mlp_launch_hint *hint) {
     return fail(MLP_ERR_ARG, "large grid hint outside [0,256] x [0,16]");
   if ((hint->large_row_blocks == 0) != (hint->large_hidden_blocks == 0))
     return fail(MLP_ERR_ARG, "give both large grid dimensions or neither");
-  if (hint->reserved != 0) return fail(MLP_ERR_ARG, "reserved must be 0");
+  if (hint->large_waves != 0 && hint->large_waves != 4 && hint->large_waves != 8)
+    return fail(MLP_ERR_ARG, "large_waves must be 0, 4 or 8");
   g_hint = *hint;
-  mlph::set_large_grid_hint(hint->large_row_blocks, hint->large_hidden_blocks);
+  mlph::set_large_grid_hint(hint->large_row_blocks, hint->large_hidden_blocks, hint->large_waves);
   return MLP_OK;
 }
 

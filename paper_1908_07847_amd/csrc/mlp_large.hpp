@@ -12,8 +12,9 @@ namespace mlph {
 // (MLP_ERR_UNSUPPORTED when no kernel here covers cfg).
 mlp_status large_workspace_bytes(const mlp_config &cfg, int n_nets, size_t *bytes);
 
-// Launch hint for the Gi x Gj grid (0, 0: automatic).
-void set_large_grid_hint(int row_blocks, int hidden_blocks);
+// Launch hint for the Gi x Gj grid (0, 0: automatic) and the waves per
+// workgroup (0: automatic, else 4 or 8).
+void set_large_grid_hint(int row_blocks, int hidden_blocks, int waves);
 
 // Longest a grid-barrier wait may take before it gives up (microseconds;
 // negative: the default of 5 s).

@@ -322,10 +322,10 @@ def train_shared(X: torch.Tensor, T: torch.Tensor, theta: torch.Tensor, lrs, epo
     return loss_hist
 
 
-def set_launch_hint(small_threads: int = 0, large_grid: tuple[int, int] | None = None) -> None:
+def set_launch_hint(small_threads: int = 0, large_grid: tuple[int, int] | None = None, large_waves: int = 0) -> None:
     """Launch-shape override for the autotuner (0 / None: the library's choice)."""
     gi, gj = large_grid if large_grid else (0, 0)
-    h = LaunchHint(int(small_threads), int(gi), int(gj), 0)
+    h = LaunchHint(int(small_threads), int(gi), int(gj), int(large_waves))
     check(lib.mlp_set_launch_hint(ctypes.byref(h)))
 
 

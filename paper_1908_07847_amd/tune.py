@@ -1,14 +1,16 @@
 """Autotuner for libmlp launch shapes.
 
-Two choices are tuned, both through `mlp_set_launch_hint` (include/mlp.h):
+Choices tuned through `mlp_set_launch_hint` (include/mlp.h):
 
   * small / batched trainer: waves per net (128, 256 or 512 threads).  More
     waves shorten one net's epoch (fewer row tiles per wave); fewer waves let
     more nets share a CU.
-  * large-N trainer: the Gi x Gj grid (row blocks x hidden blocks).  More
-    row blocks spread the minibatch wider but add partial gradients to sum;
-    more hidden blocks shrink each workgroup's tile but add the cross-block
-    output exchange.
+  * large-N trainer: the Gi x Gj grid (row blocks x hidden blocks) and the
+    waves per workgroup (4 or 8).  More row blocks spread the minibatch wider
+    but add partial gradients to sum; more hidden blocks shrink each
+    workgroup's tile but add the cross-block output exchange; 8 waves (two
+    per SIMD) overlap one wave's matrix-core work with another's vector work
+    but halve each wave's registers.
 
 Each candidate is timed on the caller's own data for a short run (HIP
 events on the current stream) and the fastest is cached in a JSON file
@@ -133,27 +135,30 @@ def tune_batched(plan: "mlp.BatchPlan", X, T, theta, n_in: int, n_out: int, epoc
 
 def tune_large(n_in: int, n_hidden: int, n_out: int, batch: int, prec: str, X, T, theta,
                steps: int = 8, force: bool = False):
-    """Pick the Gi x Gj grid of the large-N trainer by timing `steps`
-    minibatches of the caller's data (parameters are copied, not modified)."""
+    """Pick the Gi x Gj grid and the waves per workgroup of the large-N
+    trainer by timing `steps` minibatches of the caller's data (parameters
+    are copied, not modified).  Returns (Gi, Gj, waves)."""
     key = large_key(n_in, n_hidden, batch, prec)
     cached = _load_cache().get(key)
-    if cached and not force:
-        return tuple(cached["grid"])
+    if cached and not force and "waves" in cached:
+        return tuple(cached["grid"]) + (int(cached["waves"]),)
     n_cu = torch.cuda.get_device_properties(0).multi_processor_count
     rows = min(X.shape[0], steps * batch)
     Xs, Ts = X[:rows], T[:rows]
     times = {}
     for grid in large_candidates(n_hidden, batch, n_cu):
-        mlp.set_launch_hint(large_grid=grid)
-        try:
-            net = mlp.Net(n_in, n_hidden, n_out, rows, batch=batch, prec=prec, theta=theta)
-            times[grid] = _time(lambda: net.train(Xs, Ts, 1, record_loss=False))
-        except MLPError:
-            continue
-        finally:
-            mlp.reset_launch_hint()
+        for waves in (4, 8):
+            mlp.set_launch_hint(large_grid=grid, large_waves=waves)
+            try:
+                net = mlp.Net(n_in, n_hidden, n_out, rows, batch=batch, prec=prec, theta=theta)
+                times[grid + (waves,)] = _time(lambda: net.train(Xs, Ts, 1, record_loss=False))
+            except MLPError:
+                continue
+            finally:
+                mlp.reset_launch_hint()
     best = min(times, key=times.get)
-    _store(key, {"grid": list(best), "ms": {f"{g[0]}x{g[1]}": v for g, v in times.items()},
+    _store(key, {"grid": list(best[:2]), "waves": best[2],
+                 "ms": {f"{g[0]}x{g[1]}x{g[2]}": v for g, v in times.items()},
                  "steps": rows // batch, "when": time.time()})
     return best
 
@@ -171,6 +176,6 @@ def apply_large(n_in: int, n_hidden: int, batch: int, prec: str) -> bool:
     """Set the cached grid hint for this shape, if any."""
     c = _load_cache().get(large_key(n_in, n_hidden, batch, prec))
     if c:
-        mlp.set_launch_hint(large_grid=tuple(c["grid"]))
+        mlp.set_launch_hint(large_grid=tuple(c["grid"]), large_waves=int(c.get("waves", 0)))
         return True
     return False

@@ -261,24 +261,27 @@ def test_wide_workload_65536_row_subset_error_vs_exact_oracle(M):
         assert lerr <= l_tol and max(errs.values()) <= w_tol, (prec, errs, lerr)
 
 
-@pytest.mark.parametrize("wl,n,batch,grid,prec,tol", [
-    (4, 8 * 4096, 4096, (64, 4), "fp32", TOL),     # 64-unit hidden blocks: half the waves own no tile
-    (4, 8 * 4096, 4096, (32, 1), "fp32", TOL),     # one 256-unit hidden block: two tiles per wave
-    (5, 2 * 16384, 16384, (32, 8), "fp32", TOL),   # 512-row blocks staged in LDS in pieces
-    (5, 2 * 16384, 16384, (32, 8), "bf16", 1e-3)])
-def test_hinted_grids_keep_parity(M, wl, n, batch, grid, prec, tol):
-    """Grids other than the automatic one (set through the launch hint the
-    autotuner uses) still match the oracle (bf16 within its many-step
-    sanity gate)."""
+@pytest.mark.parametrize("wl,n,batch,grid,waves,prec,tol", [
+    (4, 8 * 4096, 4096, (64, 4), 8, "fp32", TOL),     # 64-unit hidden blocks: half the waves own no tile
+    (4, 8 * 4096, 4096, (32, 1), 8, "fp32", TOL),     # one 256-unit hidden block: two tiles per wave
+    (4, 8 * 4096, 4096, (32, 1), 4, "fp32", TOL),     # four waves of four tiles
+    (4, 8 * 4096, 4096, (128, 2), 8, "bf16", 1e-3),   # eight waves of one tile
+    (5, 2 * 16384, 16384, (64, 4), 4, "fp32", TOL),   # the wide net on four waves
+    (5, 2 * 16384, 16384, (32, 8), 8, "fp32", TOL),   # 512-row blocks staged in LDS in pieces
+    (5, 2 * 16384, 16384, (32, 8), 4, "bf16", 1e-3)])
+def test_hinted_grids_keep_parity(M, wl, n, batch, grid, waves, prec, tol):
+    """Grids and wave counts other than the automatic ones (set through the
+    launch hint the autotuner uses) still match the oracle (bf16 within its
+    many-step sanity gate)."""
     w = synth.single(wl, n_rows=n)
-    M.set_launch_hint(large_grid=grid)
+    M.set_launch_hint(large_grid=grid, large_waves=waves)
     try:
         _, flat, hist = gpu_train(M, w["X"], w["T"], w["theta"], 2, batch, prec=prec)
     finally:
         M.reset_launch_hint()
     q, ref_hist = oracle.train(w["X"], w["T"], Params.of(w["theta"]), 0.1, 2, batch=batch)
     errs = errors(flat, q)
-    say(f"  workload {wl} {prec} grid {grid}: {errs}")
+    say(f"  workload {wl} {prec} grid {grid} waves {waves}: {errs}")
     assert max(errs.values()) <= tol
     assert float(np.max(np.abs(hist - ref_hist) / ref_hist)) <= tol
 
