@@ -1,0 +1,115 @@
+"""GPU parity at the workloads' stated sizes (marked slow as well as gpu).
+
+  * batched: every one of the 4096 independent nets, 2000 full-batch epochs,
+    against the float64 oracle (oracle.train_many, one net per host thread);
+  * large-N: all 1,048,576 rows of the 33-256-3 workload for 20 epochs of
+    4096-row minibatches (5,120 steps), float32, against the float64
+    oracle's result stored by tests/golden/make_fullsize.py;
+  * wide: the 64-1024-3 net on the first 65,536 rows for 5 epochs (20
+    steps of 16384 rows): float32 within 1e-5 of the stored float64 result,
+    bf16 and e4m3 operands against the same exact result within their
+    sanity gates (reported).
+
+float32 bar: max|gpu - oracle| / max|oracle| <= 1e-5 per tensor (per net) and
+for the loss history.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import Params
+from paper_1908_07847_amd import synth
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+TOL = 1e-5
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def normwise(got, ref):
+    got, ref = np.asarray(got, np.float64), np.asarray(ref, np.float64)
+    return float(np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-30))
+
+
+def tensor_errors(flat_gpu, flat_ref, d, h, k):
+    g = synth.Theta.unpack(np.asarray(flat_gpu), d, h, k)
+    r = synth.Theta.unpack(np.asarray(flat_ref), d, h, k)
+    return {n: normwise(getattr(g, n), getattr(r, n)) for n in ("W1", "b1", "W2", "b2")}
+
+
+@pytest.fixture(scope="module")
+def M():
+    from paper_1908_07847_amd import mlp
+    return mlp
+
+
+def test_every_batched_net_at_2000_epochs(M):
+    w = synth.batched()
+    items, epochs = w["items"], w["epochs"]
+    plan = M.BatchPlan(items)
+    X = torch.from_numpy(w["X"]).cuda()
+    T = torch.from_numpy(w["T"]).cuda()
+    th = torch.from_numpy(w["theta"]).cuda()
+    hist = torch.empty((len(items), epochs), device="cuda")
+    M.train_batched(plan, X, T, th, torch.zeros_like(th), epochs, 33, 3, loss_hist=hist)
+    torch.cuda.synchronize()
+    got = th.cpu().numpy()
+    h = np.empty((len(items), epochs), dtype=np.float32)
+    h[plan.order] = hist.cpu().numpy()
+    say(f"batched: {len(items)} nets x {epochs} epochs on the GPU; the oracle on {oracle.max_threads()} threads")
+    ref, ref_hist = oracle.train_many(items, w["X"], w["T"], w["theta"], 33, 3, epochs, threads=0)
+    worst, worst_net = 0.0, -1
+    for i, it in enumerate(items):
+        s = slice(it["p_off"], it["p_off"] + synth.n_params(33, it["n_hidden"], 3))
+        e = max(tensor_errors(got[s], ref[s], 33, it["n_hidden"], 3).values())
+        e = max(e, normwise(h[i], ref_hist[i]))
+        if e > worst:
+            worst, worst_net = e, i
+    say(f"  worst normwise error over every net and tensor and the loss histories: {worst:.2e} (net {worst_net})")
+    assert worst <= TOL
+
+
+def _golden(name):
+    path = os.path.join(GOLDEN, f"fullsize_{name}.npz")
+    with np.load(path, allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
+def _train(M, w, epochs, prec):
+    net = M.Net(w["D"], w["H"], w["K"], w["X"].shape[0], batch=w["batch"], lr=w["lr"], prec=prec, theta=w["theta"])
+    X = torch.from_numpy(w["X"]).cuda()
+    T = torch.from_numpy(w["T"]).cuda()
+    hist = net.train(X, T, epochs)
+    torch.cuda.synchronize()
+    assert net.status() == 0
+    return net.flat.cpu().numpy(), hist.cpu().numpy()
+
+
+def test_large_n_workload_full_size_fp32(M):
+    g = _golden("w4")
+    w = synth.single(4)
+    assert int(g["rows"]) == w["X"].shape[0] and int(g["batch"]) == w["batch"]
+    flat, hist = _train(M, w, int(g["epochs"]), "fp32")
+    errs = tensor_errors(flat, g["theta"], w["D"], w["H"], w["K"])
+    lerr = normwise(hist, g["loss_hist"])
+    say(f"large-N full size, {int(g['epochs'])} epochs: params {errs} loss history {lerr:.2e}")
+    assert max(errs.values()) <= TOL and lerr <= TOL
+
+
+@pytest.mark.parametrize("prec,w_tol,l_tol", [("fp32", TOL, TOL), ("bf16", 1e-2, 1e-3), ("e4m3", 1e-1, 5e-2)])
+def test_wide_workload_65536_rows_5_epochs(M, prec, w_tol, l_tol):
+    g = _golden("w5")
+    w = synth.single(5, n_rows=int(g["rows"]))
+    flat, hist = _train(M, w, int(g["epochs"]), prec)
+    errs = tensor_errors(flat, g["theta"], w["D"], w["H"], w["K"])
+    lerr = normwise(hist, g["loss_hist"])
+    say(f"wide net, {int(g['rows'])} rows, {int(g['epochs'])} epochs, {prec}: params {errs} loss history {lerr:.2e}")
+    assert max(errs.values()) <= w_tol and lerr <= l_tol
