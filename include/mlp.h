@@ -282,6 +282,26 @@ mlp_status mlp_train_shared(const mlp_config *cfg /*host*/, int32_t n_nets, cons
                             const float *X, const float *T, float *theta, float *comp, int32_t epochs,
                             float *loss_hist, void *workspace, size_t ws_bytes, void *stream);
 
+/* Allocation-free form of mlp_train_shared, for callers that cannot
+ * allocate device memory or pass a workspace (code under HIP-graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ * semantics and results (bitwise equal to mlp_train_shared on the same
+ * device and shape) except that the scratch the kernels need lives in a
+ * fixed device array inside the library: 32 MiB (MLP_STATIC_SCRATCH_BYTES),
+ * one copy per GPU the library runs on, held until the process ends.  The
+ * call allocates nothing, looks the array's address up on its first call on
+ * a device, and rejects with MLP_ERR_WORKSPACE a shape whose grid needs more
+ * scratch than that (e.g. the 64-1024-3 net fits; 64 such nets sharing X do
+ * not -- use mlp_train_shared).  Every call on one GPU shares its array:
+ * calls that overlap on that GPU (different streams, threads or processes
+ * without ordering) race and must not be made.  The status block is not
+ * reachable by the caller: a grid-barrier wait that gave up shows as NaN in
+ * loss_hist, and MLP_F_CHECK_FINITE is rejected (MLP_ERR_UNSUPPORTED). */
+#define MLP_STATIC_SCRATCH_BYTES (32u << 20)
+mlp_status mlp_train_shared_static(const mlp_config *cfg /*host*/, int32_t n_nets, const float *lr /*host*/,
+                                   const float *X, const float *T, float *theta, float *comp, int32_t epochs,
+                                   float *loss_hist, void *stream);
+
 /* ---- networks with several hidden layers ----------------------------------- */
 
 /* One fully connected layer of a deeper network (section 2.2's layer,

@@ -20,6 +20,7 @@ PREC = {"fp32": 0, "bf16": 1, "e4m3": 2}
 MLP_F_COMPENSATED = 1
 SMALL_MAX_ROWS, SMALL_MAX_HIDDEN, SMALL_MAX_IN, SMALL_MAX_OUT = 128, 64, 48, 4
 MAX_SHARED_NETS = 64
+STATIC_SCRATCH_BYTES = 32 << 20   # MLP_STATIC_SCRATCH_BYTES
 
 
 class MLPError(RuntimeError):
@@ -57,7 +58,7 @@ BARRIER_PROBE_WS_BYTES = 2048   # MLP_BARRIER_PROBE_WS_BYTES
 
 SYMBOLS = ["mlp_workspace_size", "mlp_init", "mlp_destroy", "mlp_forward", "mlp_backward", "mlp_step",
            "mlp_train", "mlp_predict", "mlp_train_batched", "mlp_eval_batched", "mlp_shared_workspace_size",
-           "mlp_train_shared", "mlp_barrier_probe", "mlp_set_momentum", "mlp_dense_forward", "mlp_dense_backward",
+           "mlp_train_shared", "mlp_train_shared_static", "mlp_barrier_probe", "mlp_set_momentum", "mlp_dense_forward", "mlp_dense_backward",
            "mlp_update", "mlp_mse_grad", "mlp_deep_train", "mlp_query_status", "mlp_workspace_status",
            "mlp_set_wait_limit", "mlp_mfma_probe", "mlp_set_launch_hint", "mlp_status_string", "mlp_last_error"]
 
@@ -83,6 +84,8 @@ def _load():
     lib.mlp_shared_workspace_size.argtypes = [ctypes.POINTER(Config), i32, ctypes.POINTER(ctypes.c_size_t)]
     lib.mlp_train_shared.argtypes = [ctypes.POINTER(Config), i32, ctypes.POINTER(f32), vp, vp, vp, vp, i32, vp,
                                      vp, ctypes.c_size_t, vp]
+    lib.mlp_train_shared_static.argtypes = [ctypes.POINTER(Config), i32, ctypes.POINTER(f32), vp, vp, vp, vp, i32,
+                                            vp, vp]
     lib.mlp_set_launch_hint.argtypes = [ctypes.POINTER(LaunchHint)]
     lib.mlp_barrier_probe.argtypes = [i32, i32, vp, ctypes.c_size_t, vp]
     lib.mlp_set_momentum.argtypes = [vp, f32, vp]

@@ -31,6 +31,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <mutex>
 #include <cstdio>
 #include <cstdlib>
 #include <string>
@@ -1503,6 +1504,59 @@ mlp_status barrier_probe(int n_wg, int rounds, void *ws, hipStream_t s, std::str
 }
 
 size_t barrier_probe_workspace_bytes() { return sizeof(unsigned) * mlpk::kBarWords; }
+
+// ---------------------------------------------------------------- allocation-free entry
+// Scratch of mlp_train_shared_static: device memory of fixed size in the
+// code object, one copy per GPU the library is loaded on.  Host code never
+// passes the array's name to a kernel (on the host it is only a stand-in):
+// its device address is looked up once per device and kept.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+mlp_status scratch_of_current_device(void **out, std::string *err) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) { *err = std::string("hipGetDevice: ") + hipGetErrorString(e); return MLP_ERR_HIP; }
+  if (dev < 0 || dev >= kMaxDevices) { *err = "device index above the supported 64"; return MLP_ERR_UNSUPPORTED; }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      *err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return MLP_ERR_HIP;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return MLP_OK;
+}
+}  // namespace
+
+mlp_status large_train_static(const mlp_config &c, int n_nets, const float *lrs, const mlp_params &theta,
+                              float *comp, int n_cu, const float *X, const float *T, int epochs, float *loss_hist,
+                              hipStream_t s, std::string *err) {
+  Plan pl;
+  std::string why;
+  if (!plan_for(c, n_nets, n_cu, &pl, &why)) {
+    *err = "no grid for this shape: " + why;
+    return MLP_ERR_UNSUPPORTED;
+  }
+  const size_t need = ws_layout(c, n_nets, pl.Gi, pl.Gj).total;
+  if (need > kStaticScratchBytes) {
+    *err = "this shape needs " + std::to_string(need) + " bytes of scratch; the static scratch holds " +
+           std::to_string(kStaticScratchBytes) + " (use mlp_train_shared with a workspace)";
+    return MLP_ERR_WORKSPACE;
+  }
+  void *ws = nullptr;
+  const mlp_status st = scratch_of_current_device(&ws, err);
+  if (st != MLP_OK) return st;
+  return large_train(c, n_nets, lrs, theta, comp, ws, kStaticScratchBytes, n_cu, X, T, epochs, loss_hist, s, err);
+}
 
 hipError_t launch_mfma_probe(int prec, const float *A, const float *B, float *C, int M, int N, int Kd,
                              hipStream_t s) {

@@ -390,11 +390,13 @@ mlp_status mlp_shared_workspace_size(const mlp_config *cfg, int32_t n_nets, size
   return MLP_OK;
 }
 
-mlp_status mlp_train_shared(const mlp_config *cfg, int32_t n_nets, const float *lr, const float *X,
-                            const float *T, float *theta, float *comp, int32_t epochs, float *loss_hist,
-                            void *workspace, size_t ws_bytes, void *stream) {
-  size_t need = 0;
-  mlp_status s = mlp_shared_workspace_size(cfg, n_nets, &need);
+namespace {
+// Argument checks shared by mlp_train_shared and mlp_train_shared_static
+// (host only, before any HIP call).
+mlp_status check_shared(const mlp_config *cfg, int32_t n_nets, const float *lr, const float *X, const float *T,
+                        const float *theta, const float *comp, int32_t epochs, const float *loss_hist,
+                        size_t *ws_need) {
+  mlp_status s = mlp_shared_workspace_size(cfg, n_nets, ws_need);
   if (s != MLP_OK) return s;
   if (!X || !T || !theta) return fail(MLP_ERR_ARG, "X, T and theta must not be NULL");
   if ((cfg->flags & MLP_F_COMPENSATED) && !comp)
@@ -410,19 +412,52 @@ mlp_status mlp_train_shared(const mlp_config *cfg, int32_t n_nets, const float *
   if (!aligned16(X) || !aligned16(T)) return fail(MLP_ERR_ALIGN, "X and T must be 16-byte aligned");
   if (!aligned4(theta) || (comp && !aligned4(comp)) || (loss_hist && !aligned4(loss_hist)))
     return fail(MLP_ERR_ALIGN, "theta, comp and loss_hist must be 4-byte aligned");
+  return MLP_OK;
+}
+
+mlp_status device_cus(int *ncu) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  e = hipDeviceGetAttribute(ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+  return MLP_OK;
+}
+}  // namespace
+
+mlp_status mlp_train_shared(const mlp_config *cfg, int32_t n_nets, const float *lr, const float *X,
+                            const float *T, float *theta, float *comp, int32_t epochs, float *loss_hist,
+                            void *workspace, size_t ws_bytes, void *stream) {
+  size_t need = 0;
+  mlp_status s = check_shared(cfg, n_nets, lr, X, T, theta, comp, epochs, loss_hist, &need);
+  if (s != MLP_OK) return s;
   if (!workspace || ws_bytes < need)
     return fail(MLP_ERR_WORKSPACE, "workspace of %zu bytes given, %zu needed", workspace ? ws_bytes : 0, need);
   if (!aligned16(workspace)) return fail(MLP_ERR_ALIGN, "workspace must be 16-byte aligned");
   if (epochs == 0) return MLP_OK;
-  int dev = 0, ncu = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-  e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+  int ncu = 0;
+  if ((s = device_cus(&ncu)) != MLP_OK) return s;
   const int64_t D = cfg->n_in, H = cfg->n_hidden, K = cfg->n_out;
   mlp_params p{theta, theta + D * H, theta + D * H + H, theta + D * H + H + H * K};
   return mlph::large_train(*cfg, n_nets, lr, p, (cfg->flags & MLP_F_COMPENSATED) ? comp : nullptr, workspace,
                            ws_bytes, ncu, X, T, epochs, loss_hist, (hipStream_t)stream, &g_last_error);
+}
+
+mlp_status mlp_train_shared_static(const mlp_config *cfg, int32_t n_nets, const float *lr, const float *X,
+                                   const float *T, float *theta, float *comp, int32_t epochs, float *loss_hist,
+                                   void *stream) {
+  size_t need = 0;
+  mlp_status s = check_shared(cfg, n_nets, lr, X, T, theta, comp, epochs, loss_hist, &need);
+  if (s != MLP_OK) return s;
+  if (cfg->flags & MLP_F_CHECK_FINITE)
+    return fail(MLP_ERR_UNSUPPORTED, "the finite check reports through a workspace; use mlp_train_shared");
+  if (epochs == 0) return MLP_OK;
+  int ncu = 0;
+  if ((s = device_cus(&ncu)) != MLP_OK) return s;
+  const int64_t D = cfg->n_in, H = cfg->n_hidden, K = cfg->n_out;
+  mlp_params p{theta, theta + D * H, theta + D * H + H, theta + D * H + H + H * K};
+  return mlph::large_train_static(*cfg, n_nets, lr, p, (cfg->flags & MLP_F_COMPENSATED) ? comp : nullptr, ncu, X, T,
+                                  epochs, loss_hist, (hipStream_t)stream, &g_last_error);
 }
 
 mlp_status mlp_barrier_probe(int32_t n_workgroups, int32_t rounds, void *workspace, size_t ws_bytes,

@@ -41,6 +41,15 @@ mlp_status large_train(const mlp_config &cfg, int n_nets, const float *lrs, cons
                        float *comp, void *ws, size_t ws_bytes, int n_cu, const float *X, const float *T,
                        int epochs, float *loss_hist, hipStream_t s, std::string *err);
 
+// Bytes of the static scratch behind mlp_train_shared_static (per device).
+constexpr size_t kStaticScratchBytes = (size_t)32 << 20;
+
+// large_train on the static scratch of the current device (nothing is
+// allocated); MLP_ERR_WORKSPACE when the plan needs more than it holds.
+mlp_status large_train_static(const mlp_config &cfg, int n_nets, const float *lrs, const mlp_params &theta,
+                              float *comp, int n_cu, const float *X, const float *T, int epochs, float *loss_hist,
+                              hipStream_t s, std::string *err);
+
 // Grid-barrier probe (cooperative launch of n_wg workgroups, `rounds`
 // barriers); ws holds barrier_probe_workspace_bytes() of counters.
 mlp_status barrier_probe(int n_wg, int rounds, void *ws, hipStream_t s, std::string *err);
