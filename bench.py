@@ -408,16 +408,16 @@ def bench_batched(args):
 
     w = synth.batched(heldout=True)
     items = w["items"]
-    plan = mlp.BatchPlan(items)
+    plan = mlp.BatchPlan(items, buckets=not args.no_buckets)
     X = torch.from_numpy(w["X"]).cuda()
     T = torch.from_numpy(w["T"]).cuda()
     th = torch.from_numpy(w["theta"]).cuda()
     comp = torch.zeros_like(th)
     steps = args.steps if args.steps is not None else w["epochs"]
     warmup = args.warmup if args.warmup is not None else 5
-    # launch shape from the autotuner (timed on copies, cached per device and shape)
+    # launch shape of each size group from the autotuner (timed on copies,
+    # cached per device and group shape)
     threads = tune.tune_batched(plan, X, T, th, 33, 3, epochs=20)
-    mlp.set_launch_hint(small_threads=threads)
     if warmup:
         mlp.train_batched(plan, X, T, th.clone(), torch.zeros_like(th), warmup, 33, 3)
     hist = torch.empty((len(items), steps), device="cuda")
@@ -426,7 +426,6 @@ def bench_batched(args):
     stream = torch.cuda.current_stream()
     wall, kern = timed(graph.replay, stream)
     reps = repeats(graph.replay, stream, wall, steps)
-    mlp.reset_launch_hint()
     # plain form: the single-network kernel launched once per net, one net
     # after another, on the first 32 nets
     sample = items[:32]
@@ -476,7 +475,9 @@ def bench_batched(args):
         config={"workload": "batched: 4096 independent 33-H-3 nets, H~U{4..64}, 40..120 rows each "
                             "(5-fold CV splits), lr~logU(0.01,1), full batch, one launch",
                 "nets": len(items), "total_rows": rows, "step": "one epoch of every net",
-                "threads_per_net": threads, "launch": "hipGraph replay of one persistent kernel"},
+                "threads_per_net": threads,
+                "groups": [{"nets": c, "max_rows": r, "max_hidden": h} for (_, c, r, h) in plan.groups],
+                "launch": "hipGraph replay of one trainer launch per size group"},
         cv_eval={"kernel": "mlpk::k_eval_batched", "ms": eval_s * 1e3, "heldout_rows": vrows,
                  "rows_per_s": vrows / eval_s, "best_group": best, "best_group_hidden": int(
                      w["items_val"][int(np.nonzero(groups == best)[0][0])]["n_hidden"]),
@@ -703,6 +704,17 @@ def bench_autograd(args):
         net.set_theta(w["theta"])
     stream = torch.cuda.current_stream()
     wall, kern = timed(lambda: epochs(steps), stream)
+    # the same epochs as library calls only (forward, the library's MSE
+    # adjoint, update) replayed from a HIP graph of G epochs
+    G = 50
+    gnet = mlp.Net(D, H, K, N, lr=w["lr"], theta=w["theta"])
+    gep = mlp.NetEpochs(gnet, X, T).graph(G)
+
+    def run_graph():
+        for r in range(max(steps // G, 1)):
+            gep.replay()
+    gwall, _ = timed(run_graph, stream)
+    gsteps = max(steps // G, 1) * G
     P = D * H + H + H * K + K
     flops = flops_per_sample_epoch(D, H, K) * N * steps + 2 * P * steps
     achieved = flops / kern / 1e12
@@ -716,6 +728,9 @@ def bench_autograd(args):
                   "frac": achieved / PEAK["fp32"], "traffic": None, "traffic_unit": "bytes per launch",
                   "kernel": "mlpk::k_forward_tiled + k_backward_rows + k_backward_sum + k_step (per epoch)",
                   "kernel_ms": kern * 1e3, "flops_per_launch": flops},
+        graph={"value": N * gsteps / gwall, "ms_per_step": gwall * 1e3 / gsteps, "epochs": gsteps,
+               "form": f"per epoch mlp_forward, mlp_backward (the library's MSE adjoint) and mlp_step as library "
+                       f"calls, replayed from a HIP graph of {G} epochs (no torch autograd inside the capture)"},
         final_loss=float(hist[steps - 1].item()) if steps else None, steps=steps, warmup=warmup)
     return res, dict(w=w, wl=2, batch=N)
 
@@ -799,6 +814,7 @@ def main():
     ap.add_argument("--momentum", type=float, default=0.0, help="heavy-ball rate (w1, w2; 0 = the paper's GD)")
     ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-buckets", action="store_true", help="w3: one launch for all nets (no size groups)")
     ap.add_argument("--copy-probe", action="store_true", help="only run a 1 GiB device copy (counter scale)")
     args = ap.parse_args()
     if args.copy_probe:

@@ -205,6 +205,57 @@ def set_wait_limit(microseconds: int) -> None:
     check(lib.mlp_set_wait_limit(int(microseconds)))
 
 
+class NetEpochs:
+    """Full-batch epochs of a one-hidden-layer Net as library calls only:
+    per epoch mlp_forward (hidden activations and outputs into fixed
+    buffers), mlp_backward with the mean-squared-error reading (dY = NULL,
+    the loss written to a device slot) and mlp_step.  `graph(epochs)`
+    captures that many epochs in a HIP graph (torch.cuda.CUDAGraph) whose
+    replays train the net in place, with no host work between the kernels
+    and no torch operation inside the capture."""
+
+    def __init__(self, net: "Net", X: torch.Tensor, T: torch.Tensor):
+        self.net, self.X, self.T = net, X, T
+        n = X.shape[0]
+        self.A = torch.empty((n, net.H), dtype=torch.float32, device=net.device)
+        self.Y = torch.empty((n, net.K), dtype=torch.float32, device=net.device)
+        self.grads = net.new_grads()
+        self.loss = None
+        self.cuda_graph = None
+
+    def run(self, epochs: int, loss_hist: torch.Tensor, stream=None) -> None:
+        """`epochs` epochs now (eagerly); loss_hist[e] gets epoch e's loss."""
+        net, n, st = self.net, self.X.shape[0], _stream(stream)
+        for e in range(epochs):
+            check(lib.mlp_forward(net._h, _ptr(self.X), n, _ptr(self.A), _ptr(self.Y), st))
+            check(lib.mlp_backward(net._h, _ptr(self.X), _ptr(self.A), _ptr(self.Y), None, _ptr(self.T), n,
+                                   self.grads.c(), None, loss_hist[e:e + 1].data_ptr(), st))
+            check(lib.mlp_step(net._h, self.grads.c(), float(net.lr), st))
+
+    def graph(self, epochs: int) -> "NetEpochs":
+        """Capture `epochs` epochs (after one eager epoch that loads every
+        kernel; the parameters are restored); `replay()` runs them."""
+        if epochs <= 0:
+            raise ValueError("epochs must be positive")
+        net = self.net
+        self.loss = torch.empty(max(epochs, 4), dtype=torch.float32, device=net.device)[:epochs]
+        flat0 = net.flat.detach().clone()
+        comp0 = net.comp.clone() if net.comp is not None else None
+        self.run(1, self.loss)
+        torch.cuda.synchronize()
+        net.flat.detach().copy_(flat0)
+        if comp0 is not None:
+            net.comp.copy_(comp0)
+        torch.cuda.synchronize()
+        self.cuda_graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.cuda_graph, capture_error_mode="thread_local"):
+            self.run(epochs, self.loss)
+        return self
+
+    def replay(self) -> None:
+        self.cuda_graph.replay()
+
+
 def theta_packed(theta) -> np.ndarray:
     if hasattr(theta, "packed"):
         return theta.packed()
@@ -219,17 +270,40 @@ class BatchPlan:
     greedy longest-processing-time schedule over the hardware's workgroup
     dispatcher.  Results are indexed by the caller's net index regardless of
     the order.
+
+    With `buckets=True` the nets are grouped by size -- hidden units in
+    16-unit tiles (up to 16, 32 or 64 units) and rows up to 64 or 128 --
+    and each group is one launch (largest group cost first, longest first
+    inside a group): a launch reserves LDS and registers for its largest
+    net, so grouping lets the many smaller nets run more workgroups per CU.
+    `groups` lists (start, count, max_rows, max_hidden) in plan order, and
+    `threads[g]` (0: the library's choice) is the launch shape of group g,
+    set by the autotuner (tune.tune_batched).
     """
 
-    def __init__(self, items, device="cuda", order: str = "lpt"):
+    def __init__(self, items, device="cuda", order: str = "lpt", buckets: bool = False):
         n = len(items)
         cost = np.array([it["n_rows"] * it["n_hidden"] for it in items], dtype=np.int64)
         if isinstance(order, str) and order == "lpt":
-            self.order = np.argsort(-cost, kind="stable")
+            lpt = np.argsort(-cost, kind="stable")
+            if buckets:
+                key = np.array([((it["n_hidden"] + 15) // 16 + 1) // 2 * 2 if it["n_hidden"] > 16 else 1
+                                for it in items]) * 2 + np.array([it["n_rows"] > 64 for it in items])
+                groups = {}
+                for i in lpt:
+                    groups.setdefault(int(key[i]), []).append(int(i))
+                members = sorted(groups.values(), key=lambda g: -int(cost[g].sum()))
+                self.order = np.array([i for g in members for i in g], dtype=np.int64)
+                sizes = [len(g) for g in members]
+            else:
+                self.order = lpt
+                sizes = [n]
         elif isinstance(order, str) and order == "given":
             self.order = np.arange(n)
+            sizes = [n]
         else:
             self.order = np.asarray(order)
+            sizes = [n]
         arr = (BatchItem * n)()
         for pos, i in enumerate(self.order):
             it = items[int(i)]
@@ -241,23 +315,62 @@ class BatchPlan:
         self.dev = torch.from_numpy(raw).to(device)
         self.max_rows = int(max(it["n_rows"] for it in items))
         self.max_hidden = int(max(it["n_hidden"] for it in items))
+        self.groups = []
+        self.side_streams = []
+        start = 0
+        for c in sizes:
+            sel = [items[int(i)] for i in self.order[start:start + c]]
+            self.groups.append((start, c, int(max(it["n_rows"] for it in sel)),
+                                int(max(it["n_hidden"] for it in sel))))
+            start += c
+        self.threads = [0] * len(self.groups)
+        if len(self.groups) > 1:
+            self.side_streams = [torch.cuda.Stream(device=device) for _ in range(min(len(self.groups), 3))]
+
+    def host_at(self, start: int):
+        """Pointer to the host item table from position `start`."""
+        return ctypes.cast(ctypes.addressof(self.host) + start * ctypes.sizeof(BatchItem), ctypes.POINTER(BatchItem))
 
 
 def train_batched(plan: BatchPlan, X: torch.Tensor, T: torch.Tensor, theta: torch.Tensor,
                   comp: torch.Tensor | None, epochs: int, n_in: int, n_out: int,
-                  loss_hist: torch.Tensor | None = None, stream=None):
-    """Train every net of the plan in one launch; loss_hist rows follow the plan order."""
-    check(lib.mlp_train_batched(plan.host, _ptr(plan.dev), plan.n, n_in, n_out, _ptr(X), _ptr(T),
-                                X.shape[0], _ptr(theta), _ptr(comp), theta.numel(), int(epochs),
-                                _ptr(loss_hist), _stream(stream)))
+                  loss_hist: torch.Tensor | None = None, stream=None, groups=None):
+    """Train every net of the plan, one launch per group of the plan (one
+    launch without buckets); loss_hist rows follow the plan order.  `groups`
+    (indices) restricts the call to some groups.  Several groups run
+    concurrently on the plan's side streams (plan.side_streams, default
+    priority), forked from and joined back into the calling stream, so one
+    group's last workgroups overlap the next group's."""
+    cur = stream if stream is not None else torch.cuda.current_stream()
+    item_bytes = ctypes.sizeof(BatchItem)
+    todo = [g for g in range(len(plan.groups)) if groups is None or g in groups]
+    side = plan.side_streams if len(todo) > 1 else []
+    for s_ in side:
+        s_.wait_stream(cur)
+    for j, g in enumerate(todo):
+        start, count, _, _ = plan.groups[g]
+        threads = plan.threads[g]
+        st = side[j % len(side)] if side else cur
+        if threads:
+            set_launch_hint(small_threads=threads)
+        try:
+            lh = None if loss_hist is None else loss_hist.data_ptr() + start * int(epochs) * 4
+            check(lib.mlp_train_batched(plan.host_at(start), plan.dev.data_ptr() + start * item_bytes, count, n_in,
+                                        n_out, _ptr(X), _ptr(T), X.shape[0], _ptr(theta), _ptr(comp),
+                                        theta.numel(), int(epochs), lh, st.cuda_stream))
+        finally:
+            if threads:
+                reset_launch_hint()
+    for s_ in side:
+        cur.wait_stream(s_)
     return loss_hist
 
 
 class BatchedGraph:
     """mlp_train_batched captured once in a HIP graph (torch.cuda.CUDAGraph):
     every replay trains all nets of the plan for `epochs` more epochs, in
-    place, with one graph launch.  The captured work is the single trainer
-    kernel (no memset or copy nodes).  Buffers must stay alive and in place
+    place, with one graph launch.  The captured work is the trainer kernel
+    of each group of the plan (no memset or copy nodes).  Buffers must stay alive and in place
     for the graph's lifetime."""
 
     def __init__(self, plan: BatchPlan, X, T, theta, comp, epochs: int, n_in: int, n_out: int,

@@ -112,25 +112,30 @@ def _time(fn, reps: int = 2) -> float:
 
 
 def tune_batched(plan: "mlp.BatchPlan", X, T, theta, n_in: int, n_out: int, epochs: int = 20,
-                 force: bool = False) -> int:
-    """Pick threads per net for mlp_train_batched on this workload (theta is
-    not modified: candidates train copies)."""
-    key = small_key(n_in, plan.max_rows, plan.max_hidden, plan.n)
-    cached = _load_cache().get(key)
-    if cached and not force:
-        return int(cached["threads"])
-    times = {}
-    for t in SMALL_CHOICES:
-        mlp.set_launch_hint(small_threads=t)
-        th = theta.clone()
-        comp = torch.zeros_like(th)
-        try:
-            times[t] = _time(lambda: mlp.train_batched(plan, X, T, th, comp, epochs, n_in, n_out))
-        finally:
-            mlp.reset_launch_hint()
-    best = min(times, key=times.get)
-    _store(key, {"threads": best, "ms": times, "epochs": epochs, "when": time.time()})
-    return best
+                 force: bool = False) -> list:
+    """Pick threads per net for each group of the plan (mlp_train_batched
+    launches; theta is not modified: candidates train copies), store them in
+    plan.threads and return them."""
+    chosen = []
+    for g, (start, count, max_rows, max_hidden) in enumerate(plan.groups):
+        key = small_key(n_in, max_rows, max_hidden, count)
+        cached = _load_cache().get(key)
+        if cached and not force:
+            chosen.append(int(cached["threads"]))
+            continue
+        times = {}
+        saved = list(plan.threads)
+        for t in SMALL_CHOICES:
+            plan.threads[g] = t
+            th = theta.clone()
+            comp = torch.zeros_like(th)
+            times[t] = _time(lambda: mlp.train_batched(plan, X, T, th, comp, epochs, n_in, n_out, groups=[g]))
+        plan.threads[:] = saved
+        best = min(times, key=times.get)
+        _store(key, {"threads": best, "ms": times, "epochs": epochs, "when": time.time()})
+        chosen.append(best)
+    plan.threads[:] = chosen
+    return chosen
 
 
 def tune_large(n_in: int, n_hidden: int, n_out: int, batch: int, prec: str, X, T, theta,
@@ -170,6 +175,17 @@ def apply_small(n_in: int, max_rows: int, max_hidden: int, n_nets: int) -> bool:
         mlp.set_launch_hint(small_threads=int(c["threads"]))
         return True
     return False
+
+
+def apply_batched(plan: "mlp.BatchPlan", n_in: int) -> bool:
+    """Set plan.threads from the cache for every group that has an entry."""
+    hit = False
+    for g, (start, count, max_rows, max_hidden) in enumerate(plan.groups):
+        c = _load_cache().get(small_key(n_in, max_rows, max_hidden, count))
+        if c:
+            plan.threads[g] = int(c["threads"])
+            hit = True
+    return hit
 
 
 def apply_large(n_in: int, n_hidden: int, batch: int, prec: str) -> bool:

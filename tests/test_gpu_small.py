@@ -317,3 +317,87 @@ def test_batched_training_as_a_replayed_hip_graph(M, batched_full):
         torch.cuda.synchronize()
         assert junk.isfinite()
         assert torch.equal(th_g, th_e) and torch.equal(c_g, c_e) and torch.equal(h_g, h_e), rep
+
+
+def test_epochs_as_library_calls_and_their_graph(M):
+    """NetEpochs (per epoch mlp_forward, mlp_backward with the library's
+    mean-squared-error reading, mlp_step) against the oracle, and its HIP
+    graph: replays equal the same epochs run eagerly, bitwise, with eager
+    work between the replays."""
+    w = synth.single(2)
+    X, T = torch.from_numpy(w["X"]).cuda(), torch.from_numpy(w["T"]).cuda()
+    D, H, K, n = w["D"], w["H"], w["K"], w["X"].shape[0]
+    net = M.Net(D, H, K, n, lr=w["lr"], theta=w["theta"])
+    ep = M.NetEpochs(net, X, T)
+    hist = torch.empty(500, device="cuda")
+    ep.run(500, hist)
+    torch.cuda.synchronize()
+    q, ref_hist = oracle.train(w["X"], w["T"], Params.of(w["theta"]), w["lr"], 500)
+    check_params(net.flat.cpu().numpy(), q)
+    assert normwise(hist.cpu().numpy(), ref_hist) <= TOL
+    G = 50
+    a = M.Net(D, H, K, n, lr=w["lr"], theta=w["theta"])
+    b = M.Net(D, H, K, n, lr=w["lr"], theta=w["theta"])
+    ea, eb = M.NetEpochs(a, X, T), M.NetEpochs(b, X, T).graph(G)
+    assert np.array_equal(b.flat.cpu().numpy(), synth.Theta.packed(w["theta"]))   # capture left the net as it was
+    lbuf = torch.empty(G, device="cuda")
+    for rep in range(3):
+        ea.run(G, lbuf)
+        eb.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(a.flat, b.flat) and torch.equal(a.comp, b.comp), rep
+        assert torch.equal(eb.loss, lbuf), rep
+
+
+def test_size_grouped_batched_plan_every_net(M, batched_full):
+    """A plan grouped by size (one launch per group, each sized for its
+    largest net and tuned to its own threads per net) trains every net as
+    the oracle does, and its results do not depend on the run (bitwise)."""
+    from paper_1908_07847_amd import tune
+    w = batched_full
+    epochs = 25
+    plan = M.BatchPlan(w["items"], buckets=True)
+    assert len(plan.groups) > 1 and sum(c for _, c, _, _ in plan.groups) == len(w["items"])
+    X = torch.from_numpy(w["X"]).cuda()
+    T = torch.from_numpy(w["T"]).cuda()
+    th0 = torch.from_numpy(w["theta"]).cuda()
+    plan.threads[:] = [512, 256, 128, 512, 256, 128][:len(plan.groups)]
+    outs = []
+    for rep in range(2):
+        th = th0.clone()
+        hist = torch.empty((len(w["items"]), epochs), device="cuda")
+        M.train_batched(plan, X, T, th, torch.zeros_like(th), epochs, 33, 3, loss_hist=hist)
+        torch.cuda.synchronize()
+        outs.append((th.cpu().numpy(), hist.cpu().numpy()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    got, h = outs[0][0], np.empty_like(outs[0][1])
+    h[plan.order] = outs[0][1]
+    ref, ref_hist = oracle.train_many(w["items"], w["X"], w["T"], w["theta"], 33, 3, epochs, threads=0)
+    worst = 0.0
+    for i, it in enumerate(w["items"]):
+        s = _net_slice(w, it)
+        check_params(got[s], Params.of(synth.Theta.unpack(ref[s], 33, it["n_hidden"], 3)))
+        worst = max(worst, normwise(h[i], ref_hist[i]))
+    assert worst <= TOL
+
+
+def test_size_grouped_plan_replays_from_a_graph(M, batched_full):
+    """The groups of a size-grouped plan, launched concurrently on side
+    streams, captured in one HIP graph: each replay equals the same epochs
+    run eagerly (bitwise), with eager work between the replays."""
+    w = batched_full
+    items = w["items"][:600]
+    plan = M.BatchPlan(items, buckets=True)
+    X = torch.from_numpy(w["X"]).cuda()
+    T = torch.from_numpy(w["T"]).cuda()
+    th0 = torch.from_numpy(w["theta"]).cuda()
+    a, ca = th0.clone(), torch.zeros_like(th0)
+    b, cb = th0.clone(), torch.zeros_like(th0)
+    hb = torch.empty((len(items), 10), device="cuda")
+    graph = M.BatchedGraph(plan, X, T, b, cb, 10, 33, 3, loss_hist=hb)
+    ha = torch.empty_like(hb)
+    for rep in range(3):
+        M.train_batched(plan, X, T, a, ca, 10, 33, 3, loss_hist=ha)
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(a, b) and torch.equal(ca, cb) and torch.equal(ha, hb), rep
