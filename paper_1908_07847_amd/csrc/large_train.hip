@@ -439,8 +439,10 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
     int rows_;
     block_rows(st, 0, rb0_, rows_);
     const float *src = a.X + rb0_ * D;
+    int tid_o = tid;
+    asm volatile("" : "+v"(tid_o));   // addresses formed here, per step, not hoisted out of the loop
 #pragma unroll
-    for (int k = 0; k < kUnitsPre; ++k) load_unit(src, rows_, k * kLT + tid, v + 8 * k);
+    for (int k = 0; k < kUnitsPre; ++k) load_unit(src, rows_, k * kLT + tid_o, v + 8 * k);
   };
   // stage piece pc of step st; with v (piece 0 only) its first
   // kUnitsPre * kLT units come from the registers
@@ -954,6 +956,12 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
     {
       float *gpi = a.gp + (int64_t)gi * PT + (int64_t)net * P;
       const float gscale = PREC == 2 ? isd * isx : 1.0f;
+      // lane coordinates made opaque to the compiler here, so the store
+      // addresses below are formed per step next to their stores instead of
+      // being hoisted out of the step loop (where they would sit in
+      // registers, or in scratch, for the whole run)
+      int lg_o = lg, l16_o = l16;
+      asm volatile("" : "+v"(lg_o), "+v"(l16_o));
 #pragma unroll
       for (int hb = 0; hb < NHM; ++hb) {
         if (hb < NHB) {
@@ -962,7 +970,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
             if (fb < NFB) {
 #pragma unroll
               for (int i = 0; i < 4; ++i) {
-                const int h = gj * HB + tile_unit(hb) + 4 * lg + i, d = fb * 16 + l16;
+                const int h = gj * HB + (hb * kNW + wave) * 16 + 4 * lg_o + i, d = fb * 16 + l16_o;
                 if (h < H && d < D) gpi[h * D + d] = gacc[hb][fb][i] * gscale;
               }
             }
@@ -978,8 +986,8 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
             t += __shfl_xor(t, 32, kWave);
             w[k] = t;
           }
-          const int h = gj * HB + tile_unit(hb) + l16;
-          if (lg == 0 && h < H) {
+          const int h = gj * HB + (hb * kNW + wave) * 16 + l16_o;
+          if (lg_o == 0 && h < H) {
             gpi[oB1 + h] = v;
 #pragma unroll
             for (int k = 0; k < KO; ++k)
@@ -1017,7 +1025,9 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
       // loads of a batch are all issued before the first add
       // (32-bit offsets from the workspace's uniform base: Gi PT < 2^30)
       auto psum = [&](int64_t p, int g0, int g1) {
-        const uint32_t pq = (uint32_t)p, ptq = (uint32_t)PT;
+        uint32_t pq = (uint32_t)p;
+        asm volatile("" : "+v"(pq));   // formed per step (see the gradient stores)
+        const uint32_t ptq = (uint32_t)PT;
         float sum = 0.0f;
         for (int gb = g0; gb < g1; gb += kRedU) {
           float v[kRedU];
