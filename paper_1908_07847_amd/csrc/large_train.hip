@@ -185,7 +185,7 @@ __device__ __forceinline__ uint8_t e4m3_byte(float v) {
 }
 
 constexpr int kStageU = 16;  // loads in flight per thread while staging
-constexpr int kPre = 16;     // X elements per thread prefetched a step ahead
+constexpr int kPre = 32;     // X elements per thread prefetched a step ahead
 constexpr int kRedU = 32;    // partial-gradient loads in flight per thread
 constexpr int kUpdU = 4;     // parameters per thread per batch when there are at most 4 partials
 
@@ -738,6 +738,104 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
       }
     };
 
+    // The same partial output pre-activations with the work split by rows:
+    // one wave takes a 16-row set of the piece and runs z1 for every hidden
+    // tile of the block (four tiles at a time), sigma and the output-layer
+    // sums, reduced over the tile rows' 16 lanes and across tiles in
+    // registers -- no exchange between waves and no workgroup barrier, so the
+    // two waves of a SIMD drift apart and one's matrix-core work overlaps the
+    // other's sigma.  Used when the piece has a row set for every wave.
+    // out(rr, k, v) receives row rr's (within the piece) sum for output k.
+    auto z2_rowset = [&](int r0, auto &&out) {
+      float zp[4][KO];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int k = 0; k < KO; ++k) zp[i][k] = 0.0f;
+      float xa32[16];
+      bf16x8 xa16[2];
+      long xa8[2];
+      if (PREC == 0) {
+#pragma unroll
+        for (int st = 0; st < 16; ++st)
+          xa32[st] = (4 * st < DK) ? reinterpret_cast<const float *>(xr)[(r0 + l16) * XROW + lg + 4 * st] : 0.0f;
+      } else if (PREC == 1) {
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+          xa16[ks] = (32 * ks < DK) ? *reinterpret_cast<const bf16x8 *>(reinterpret_cast<const __bf16 *>(xr) +
+                                                                        (r0 + l16) * XROW + 8 * lg + 32 * ks)
+                                    : bf16x8{};
+      } else {
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+          xa8[ks] = (32 * ks < DK) ? *reinterpret_cast<const long *>(reinterpret_cast<const uint8_t *>(xr) +
+                                                                     (r0 + l16) * XROW + 8 * lg + 32 * ks)
+                                   : 0l;
+      }
+      for (int t0 = 0; t0 < NT; t0 += 4) {
+        f32x4 z[4];
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) {
+          z[tt] = f32x4{0.f, 0.f, 0.f, 0.f};
+          const int t = t0 + tt;
+          if (t < NT) {
+            if (PREC == 0) {
+              const float *wb = reinterpret_cast<const float *>(w1s) + (16 * t + l16) * XROW + lg;
+#pragma unroll
+              for (int st = 0; st < 16; ++st)
+                if (4 * st < DK) z[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa32[st], wb[4 * st], z[tt], 0, 0, 0);
+            } else if (PREC == 1) {
+#pragma unroll
+              for (int ks = 0; ks < 2; ++ks)
+                if (32 * ks < DK) {
+                  const bf16x8 wv = *reinterpret_cast<const bf16x8 *>(reinterpret_cast<const __bf16 *>(w1s) +
+                                                                      (16 * t + l16) * XROW + 8 * lg + 32 * ks);
+                  z[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa16[ks], wv, z[tt], 0, 0, 0);
+                }
+            } else {
+#pragma unroll
+              for (int ks = 0; ks < 2; ++ks)
+                if (32 * ks < DK) {
+                  const long wv = *reinterpret_cast<const long *>(reinterpret_cast<const uint8_t *>(w1s) +
+                                                                  (16 * t + l16) * XROW + 8 * lg + 32 * ks);
+                  z[tt] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(xa8[ks], wv, z[tt], 0, 0, 0);
+                }
+              z[tt] = z[tt] * (isx * isw);
+            }
+          }
+        }
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) {
+          const int t = t0 + tt;
+          if (t < NT) {
+            const int hl = 16 * t + l16;
+            const float bias = b1s[hl];
+            float w2v[KO];
+#pragma unroll
+            for (int k = 0; k < KO; ++k) w2v[k] = w2s[k * HB + hl];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const float av = sigmoid(z[tt][i] + bias);
+#pragma unroll
+              for (int k = 0; k < KO; ++k) zp[i][k] = fmaf(av, w2v[k], zp[i][k]);
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int k = 0; k < KO; ++k) zp[i][k] = sum16(zp[i][k]);
+      if (l16 == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int k = 0; k < KO; ++k) out(r0 + 4 * lg + i, k, zp[i][k]);
+      }
+    };
+    // row sets of the piece for every wave: split the work by rows
+    const bool by_rows = RBP / 16 >= kNW;
+
     const bool split = a.Gj > 1;
     if (split) {
       // the Gj partials of a row meet in the workspace
@@ -745,8 +843,13 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
         stage_piece(pc);
         const int64_t rowbase = (int64_t)gc * a.b + (int64_t)gi * RB + (int64_t)pc * RBP;
         float *zrow = a.z2p + rowbase * 4;   // this piece's rows (uniform base, 32-bit offsets)
-        for (int c0 = 0; c0 < RBP; c0 += kRC)
-          z2_chunk(c0, [&](int rr, int k, float v) { zrow[(c0 + rr) * 4 + k] = v; });
+        if (by_rows) {
+          for (int r0 = 16 * wave; r0 < RBP; r0 += 16 * kNW)
+            z2_rowset(r0, [&](int rr, int k, float v) { zrow[rr * 4 + k] = v; });
+        } else {
+          for (int c0 = 0; c0 < RBP; c0 += kRC)
+            z2_chunk(c0, [&](int rr, int k, float v) { zrow[(c0 + rr) * 4 + k] = v; });
+        }
       }
       if (!barrier()) { ok = false; break; }
     }
@@ -778,8 +881,13 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
       const int prows = max(0, min(RBP, rows_here - prow0));     // real rows of the piece
       if (!split) {
         // Gj == 1: z2 partials are complete inside this workgroup
-        for (int c0 = 0; c0 < RBP; c0 += kRC)
-          z2_chunk(c0, [&](int rr, int k, float v) { d2s[(c0 + rr) * 4 + k] = v; });
+        if (by_rows) {
+          for (int r0 = 16 * wave; r0 < RBP; r0 += 16 * kNW)
+            z2_rowset(r0, [&](int rr, int k, float v) { d2s[rr * 4 + k] = v; });
+        } else {
+          for (int c0 = 0; c0 < RBP; c0 += kRC)
+            z2_chunk(c0, [&](int rr, int k, float v) { d2s[(c0 + rr) * 4 + k] = v; });
+        }
         __syncthreads();   // d2s entries are read below by other threads
       }
       {
