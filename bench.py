@@ -343,7 +343,9 @@ def bench_large(args):
                             kernel_ms_per_launch=r["kernel_s"] * 1e3,
                             median_ms_per_launch=float(np.median(r["durs"])) * 1e3,
                             min_ms_per_launch=float(min(r["durs"])) * 1e3,
-                            kernel=f"mlpk::k_large_train<{pi}, {3 if K <= 3 else 4}>",
+                            # the automatic plans of these workloads run 8 waves per workgroup
+                            # (hidden blocks of 128 or 256 units)
+                            kernel=f"mlpk::k_large_train<{pi}, {3 if K <= 3 else 4}, 8>",
                             achieved_tflops=ach, peak_tflops=PEAK[q], frac=ach / PEAK[q],
                             final_loss=r["final_loss"], dtype={"fp32": "f32", "bf16": "bf16", "e4m3": "e4m3"}[q])
     head = res_forms[prec]
@@ -555,7 +557,7 @@ def bench_shared(args):
                 "compensated_update": True, "operand_precision": prec, "step": "one epoch of every net"},
         roofline={"bound": "mfma", "achieved": achieved, "peak": PEAK[prec], "unit": "TFLOP/s",
                   "frac": achieved / PEAK[prec], "traffic": measured_traffic(f"w6-{prec}-steps{steps}", "large"),
-                  "traffic_unit": "bytes per launch", "kernel": f"mlpk::k_large_train<{pi}, 3>",
+                  "traffic_unit": "bytes per launch", "kernel": f"mlpk::k_large_train<{pi}, 3, 8>",
                   "kernel_ms": kern * 1e3, "flops_per_launch": flops},
         final_loss_mean=final_loss_mean, repeats={"runs": 1, "median_ms_per_step": wall * 1e3 / steps,
                                                   "min_ms_per_step": wall * 1e3 / steps},
@@ -816,7 +818,25 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-buckets", action="store_true", help="w3: one launch for all nets (no size groups)")
     ap.add_argument("--copy-probe", action="store_true", help="only run a 1 GiB device copy (counter scale)")
+    ap.add_argument("--record-counters", nargs=6, metavar=("KEY", "KIND", "FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
+                                                           "COPY_WRITE_CSV"),
+                    help="host only: store the HBM bytes of one launch (one epoch) of the large-N trainer from "
+                         "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE files in profiles/counters.json under KEY, with "
+                         "the current source hash of kernel KIND")
     args = ap.parse_args()
+    if args.record_counters:
+        key, kind, f, w, cf, cw = args.record_counters
+        rec = counters_record(f, w, cf, cw, "void mlpk::k_large_train" if kind == "large" else "void mlpk::")
+        path = os.path.join(ROOT, "profiles", "counters.json")
+        with open(path) as fh:
+            allrec = json.load(fh)
+        allrec[key] = {"source": kernel_source_hash(kind), "hbm_bytes_per_epoch": rec["hbm_bytes"],
+                       "fetch_kib": rec["fetch_kib"], "write_kib": rec["write_kib"],
+                       "fetch_scale": rec["fetch_scale"], "write_scale": rec["write_scale"]}
+        with open(path, "w") as fh:
+            json.dump(allrec, fh, indent=1, sort_keys=True)
+        print(json.dumps({key: allrec[key]}))
+        return
     if args.copy_probe:
         copy_probe()
         return

@@ -411,7 +411,8 @@ mlp_status mlp_mfma_probe(int32_t prec, const float *A, const float *B, float *C
  *   large_row_blocks,    the Gi x Gj grid of the large-N trainer (row blocks
  *   large_hidden_blocks  of >= 32 rows, hidden blocks of <= 256 units);
  *   large_waves          waves per workgroup of the large-N trainer, 4 or 8
- *                        (0: 8 for hidden blocks of 256 units, else 4). */
+ *                        (0: 8 for hidden blocks of at least 128 units,
+ *                        else 4). */
 typedef struct {
   int32_t small_threads;
   int32_t large_row_blocks;

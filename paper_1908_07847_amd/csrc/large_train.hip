@@ -1423,14 +1423,14 @@ static bool plan_for(const mlp_config &c, int M, int n_cu, Plan *pl, std::string
   if (Hp / Gj > 256) { *why = "hidden block above 256 units"; return false; }
   if (Gi > max_row_blocks(M, Gj) || Gj > kMaxHiddenBlocks) { *why = "grid above the workspace plan"; return false; }
   if (b % Gi != 0 || (b / Gi) % 32 != 0) { *why = "rows per block must be a multiple of 32"; return false; }
-  // one workgroup per CU: 8 waves (two tiles each) for 256-unit hidden
-  // blocks, else 4
+  // one workgroup per CU: 8 waves (two per SIMD) when the hidden block has
+  // a tile for each, else 4
   const int G = Gi * M * Gj;
   if (G > n_cu) { *why = "grid above one workgroup per CU"; return false; }
   pl->Gi = Gi;
   pl->Gj = Gj;
   pl->Hp = Hp;
-  pl->nw = g_waves ? g_waves : (Hp / Gj >= 256 ? 8 : 4);
+  pl->nw = g_waves ? g_waves : (Hp / Gj >= 128 ? 8 : 4);
   pl->RBP = piece_rows(c.prec, Hp / Gj, (int)(b / Gi), kLdsLimit);
   if (pl->RBP == 0) { *why = "no row piece of the block fits the LDS"; return false; }
   pl->lds = lds_for(c.prec, Hp / Gj, pl->RBP);
