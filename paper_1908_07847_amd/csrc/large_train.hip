@@ -947,9 +947,18 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
       // are summed in the order the z1 accumulator holds them (lane group lg
       // has rows 4 lg + i and 16 + 4 lg + i of the chunk), and the X operand
       // is read for the same rows.
+      // z1 of the next chunk is issued on the matrix cores before this
+      // chunk's vector work (sigma', delta1), which does not depend on it
+      f32x4 ztn[NHM][2];
+      z1_tiles(0, ztn);
       for (int c0 = 0; c0 < RBP; c0 += kRC) {
       f32x4 zt[NHM][2];
-      z1_tiles(c0, zt);
+#pragma unroll
+      for (int hb = 0; hb < NHM; ++hb) {
+        zt[hb][0] = ztn[hb][0];
+        zt[hb][1] = ztn[hb][1];
+      }
+      if (c0 + kRC < RBP) z1_tiles(c0 + kRC, ztn);
       // X operands of this chunk's gW1 contraction, shared by the wave's tiles:
       // float32 [rs][i][fb] = X[c0 + 16 rs + 4 lg + i][16 fb + l16]; bf16 /
       // e4m3 [fb] = X[rows c0 + 4 lg .. +3, then c0 + 16 + 4 lg .. +3][16 fb + l16]
