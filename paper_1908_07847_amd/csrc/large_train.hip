@@ -281,7 +281,9 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
   using E = typename O::elem;
   constexpr int XROW = O::XROW;
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // the wave index is uniform over the wave: held in a scalar register, so
+  // everything derived from it (tiles, row sets, partial ranges) is too
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   // Column blocks: M nets x Gj hidden blocks each (M > 1: nets that share X).
   const int Gc = a.M * a.Gj, G = a.Gi * Gc;
   // XCD-aware placement: workgroups are dispatched round-robin over the 8
@@ -582,7 +584,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
       for (int hb = 0; hb < NHM; ++hb)
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
-          const bool on = hb < NHB && 32 * ks < DK;
+          const bool on = hb < NHB;
           const int o = on ? (tile_unit(hb) + l16) * XROW + 8 * lg + 32 * ks : 0;
           if (PREC == 1) {
             const bf16x8 v = *reinterpret_cast<const bf16x8 *>(reinterpret_cast<const __bf16 *>(w1s) + o);
@@ -594,6 +596,12 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
           }
         }
     }
+    // LDS rows of X and W1 hold kMaxD = 64 columns, those past D zero, so
+    // every operand load below reads a valid address and the padding adds
+    // exact zeros: the loads need no guard, and the float32 contraction runs
+    // in groups of 4 k-steps (16 features), whole groups up to DK.  A tile's
+    // operands are loaded together, ahead of its products (one LDS round trip
+    // per tile, not one per k-step).
     auto z1_tiles = [&](int c0, f32x4 (&zt)[NHM][2]) {
       if (PREC == 0) {
         float xa[2][16];
@@ -601,20 +609,23 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
         for (int rs = 0; rs < 2; ++rs)
 #pragma unroll
           for (int st = 0; st < 16; ++st)
-            xa[rs][st] = (4 * st < DK)
-                             ? reinterpret_cast<const float *>(xr)[(c0 + rs * 16 + l16) * XROW + lg + 4 * st]
-                             : 0.0f;
+            xa[rs][st] = reinterpret_cast<const float *>(xr)[(c0 + rs * 16 + l16) * XROW + lg + 4 * st];
 #pragma unroll
         for (int hb = 0; hb < NHM; ++hb) {
           f32x4 z0 = {0.f, 0.f, 0.f, 0.f}, z1v = {0.f, 0.f, 0.f, 0.f};
           if (hb < NHB) {
             const float *wb = reinterpret_cast<const float *>(w1s) + (tile_unit(hb) + l16) * XROW + lg;
+            float wv[16];
 #pragma unroll
-            for (int st = 0; st < 16; ++st) {
-              if (4 * st < DK) {
-                const float wv = wb[4 * st];
-                z0 = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[0][st], wv, z0, 0, 0, 0);
-                z1v = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[1][st], wv, z1v, 0, 0, 0);
+            for (int st = 0; st < 16; ++st) wv[st] = wb[4 * st];
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+              if (16 * g < DK) {
+#pragma unroll
+                for (int s = 4 * g; s < 4 * g + 4; ++s) {
+                  z0 = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[0][s], wv[s], z0, 0, 0, 0);
+                  z1v = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[1][s], wv[s], z1v, 0, 0, 0);
+                }
               }
             }
           }
@@ -627,19 +638,16 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
         for (int rs = 0; rs < 2; ++rs)
 #pragma unroll
           for (int ks = 0; ks < 2; ++ks)
-            if (32 * ks < DK)
-              xa[rs][ks] = *reinterpret_cast<const bf16x8 *>(
-                  reinterpret_cast<const __bf16 *>(xr) + (c0 + rs * 16 + l16) * XROW + 8 * lg + 32 * ks);
+            xa[rs][ks] = *reinterpret_cast<const bf16x8 *>(
+                reinterpret_cast<const __bf16 *>(xr) + (c0 + rs * 16 + l16) * XROW + 8 * lg + 32 * ks);
 #pragma unroll
         for (int hb = 0; hb < NHM; ++hb) {
           f32x4 z0 = {0.f, 0.f, 0.f, 0.f}, z1v = {0.f, 0.f, 0.f, 0.f};
           if (hb < NHB) {
 #pragma unroll
             for (int ks = 0; ks < 2; ++ks) {
-              if (32 * ks < DK) {
-                z0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[0][ks], w1b[hb][ks], z0, 0, 0, 0);
-                z1v = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[1][ks], w1b[hb][ks], z1v, 0, 0, 0);
-              }
+              z0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[0][ks], w1b[hb][ks], z0, 0, 0, 0);
+              z1v = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[1][ks], w1b[hb][ks], z1v, 0, 0, 0);
             }
           }
           zt[hb][0] = z0;
@@ -651,19 +659,16 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
         for (int rs = 0; rs < 2; ++rs)
 #pragma unroll
           for (int ks = 0; ks < 2; ++ks)
-            if (32 * ks < DK)
-              xa[rs][ks] = *reinterpret_cast<const long *>(
-                  reinterpret_cast<const uint8_t *>(xr) + (c0 + rs * 16 + l16) * XROW + 8 * lg + 32 * ks);
+            xa[rs][ks] = *reinterpret_cast<const long *>(
+                reinterpret_cast<const uint8_t *>(xr) + (c0 + rs * 16 + l16) * XROW + 8 * lg + 32 * ks);
 #pragma unroll
         for (int hb = 0; hb < NHM; ++hb) {
           f32x4 z0 = {0.f, 0.f, 0.f, 0.f}, z1v = {0.f, 0.f, 0.f, 0.f};
           if (hb < NHB) {
 #pragma unroll
             for (int ks = 0; ks < 2; ++ks) {
-              if (32 * ks < DK) {
-                z0 = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(xa[0][ks], w1e[hb][ks], z0, 0, 0, 0);
-                z1v = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(xa[1][ks], w1e[hb][ks], z1v, 0, 0, 0);
-              }
+              z0 = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(xa[0][ks], w1e[hb][ks], z0, 0, 0, 0);
+              z1v = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(xa[1][ks], w1e[hb][ks], z1v, 0, 0, 0);
             }
           }
           zt[hb][0] = z0 * (isx * isw);
@@ -757,67 +762,93 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
       long xa8[2];
       if (PREC == 0) {
 #pragma unroll
-        for (int st = 0; st < 16; ++st)
-          xa32[st] = (4 * st < DK) ? reinterpret_cast<const float *>(xr)[(r0 + l16) * XROW + lg + 4 * st] : 0.0f;
+        for (int st = 0; st < 16; ++st) xa32[st] = reinterpret_cast<const float *>(xr)[(r0 + l16) * XROW + lg + 4 * st];
       } else if (PREC == 1) {
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks)
-          xa16[ks] = (32 * ks < DK) ? *reinterpret_cast<const bf16x8 *>(reinterpret_cast<const __bf16 *>(xr) +
-                                                                        (r0 + l16) * XROW + 8 * lg + 32 * ks)
-                                    : bf16x8{};
+          xa16[ks] = *reinterpret_cast<const bf16x8 *>(reinterpret_cast<const __bf16 *>(xr) + (r0 + l16) * XROW +
+                                                       8 * lg + 32 * ks);
       } else {
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks)
-          xa8[ks] = (32 * ks < DK) ? *reinterpret_cast<const long *>(reinterpret_cast<const uint8_t *>(xr) +
-                                                                     (r0 + l16) * XROW + 8 * lg + 32 * ks)
-                                   : 0l;
+          xa8[ks] = *reinterpret_cast<const long *>(reinterpret_cast<const uint8_t *>(xr) + (r0 + l16) * XROW +
+                                                    8 * lg + 32 * ks);
       }
-      for (int t0 = 0; t0 < NT; t0 += 4) {
-        f32x4 z[4];
+      // Tiles go in groups of 4; a group's tile index is clamped to the block
+      // (the products of a clamped tile are computed and dropped).  bf16 /
+      // e4m3: the W1 operands of the next group are loaded while this group's
+      // sigma runs; float32 (16 operands per tile): the group's 64 operands
+      // are loaded together ahead of its products.
+      bf16x8 wvb[4][2];
+      long wve[4][2];
+      auto load_group = [&](int t0) {
 #pragma unroll
         for (int tt = 0; tt < 4; ++tt) {
-          z[tt] = f32x4{0.f, 0.f, 0.f, 0.f};
-          const int t = t0 + tt;
-          if (t < NT) {
-            if (PREC == 0) {
-              const float *wb = reinterpret_cast<const float *>(w1s) + (16 * t + l16) * XROW + lg;
+          const int t = min(t0 + tt, NT - 1);
 #pragma unroll
-              for (int st = 0; st < 16; ++st)
-                if (4 * st < DK) z[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa32[st], wb[4 * st], z[tt], 0, 0, 0);
-            } else if (PREC == 1) {
+          for (int ks = 0; ks < 2; ++ks) {
+            const int o = (16 * t + l16) * XROW + 8 * lg + 32 * ks;
+            if (PREC == 1) wvb[tt][ks] = *reinterpret_cast<const bf16x8 *>(reinterpret_cast<const __bf16 *>(w1s) + o);
+            if (PREC == 2) wve[tt][ks] = *reinterpret_cast<const long *>(reinterpret_cast<const uint8_t *>(w1s) + o);
+          }
+        }
+      };
+      if (PREC != 0) load_group(0);
+      for (int t0 = 0; t0 < NT; t0 += 4) {
+        float bias[4], w2v[4][KO];
 #pragma unroll
-              for (int ks = 0; ks < 2; ++ks)
-                if (32 * ks < DK) {
-                  const bf16x8 wv = *reinterpret_cast<const bf16x8 *>(reinterpret_cast<const __bf16 *>(w1s) +
-                                                                      (16 * t + l16) * XROW + 8 * lg + 32 * ks);
-                  z[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa16[ks], wv, z[tt], 0, 0, 0);
-                }
-            } else {
+        for (int tt = 0; tt < 4; ++tt) {
+          const int hl = 16 * min(t0 + tt, NT - 1) + l16;
+          bias[tt] = b1s[hl];
 #pragma unroll
-              for (int ks = 0; ks < 2; ++ks)
-                if (32 * ks < DK) {
-                  const long wv = *reinterpret_cast<const long *>(reinterpret_cast<const uint8_t *>(w1s) +
-                                                                  (16 * t + l16) * XROW + 8 * lg + 32 * ks);
-                  z[tt] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(xa8[ks], wv, z[tt], 0, 0, 0);
-                }
-              z[tt] = z[tt] * (isx * isw);
+          for (int k = 0; k < KO; ++k) w2v[tt][k] = w2s[k * HB + hl];
+        }
+        f32x4 z[4];
+        if (PREC == 0) {
+          float wv[4][16];
+#pragma unroll
+          for (int tt = 0; tt < 4; ++tt) {
+            const float *wb = reinterpret_cast<const float *>(w1s) + (16 * min(t0 + tt, NT - 1) + l16) * XROW + lg;
+#pragma unroll
+            for (int st = 0; st < 16; ++st) wv[tt][st] = wb[4 * st];
+          }
+#pragma unroll
+          for (int tt = 0; tt < 4; ++tt) z[tt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int g = 0; g < 4; ++g) {
+            if (16 * g < DK) {
+#pragma unroll
+              for (int st = 4 * g; st < 4 * g + 4; ++st)
+#pragma unroll
+                for (int tt = 0; tt < 4; ++tt)
+                  z[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa32[st], wv[tt][st], z[tt], 0, 0, 0);
             }
+          }
+        } else {
+#pragma unroll
+          for (int tt = 0; tt < 4; ++tt) {
+            if (PREC == 1) {
+              z[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa16[0], wvb[tt][0], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+              z[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa16[1], wvb[tt][1], z[tt], 0, 0, 0);
+            } else {
+              z[tt] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(xa8[0], wve[tt][0], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+              z[tt] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(xa8[1], wve[tt][1], z[tt], 0, 0, 0);
+            }
+          }
+          if (t0 + 4 < NT) load_group(t0 + 4);
+          if (PREC == 2) {
+#pragma unroll
+            for (int tt = 0; tt < 4; ++tt) z[tt] = z[tt] * (isx * isw);
           }
         }
 #pragma unroll
         for (int tt = 0; tt < 4; ++tt) {
-          const int t = t0 + tt;
-          if (t < NT) {
-            const int hl = 16 * t + l16;
-            const float bias = b1s[hl];
-            float w2v[KO];
-#pragma unroll
-            for (int k = 0; k < KO; ++k) w2v[k] = w2s[k * HB + hl];
+          if (t0 + tt < NT) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-              const float av = sigmoid(z[tt][i] + bias);
+              const float av = sigmoid(z[tt][i] + bias[tt]);
 #pragma unroll
-              for (int k = 0; k < KO; ++k) zp[i][k] = fmaf(av, w2v[k], zp[i][k]);
+              for (int k = 0; k < KO; ++k) zp[i][k] = fmaf(av, w2v[tt][k], zp[i][k]);
             }
           }
         }
@@ -1139,21 +1170,28 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
         if (p < oB1) wmax = fmaxf(wmax, fabsf(w));
       };
       // sum of partials g in [g0, g1) of parameter p, in increasing g; the
-      // loads of a batch are all issued before the first add
-      // (32-bit offsets from the workspace's uniform base: Gi PT < 2^30)
+      // loads of a batch are all issued before the first add.  g0 and g1 are
+      // uniform over the wave, so the batches need no lane masks; each load
+      // is a uniform partial-row base plus the lane's 32-bit byte offset
+      // (Gi PT < 2^30 floats).
       auto psum = [&](int64_t p, int g0, int g1) {
-        uint32_t pq = (uint32_t)p;
+        g0 = __builtin_amdgcn_readfirstlane(g0);
+        g1 = __builtin_amdgcn_readfirstlane(g1);
+        uint32_t pq = (uint32_t)p * 4u;
         asm volatile("" : "+v"(pq));   // formed per step (see the gradient stores)
-        const uint32_t ptq = (uint32_t)PT;
+        const char *gpb = reinterpret_cast<const char *>(a.gp);
+        const uint64_t rowb = (uint64_t)PT * 4u;
         float sum = 0.0f;
-        for (int gb = g0; gb < g1; gb += kRedU) {
+        int gb = g0;
+        for (; gb + kRedU <= g1; gb += kRedU) {
+          const char *base = gpb + (uint64_t)gb * rowb;
           float v[kRedU];
 #pragma unroll
-          for (int u = 0; u < kRedU; ++u) v[u] = (gb + u < g1) ? a.gp[pq + (uint32_t)(gb + u) * ptq] : 0.0f;
+          for (int u = 0; u < kRedU; ++u) v[u] = *reinterpret_cast<const float *>(base + u * rowb + pq);
 #pragma unroll
-          for (int u = 0; u < kRedU; ++u)
-            if (gb + u < g1) sum += v[u];
+          for (int u = 0; u < kRedU; ++u) sum += v[u];
         }
+        for (; gb < g1; ++gb) sum += *reinterpret_cast<const float *>(gpb + (uint64_t)gb * rowb + pq);
         return sum;
       };
       if (np <= 64 && a.Gi >= kNW) {
