@@ -1003,24 +1003,22 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
           for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int fb = 0; fb < 4; ++fb)
-              xg[rs][i][fb] = fb < NFB ? reinterpret_cast<const float *>(xr)[(c0 + 16 * rs + 4 * lg + i) * XROW +
-                                                                            16 * fb + l16]
-                                       : 0.0f;
+              xg[rs][i][fb] = reinterpret_cast<const float *>(xr)[(c0 + 16 * rs + 4 * lg + i) * XROW + 16 * fb + l16];
       } else if (PREC == 1) {
 #pragma unroll
         for (int fb = 0; fb < 4; ++fb) {
           const __bf16 *p = reinterpret_cast<const __bf16 *>(xt) + (16 * fb + l16) * XTS + c0 + 4 * lg;
           typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-          const bf16x4 lo = fb < NFB ? *reinterpret_cast<const bf16x4 *>(p) : bf16x4{};
-          const bf16x4 hi = fb < NFB ? *reinterpret_cast<const bf16x4 *>(p + 16) : bf16x4{};
+          const bf16x4 lo = *reinterpret_cast<const bf16x4 *>(p);
+          const bf16x4 hi = *reinterpret_cast<const bf16x4 *>(p + 16);
           xgb[fb] = bf16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
         }
       } else {
 #pragma unroll
         for (int fb = 0; fb < 4; ++fb) {
           const uint8_t *p = reinterpret_cast<const uint8_t *>(xt) + (16 * fb + l16) * XTS + c0 + 4 * lg;
-          const uint32_t lo = fb < NFB ? *reinterpret_cast<const uint32_t *>(p) : 0u;
-          const uint32_t hi = fb < NFB ? *reinterpret_cast<const uint32_t *>(p + 16) : 0u;
+          const uint32_t lo = *reinterpret_cast<const uint32_t *>(p);
+          const uint32_t hi = *reinterpret_cast<const uint32_t *>(p + 16);
           xge[fb] = (long)((uint64_t)lo | ((uint64_t)hi << 32));
         }
       }
@@ -1053,23 +1051,20 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
               gb1[hb] += d1;
               d1v[rs][i] = d1;
               if (PREC == 2) d1max = fmaxf(d1max, fabsf(d1));
-            }
-          }
-          // gW1[tile][feature blocks] += delta1^T X over the chunk's rows
-          if (PREC == 0) {
+              // float32: gW1[tile][feature blocks] += delta1^T X, one k-step
+              // per row as soon as its delta1 is formed, so the products of
+              // one row run on the matrix cores under the next row's vector
+              // work (the feature blocks are independent accumulators; blocks
+              // past D multiply the zero LDS padding and are never stored)
+              if (PREC == 0) {
 #pragma unroll
-            for (int fb = 0; fb < 4; ++fb) {
-              if (fb < NFB) {
-                f32x4 g = gacc[hb][fb];
-#pragma unroll
-                for (int rs = 0; rs < 2; ++rs)
-#pragma unroll
-                  for (int i = 0; i < 4; ++i)
-                    g = __builtin_amdgcn_mfma_f32_16x16x4f32(d1v[rs][i], xg[rs][i][fb], g, 0, 0, 0);
-                gacc[hb][fb] = g;
+                for (int fb = 0; fb < 4; ++fb)
+                  gacc[hb][fb] = __builtin_amdgcn_mfma_f32_16x16x4f32(d1, xg[rs][i][fb], gacc[hb][fb], 0, 0, 0);
               }
             }
-          } else if (PREC == 1) {
+          }
+          // bf16 / e4m3: gW1[tile][feature blocks] += delta1^T X over the chunk's rows
+          if (PREC == 1) {
             bf16x8 av;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -1078,14 +1073,14 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
             }
 #pragma unroll
             for (int fb = 0; fb < 4; ++fb)
-              if (fb < NFB) gacc[hb][fb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, xgb[fb], gacc[hb][fb], 0, 0, 0);
-          } else {
+              gacc[hb][fb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, xgb[fb], gacc[hb][fb], 0, 0, 0);
+          } else if (PREC == 2) {
             const long av =
                 (long)((uint64_t)pack_e4m3x4(d1v[0][0] * sd, d1v[0][1] * sd, d1v[0][2] * sd, d1v[0][3] * sd) |
                        ((uint64_t)pack_e4m3x4(d1v[1][0] * sd, d1v[1][1] * sd, d1v[1][2] * sd, d1v[1][3] * sd) << 32));
 #pragma unroll
             for (int fb = 0; fb < 4; ++fb)
-              if (fb < NFB) gacc[hb][fb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, xge[fb], gacc[hb][fb], 0, 0, 0);
+              gacc[hb][fb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, xge[fb], gacc[hb][fb], 0, 0, 0);
           }
         }
       }
