@@ -184,6 +184,35 @@ __device__ __forceinline__ uint8_t e4m3_byte(float v) {
   return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0, false) & 0xff);
 }
 
+// Hidden-layer sigmoid of the reduced-precision forms: the hardware base-2
+// exponential of t = -z log2(e), rounded once, and the hardware reciprocal.
+// The rounding of t scales e^-z by 2^(|t| 2^-24), so e^-z is good to about
+// |z| 7e-8 relative (1e-6 at |z| = 15) and sigma to that times (1 - sigma)
+// plus a few float ulps.  The contraction operands of these forms carry
+// 2^-9 (bf16) or 2^-4 (e4m3) relative rounding; the float32 form keeps the
+// compensated evaluation of sigmoid_e.  PREC selects the form by operand type.
+template <int PREC>
+__device__ __forceinline__ float hidden_sigmoid_e(float z, float &e_out) {
+  if (PREC == 0) return sigmoid_e(z, e_out);
+  const float t = fminf(-z * 1.44269502162933349609375f, 126.0f);
+  const float e = __builtin_amdgcn_exp2f(t);
+  e_out = e;
+  return __builtin_amdgcn_rcpf(1.0f + e);
+}
+template <int PREC>
+__device__ __forceinline__ float hidden_sigmoid(float z) {
+  float e;
+  return hidden_sigmoid_e<PREC>(z, e);
+}
+// sigma and its slope e^-z sigma^2 (see sigmoid_slope)
+template <int PREC>
+__device__ __forceinline__ float hidden_sigmoid_slope(float z, float &slope) {
+  float e;
+  const float a = hidden_sigmoid_e<PREC>(z, e);
+  slope = (e * a) * a;
+  return a;
+}
+
 constexpr int kStageU = 16;  // loads in flight per thread while staging
 constexpr int kPre = 32;     // X elements per thread prefetched a step ahead
 constexpr int kRedU = 32;    // partial-gradient loads in flight per thread
@@ -703,7 +732,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
           const f32x4 z = zt[hb][rs];
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            const float av = sigmoid(z[i] + bias);
+            const float av = hidden_sigmoid<PREC>(z[i] + bias);
 #pragma unroll
             for (int k = 0; k < KO; ++k) zp[rs][i][k] = fmaf(av, w2v[k], zp[rs][i][k]);
           }
@@ -846,7 +875,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
           if (t0 + tt < NT) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-              const float av = sigmoid(z[tt][i] + bias[tt]);
+              const float av = hidden_sigmoid<PREC>(z[tt][i] + bias[tt]);
 #pragma unroll
               for (int k = 0; k < KO; ++k) zp[i][k] = fmaf(av, w2v[tt][k], zp[i][k]);
             }
@@ -1038,7 +1067,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
             for (int i = 0; i < 4; ++i) {
               const int rr = rs * 16 + 4 * lg + i;          // row within the chunk
               float slope;
-              const float av = sigmoid_slope(z[i] + bias, slope);
+              const float av = hidden_sigmoid_slope<PREC>(z[i] + bias, slope);
               const float4 dv = *reinterpret_cast<const float4 *>(d2s + (c0 + rr) * 4);
               const float dd[4] = {dv.x, dv.y, dv.z, dv.w};
               float bp = 0.0f;
