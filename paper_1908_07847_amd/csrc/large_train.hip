@@ -214,7 +214,7 @@ __device__ __forceinline__ float hidden_sigmoid_slope(float z, float &slope) {
 }
 
 constexpr int kStageU = 16;  // loads in flight per thread while staging
-constexpr int kPre = 32;     // X elements per thread prefetched a step ahead
+constexpr int kPre = 32;     // X elements per thread loaded in one batch for a step's first piece
 constexpr int kRedU = 32;    // partial-gradient loads in flight per thread
 constexpr int kUpdU = 4;     // parameters per thread per batch when there are at most 4 partials
 
@@ -414,9 +414,9 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
 
   // ---- X staging.  A piece of a step's row block (RBP rows) is a
   // contiguous run of X (RBP x D floats); rows past the end of a short last
-  // minibatch are zero.  Piece 0 of the next step is loaded and stored
-  // during the update phase (its first kPre * kLT elements through registers
-  // loaded before the partial sums); other pieces are staged directly.
+  // minibatch are zero.  Piece 0 of a step is staged at the start of the
+  // step, its first kPre * kLT elements through registers all loaded before
+  // the first store; other pieces are staged in batches of kStageU.
   const int XTS = L.xts();
   const uint32_t mdD = ((1u << 22) + (uint32_t)D - 1) / (uint32_t)D;
   auto block_rows = [&](int st, int pc, int64_t &rb0_, int &rows_) {
@@ -585,8 +585,10 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
         else if (q < (1 + kMaxK) * HB) w2s[q - HB] = bw[u];
       }
     }
-    // ---- this step's row block of X (its first piece): staged during the
-    // previous step's update, except at the first step
+    // ---- this step's row block of X (its first piece): every load of the
+    // piece issued before the first store.  (Loading it during the previous
+    // step's update instead keeps kPre values per thread live across the
+    // partial sums, which the register allocation spills.)
     load_x(step, xpre);
     store_x(step, 0, &xpre);
     int cur_piece = 0;   // piece of the row block held in LDS
@@ -1178,9 +1180,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
     // Sum the Gi partials of this workgroup's slice of the parameters (of all
     // nets) in a fixed order and update the master copy.  Lanes run over
     // parameters (coalesced reads of each partial row); with few parameters
-    // per workgroup the four waves split the partials and meet in LDS.
-    // next step's X rows: loads in flight while the partials are summed,
-    // stored into LDS (free during the update) before the barrier
+    // per workgroup the waves split the partials and meet in LDS.
     {
       const int64_t per = (PT + G - 1) / G;
       const int64_t p0 = (int64_t)bid * per;
@@ -1215,7 +1215,17 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
 #pragma unroll
           for (int u = 0; u < kRedU; ++u) sum += v[u];
         }
-        for (; gb < g1; ++gb) sum += *reinterpret_cast<const float *>(gpb + (uint64_t)gb * rowb + pq);
+        if (gb < g1) {
+          // the last, partial batch: a partial past g1 (uniform test) reads
+          // partial g0 instead and adds zero, so every load is issued at once
+          const char *base = gpb + (uint64_t)gb * rowb, *safe = gpb + (uint64_t)g0 * rowb;
+          float v[kRedU];
+#pragma unroll
+          for (int u = 0; u < kRedU; ++u)
+            v[u] = *reinterpret_cast<const float *>((gb + u < g1 ? base + u * rowb : safe) + pq);
+#pragma unroll
+          for (int u = 0; u < kRedU; ++u) sum += gb + u < g1 ? v[u] : 0.0f;
+        }
         return sum;
       };
       if (np <= 64 && a.Gi >= kNW) {
