@@ -343,9 +343,8 @@ def bench_large(args):
                             kernel_ms_per_launch=r["kernel_s"] * 1e3,
                             median_ms_per_launch=float(np.median(r["durs"])) * 1e3,
                             min_ms_per_launch=float(min(r["durs"])) * 1e3,
-                            # the automatic plans of these workloads run 8 waves per workgroup
-                            # (hidden blocks of 128 or 256 units)
-                            kernel=f"mlpk::k_large_train<{pi}, {3 if K <= 3 else 4}, 8>",
+                            kernel=f"mlpk::k_large_train<{pi}, {3 if K <= 3 else 4}, "
+                                   f"{mlp.large_plan(D, H, K, N, batch=batch, prec=q)['waves']}>",
                             achieved_tflops=ach, peak_tflops=PEAK[q], frac=ach / PEAK[q],
                             final_loss=r["final_loss"], dtype={"fp32": "f32", "bf16": "bf16", "e4m3": "e4m3"}[q])
     head = res_forms[prec]
@@ -557,7 +556,9 @@ def bench_shared(args):
                 "compensated_update": True, "operand_precision": prec, "step": "one epoch of every net"},
         roofline={"bound": "mfma", "achieved": achieved, "peak": PEAK[prec], "unit": "TFLOP/s",
                   "frac": achieved / PEAK[prec], "traffic": measured_traffic(f"w6-{prec}-steps{steps}", "large"),
-                  "traffic_unit": "bytes per launch", "kernel": f"mlpk::k_large_train<{pi}, 3, 8>",
+                  "traffic_unit": "bytes per launch",
+                  "kernel": f"mlpk::k_large_train<{pi}, 3, "
+                            f"{mlp.large_plan(D, H, K, N, batch=batch, prec=prec, n_nets=M)['waves']}>",
                   "kernel_ms": kern * 1e3, "flops_per_launch": flops},
         final_loss_mean=final_loss_mean, repeats={"runs": 1, "median_ms_per_step": wall * 1e3 / steps,
                                                   "min_ms_per_step": wall * 1e3 / steps},

@@ -60,7 +60,8 @@ SYMBOLS = ["mlp_workspace_size", "mlp_init", "mlp_destroy", "mlp_forward", "mlp_
            "mlp_train", "mlp_predict", "mlp_train_batched", "mlp_eval_batched", "mlp_shared_workspace_size",
            "mlp_train_shared", "mlp_train_shared_static", "mlp_barrier_probe", "mlp_set_momentum", "mlp_dense_forward", "mlp_dense_backward",
            "mlp_update", "mlp_mse_grad", "mlp_deep_train", "mlp_query_status", "mlp_workspace_status",
-           "mlp_set_wait_limit", "mlp_mfma_probe", "mlp_set_launch_hint", "mlp_status_string", "mlp_last_error"]
+           "mlp_set_wait_limit", "mlp_mfma_probe", "mlp_set_launch_hint", "mlp_large_plan", "mlp_status_string",
+           "mlp_last_error"]
 
 
 def _load():
@@ -87,6 +88,7 @@ def _load():
     lib.mlp_train_shared_static.argtypes = [ctypes.POINTER(Config), i32, ctypes.POINTER(f32), vp, vp, vp, vp, i32,
                                             vp, vp]
     lib.mlp_set_launch_hint.argtypes = [ctypes.POINTER(LaunchHint)]
+    lib.mlp_large_plan.argtypes = [ctypes.POINTER(Config), i32, i32, ctypes.POINTER(i32)]
     lib.mlp_barrier_probe.argtypes = [i32, i32, vp, ctypes.c_size_t, vp]
     lib.mlp_set_momentum.argtypes = [vp, f32, vp]
     lib.mlp_dense_forward.argtypes = [vp, i64, i32, i32, vp, vp, i32, vp, vp]

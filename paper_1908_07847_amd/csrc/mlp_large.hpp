@@ -12,6 +12,10 @@ namespace mlph {
 // (MLP_ERR_UNSUPPORTED when no kernel here covers cfg).
 mlp_status large_workspace_bytes(const mlp_config &cfg, int n_nets, size_t *bytes);
 
+// The plan the trainer would launch for n_nets nets of shape cfg on n_cu
+// CUs: {Gi, Gj, waves, rows staged per piece}.
+mlp_status large_plan(const mlp_config &cfg, int n_nets, int n_cu, int shape[4], std::string *err);
+
 // Launch hint for the Gi x Gj grid (0, 0: automatic) and the waves per
 // workgroup (0: automatic, else 4 or 8).
 void set_large_grid_hint(int row_blocks, int hidden_blocks, int waves);

@@ -435,6 +435,19 @@ def train_shared(X: torch.Tensor, T: torch.Tensor, theta: torch.Tensor, lrs, epo
     return loss_hist
 
 
+def large_plan(n_in: int, n_hidden: int, n_out: int, n_rows: int, *, batch: int = 0, prec: str = "fp32",
+               n_nets: int = 1, n_cu: int | None = None) -> dict:
+    """The launch shape of the large-N trainer for this shape (host-side
+    query, no device call unless n_cu is None): row blocks, hidden blocks,
+    waves per workgroup and rows staged per piece."""
+    if n_cu is None:
+        n_cu = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+    cfg = Config(int(n_in), int(n_hidden), int(n_out), _lib.PREC[prec], int(n_rows), int(batch), 0.1, 0)
+    out = (ctypes.c_int32 * 4)()
+    check(lib.mlp_large_plan(ctypes.byref(cfg), int(n_nets), int(n_cu), out))
+    return {"row_blocks": out[0], "hidden_blocks": out[1], "waves": out[2], "piece_rows": out[3]}
+
+
 def set_launch_hint(small_threads: int = 0, large_grid: tuple[int, int] | None = None, large_waves: int = 0) -> None:
     """Launch-shape override for the autotuner (0 / None: the library's choice)."""
     gi, gj = large_grid if large_grid else (0, 0)

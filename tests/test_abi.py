@@ -236,3 +236,35 @@ def test_status_and_check_flags_on_the_host():
     assert L.lib.mlp_set_wait_limit(-1) == L.MLP_OK   # back to the default
     assert L.lib.mlp_status_string(L.MLP_ERR_TIMEOUT) == b"a grid-wide wait gave up"
     assert L.lib.mlp_status_string(L.MLP_ERR_NONFINITE) == b"non-finite parameter or loss"
+
+
+def test_large_plan_on_the_host():
+    """mlp_large_plan is host arithmetic: the wide 64-1024-3 net fills 256 CUs
+    with 64 row blocks of 256 rows x 4 hidden blocks of 256 units on 8 waves;
+    the 33-256-3 net with 4096-row minibatches takes 64-row blocks and 64-unit
+    hidden blocks on 4 waves; a launch hint overrides the grid and the waves;
+    bad arguments and uncovered shapes are rejected."""
+    from paper_1908_07847_amd import mlp
+    L = _lib()
+    assert mlp.large_plan(64, 1024, 3, 4194304, batch=16384, n_cu=256) == \
+        {"row_blocks": 64, "hidden_blocks": 4, "waves": 8, "piece_rows": 256}
+    p = mlp.large_plan(33, 256, 3, 1048576, batch=4096, prec="bf16", n_cu=256)
+    assert (p["row_blocks"], p["hidden_blocks"], p["waves"]) == (64, 4, 4)
+    q = mlp.large_plan(64, 1024, 3, 4194304, batch=16384, n_nets=64, n_cu=256)
+    assert q["row_blocks"] * 64 * q["hidden_blocks"] <= 256
+    mlp.set_launch_hint(large_grid=(128, 2), large_waves=8)
+    try:
+        r = mlp.large_plan(33, 256, 3, 1048576, batch=4096, n_cu=256)
+        assert (r["row_blocks"], r["hidden_blocks"], r["waves"]) == (128, 2, 8)
+    finally:
+        mlp.reset_launch_hint()
+    out = (ctypes.c_int32 * 4)()
+    c = L.Config(64, 1024, 3, 0, 4194304, 16384, 0.1, 0)
+    assert L.lib.mlp_large_plan(None, 1, 256, out) == L.MLP_ERR_ARG
+    assert L.lib.mlp_large_plan(ctypes.byref(c), 1, 256, None) == L.MLP_ERR_ARG
+    assert L.lib.mlp_large_plan(ctypes.byref(c), 1, 0, out) == L.MLP_ERR_ARG
+    assert L.lib.mlp_large_plan(ctypes.byref(c), 65, 256, out) == L.MLP_ERR_ARG
+    wide_in = L.Config(65, 16, 3, 0, 4096, 64, 0.1, 0)
+    assert L.lib.mlp_large_plan(ctypes.byref(wide_in), 1, 256, out) == L.MLP_ERR_UNSUPPORTED
+    odd_batch = L.Config(33, 256, 3, 0, 4096, 48, 0.1, 0)
+    assert L.lib.mlp_large_plan(ctypes.byref(odd_batch), 1, 256, out) == L.MLP_ERR_UNSUPPORTED
