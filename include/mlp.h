@@ -406,8 +406,12 @@ mlp_status mlp_mfma_probe(int32_t prec, const float *A, const float *B, float *C
  * calls it should affect, not concurrently with them.  It exists for an
  * autotuner that times candidate shapes and remembers the fastest:
  *   small_threads        threads per net in the small / batched trainer:
- *                        128, 256 or 512 (fewer are used when the larger
- *                        count's LDS plan would not fit);
+ *                        128, 256 or 512, the waves splitting the rows
+ *                        (fewer are used when the larger count's LDS plan
+ *                        would not fit), or 64: one wave per 16 hidden
+ *                        units of the widest net, the waves splitting the
+ *                        hidden layer (sigmoid without momentum; the
+ *                        variants then run on 128 threads);
  *   large_row_blocks,    the Gi x Gj grid of the large-N trainer (row blocks
  *   large_hidden_blocks  of >= 32 rows, hidden blocks of <= 256 units);
  *   large_waves          waves per workgroup of the large-N trainer, 4 or 8

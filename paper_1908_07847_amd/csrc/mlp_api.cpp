@@ -119,8 +119,8 @@ mlp_status mlp_set_launch_hint(const mlp_launch_hint *hint) {
     return MLP_OK;
   }
   const int t = hint->small_threads;
-  if (t != 0 && t != 128 && t != 256 && t != 512)
-    return fail(MLP_ERR_ARG, "small_threads must be 0, 128, 256 or 512");
+  if (t != 0 && t != 64 && t != 128 && t != 256 && t != 512)
+    return fail(MLP_ERR_ARG, "small_threads must be 0, 64, 128, 256 or 512");
   if (hint->large_row_blocks < 0 || hint->large_row_blocks > 256 || hint->large_hidden_blocks < 0 ||
       hint->large_hidden_blocks > 16)
     return fail(MLP_ERR_ARG, "large grid hint outside [0,256] x [0,16]");

@@ -120,8 +120,12 @@ namespace mlph {
 constexpr int64_t kBackwardChunk = 16384;
 
 // Small-network trainer: one workgroup per net, all epochs in one launch.
-// items == nullptr means a single net described by `one`.  threads is 256,
-// 512 or 1024 (small_threads picks it from the net count and a hint).
+// items == nullptr means a single net described by `one`.  threads is 128,
+// 256 or 512 (waves split the rows), or kHiddenSplit: one wave per 16
+// hidden units of the widest net (waves split the hidden layer; the paper's
+// sigmoid network without momentum, others fall back to 128 threads).
+// small_threads picks it from the net count and a hint.
+constexpr int kHiddenSplit = 64;
 size_t small_lds_bytes(int n_rows, int n_hidden, int n_in, int threads, bool momentum = false);
 size_t small_launch_lds_bytes(int max_rows, int max_hidden, int n_in, int threads, bool momentum = false);
 int small_threads(int n_nets, int hint);

@@ -446,6 +446,309 @@ hipError_t launch_nw(int max_hidden, const mlp_batch_item *items, mlp_batch_item
   return launch_one<NW, 4, 4, ACT>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs, loss_hist, var, s);
 }
 
+
+// ---------------------------------------------------------------------------
+// Hidden-split form of the same trainer (the paper's sigmoid network, plain
+// or compensated update): the NW waves of a workgroup split the hidden layer
+// instead of the rows.  Wave w owns hidden tile w (units 16 w .. 16 w + 15)
+// for every row of the net; waves past the net's last tile only pass the
+// barriers.  Per epoch:
+//   phase A (every 16-row tile): z1^T of the wave's tile on MFMA, a and the
+//     slope kept in registers for the epoch, and the tile's share of z2 (its
+//     16 hidden units, reduce-scattered over the lanes of a row) to LDS;
+//   one barrier;
+//   phase B (every row tile): z2 = the tiles' shares summed in tile order
+//     plus b2, y and delta2 (each wave forms them itself, so every wave holds
+//     the same values), then for the wave's own units gW2 += a^T delta2,
+//     delta1 = (W2^T delta2) . slope with the pre-update W2, and
+//     gW1 += delta1^T [X 1], all on MFMA and accumulated in registers;
+//   the update: each wave applies its own W1 rows and W2 columns from the
+//     registers that hold their gradients, the Kahan terms living in the same
+//     lanes; b2 is kept and updated in registers by every wave alike (the
+//     same delta2 sums), wave 0 writing it back at the end.
+// A wave reads only its own W1 rows and W2 columns, the shares of consecutive
+// epochs alternate between two buffers, and b2 is private to each wave, so
+// one barrier per epoch suffices and no per-wave partial gradients exist:
+// LDS holds X, T, the parameters and the shares only.
+// Limits: N <= 128 rows, H <= 16 NW <= 64, D <= 48, K <= 4.
+struct HSplitLayout {
+  int N, H, D, NW, NP, NPT, DA, DK, DN, FT, XS, HP;
+  __host__ __device__ HSplitLayout(int n, int h, int d, int nw) : N(n), H(h), D(d), NW(nw) {
+    NP = (n + 15) / 16 * 16;
+    NPT = NP / 16;
+    DA = d + 1;
+    DK = (DA + 3) / 4 * 4;
+    DN = (DA + 15) / 16 * 16;
+    FT = DN / 16;
+    XS = DN + 2;
+    HP = (h + 15) / 16 * 16;
+  }
+  __host__ __device__ int xs() const { return 0; }                 // [NP][XS] rows, ones column
+  __host__ __device__ int w1() const { return xs() + NP * XS; }    // [HP][XS] W1 | b1
+  __host__ __device__ int w2() const { return w1() + HP * XS; }    // [4][HP]
+  __host__ __device__ int ts() const { return w2() + 4 * HP; }     // [NP][4] targets
+  __host__ __device__ int zs() const { return ts() + NP * 4; }     // [2][NW][NP][4] z2 shares
+  __host__ __device__ int dst() const { return zs() + 2 * NW * NP * 4; }   // [NW][16][16] staging
+  __host__ __device__ int dd() const { return dst() + NW * 256; }  // [NW][16][4] delta2 staging
+  __host__ __device__ int total() const { return dd() + NW * 64; }
+};
+
+// At most 256 registers per lane (two waves per SIMD): the LDS of a net
+// (up to ~63 KB) lets two to six nets, i.e. at most two waves per SIMD,
+// share a CU anyway.
+template <int NW, int KO>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2))) void k_small_hsplit(
+    const mlp_batch_item *__restrict__ items, mlp_batch_item one, int D, int K,
+    const float *__restrict__ X, const float *__restrict__ T, float *__restrict__ theta,
+    float *__restrict__ comp, int epochs, float *__restrict__ loss_hist) {
+  constexpr int NT = NW * 64;
+  const mlp_batch_item it = items ? items[blockIdx.x] : one;
+  const int N = it.n_rows, H = it.n_hidden;
+  const float lr = it.lr;
+  const HSplitLayout L(N, H, D, NW);
+  const int XS = L.XS, HP = L.HP, FT = L.FT, DK = L.DK, NP = L.NP, NPT = L.NPT;
+  const int HTn = HP / 16;   // hidden tiles of this net
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int l16_0 = lane & 15, lg_0 = lane >> 4;
+  int l16 = l16_0, lg = lg_0;
+
+  extern __shared__ float4 smem4[];
+  float *sm = reinterpret_cast<float *>(smem4);
+  float *Xs = sm + L.xs();
+  float *W1s = sm + L.w1();
+  float *W2s = sm + L.w2();
+  float *Ts = sm + L.ts();
+  float *Zs = sm + L.zs();
+  float *Dst = sm + L.dst() + wave * 256;
+  float *Dd = sm + L.dd() + wave * 64;
+
+  const float *Xg = X + it.x_off * D;
+  const float *Tg = T + it.x_off * K;
+  float *P = theta + it.p_off;
+  float *Cp = comp ? comp + it.p_off : nullptr;
+  const bool compensated = Cp != nullptr;
+  const int D1 = D + 1;
+  const int oB1 = H * D, oW2 = oB1 + H, oB2 = oW2 + K * H;
+
+  // ---- stage rows (with the ones column), targets, W1 | b1, W2; zero padding
+  for (int i = tid; i < NP * XS; i += NT) {
+    const int r = i / XS, c = i - r * XS;
+    Xs[i] = (r < N && c < D) ? Xg[(int64_t)r * D + c] : ((r < N && c == D) ? 1.0f : 0.0f);
+  }
+  for (int i = tid; i < NP * 4; i += NT) {
+    const int r = i >> 2, k = i & 3;
+    Ts[i] = (r < N && k < K) ? Tg[(int64_t)r * K + k] : 0.0f;
+  }
+  for (int i = tid; i < HP * XS; i += NT) {
+    const int h = i / XS, c = i - h * XS;
+    W1s[i] = (h < H && c < D) ? P[h * D + c] : ((h < H && c == D) ? P[oB1 + h] : 0.0f);
+  }
+  for (int i = tid; i < 4 * HP; i += NT) {
+    const int k = i / HP, h = i - k * HP;
+    W2s[i] = (k < K && h < H) ? P[oW2 + k * H + h] : 0.0f;
+  }
+  // this wave's tile and the parameters its lanes update: W1[h0 + 4 lg + i]
+  // [16 ft + l16] (b1 is column D), W2[l16][h0 + 4 lg + i] for l16 < K, and
+  // b2[lg] (every wave's own copy)
+  const bool own = wave < HTn;
+  const int h0 = wave * 16;
+  float c1[4][4], c2[4];
+#pragma unroll
+  for (int ft = 0; ft < 4; ++ft)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int h = h0 + 4 * lg + i, d = 16 * ft + l16;
+      c1[ft][i] = (compensated && own && h < H && d < D1) ? Cp[d < D ? h * D + d : oB1 + h] : 0.0f;
+    }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int h = h0 + 4 * lg + i;
+    c2[i] = (compensated && own && l16 < K && h < H) ? Cp[oW2 + l16 * H + h] : 0.0f;
+  }
+  float b2v = lg < K ? P[oB2 + lg] : 0.0f;
+  float cb = (compensated && lg < K) ? Cp[oB2 + lg] : 0.0f;
+  __syncthreads();
+
+  const float dscale = 2.0f / (float)(N * K);
+  const float inv_nk = 1.0f / (float)(N * K);
+
+  for (int e = 0; e < epochs; ++e) {
+    float *zs = Zs + (e & 1) * (NW * NP * 4);
+    // the lane coordinates, opaque to the compiler each epoch: the per-lane
+    // LDS addresses are formed here instead of being hoisted out of the
+    // epoch loop and held (or spilled) for the whole run
+    int l16 = l16_0, lg = lg_0;
+    asm volatile("" : "+v"(l16), "+v"(lg));
+    float av[8][4], sl[8][4];
+    // ======================= phase A: a of this wave's tile, its share of z2
+    if (own) {
+#pragma unroll
+      for (int rt = 0; rt < 8; ++rt) {
+        if (rt < NPT) {
+          f32x4_s z = {0.f, 0.f, 0.f, 0.f};
+          const float *xa = Xs + (rt * 16 + l16) * XS + lg;
+          const float *wb = W1s + (h0 + l16) * XS + lg;
+          for (int k0 = 0; k0 < DK; k0 += 4) z = __builtin_amdgcn_mfma_f32_16x16x4f32(wb[k0], xa[k0], z, 0, 0, 0);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) av[rt][i] = sigmoid_slope(z[i], sl[rt][i]);
+          float zp[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int k = 0; k < KO; ++k) {
+            const f32x4_s w = *reinterpret_cast<const f32x4_s *>(W2s + k * HP + h0 + 4 * lg);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) zp[k] = fmaf(av[rt][i], w[i], zp[k]);
+          }
+          // reduce-scatter over the row's four lane groups: lane (row, lg)
+          // ends with output lg of the row
+          const bool hi2 = (lg & 2) != 0, hi1 = (lg & 1) != 0;
+          float ka = hi2 ? zp[2] : zp[0], kb = hi2 ? zp[3] : zp[1];
+          const float sa = hi2 ? zp[0] : zp[2], sb = hi2 ? zp[1] : zp[3];
+          ka += __shfl_xor(sa, 32, kWave);
+          kb += __shfl_xor(sb, 32, kWave);
+          zs[(wave * NP + rt * 16 + l16) * 4 + lg] = (hi1 ? kb : ka) + __shfl_xor(hi1 ? ka : kb, 16, kWave);
+        }
+      }
+    }
+    __syncthreads();
+    if (!own) continue;
+    // ======================= phase B: delta2, then this tile's gradients
+    f32x4_s gacc[4], g2 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ft = 0; ft < 4; ++ft) gacc[ft] = f32x4_s{0.f, 0.f, 0.f, 0.f};
+    float gb2 = 0.0f, sq = 0.0f;
+#pragma unroll
+    for (int rt = 0; rt < 8; ++rt) {
+      if (rt < NPT) {
+        const int n = rt * 16 + l16, k = lg;
+        float z2 = 0.0f;
+        for (int w = 0; w < HTn; ++w) z2 += zs[(w * NP + n) * 4 + k];
+        const float y = sigmoid(z2 + b2v);
+        const bool on = k < K && n < N;
+        const float err = on ? y - Ts[n * 4 + k] : 0.0f;
+        sq = fmaf(err, err, sq);
+        const float d2 = dscale * err * y * (1.0f - y);
+        gb2 += d2;
+        Dd[l16 * 4 + k] = d2;
+        // gW2^T += a^T delta2 (M = hidden, N = outputs, K = the tile's rows)
+        *reinterpret_cast<f32x4_s *>(Dst + l16 * 16 + 4 * lg) =
+            f32x4_s{av[rt][0], av[rt][1], av[rt][2], av[rt][3]};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const float dv = Dd[(4 * s + lg) * 4 + (l16 & 3)];
+          g2 = __builtin_amdgcn_mfma_f32_16x16x4f32(Dst[(4 * s + lg) * 16 + l16], l16 < 4 ? dv : 0.0f, g2, 0, 0,
+                                                   0);
+        }
+        // delta1^T = W2^T delta2^T (the pre-update W2), times the slope
+        const f32x4_s bp = __builtin_amdgcn_mfma_f32_16x16x4f32(W2s[lg * HP + h0 + l16], d2,
+                                                               f32x4_s{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        *reinterpret_cast<f32x4_s *>(Dst + l16 * 16 + 4 * lg) =
+            f32x4_s{bp[0] * sl[rt][0], bp[1] * sl[rt][1], bp[2] * sl[rt][2], bp[3] * sl[rt][3]};
+        // gW1 += delta1^T [X 1] (M = hidden, N = features, K = the tile's rows)
+        const float *da = Dst + lg * 16 + l16;
+#pragma unroll
+        for (int ft = 0; ft < 4; ++ft) {
+          if (ft < FT) {
+            const float *xb = Xs + (rt * 16 + lg) * XS + ft * 16 + l16;
+            f32x4_s g = gacc[ft];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) g = __builtin_amdgcn_mfma_f32_16x16x4f32(da[s * 64], xb[s * 4 * XS], g, 0, 0, 0);
+            gacc[ft] = g;
+          }
+        }
+      }
+    }
+    if (wave == 0 && loss_hist) {
+      const float sqw = wave_sum(sq);
+      if (lane == 0) loss_hist[(int64_t)blockIdx.x * epochs + e] = sqw * inv_nk;
+    }
+    // ======================= update: this wave's W1 rows and W2 columns, b2
+#pragma unroll
+    for (int ft = 0; ft < 4; ++ft) {
+      if (ft < FT) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int h = h0 + 4 * lg + i, d = 16 * ft + l16;
+          if (h < H && d < D1) {
+            const int o = h * XS + d;
+            float wv = W1s[o];
+            gd_update(wv, c1[ft][i], lr, gacc[ft][i], compensated);
+            W1s[o] = wv;
+          }
+        }
+      }
+    }
+    if (l16 < K) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int h = h0 + 4 * lg + i;
+        if (h < H) {
+          const int o = l16 * HP + h;
+          float wv = W2s[o];
+          gd_update(wv, c2[i], lr, g2[i], compensated);
+          W2s[o] = wv;
+        }
+      }
+    }
+    // every lane of group lg holds the row sum of output lg after sum16
+    gb2 = sum16(gb2);
+    if (lg < K) gd_update(b2v, cb, lr, gb2, compensated);
+  }
+  __syncthreads();
+
+  // ---- write the trained parameters (and compensation) back once
+  if (own) {
+#pragma unroll
+    for (int ft = 0; ft < 4; ++ft) {
+      if (ft < FT) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int h = h0 + 4 * lg + i, d = 16 * ft + l16;
+          if (h < H && d < D1) {
+            const int o = d < D ? h * D + d : oB1 + h;
+            P[o] = W1s[h * XS + d];
+            if (compensated) Cp[o] = c1[ft][i];
+          }
+        }
+      }
+    }
+    if (l16 < K) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int h = h0 + 4 * lg + i;
+        if (h < H) {
+          P[oW2 + l16 * H + h] = W2s[l16 * HP + h];
+          if (compensated) Cp[oW2 + l16 * H + h] = c2[i];
+        }
+      }
+    }
+  }
+  if (wave == 0 && l16 == 0 && lg < K) {
+    P[oB2 + lg] = b2v;
+    if (compensated) Cp[oB2 + lg] = cb;
+  }
+}
+
+template <int NW, int KO>
+hipError_t launch_hsplit_one(const mlp_batch_item *items, mlp_batch_item one, int n_nets, int n_in, int n_out,
+                             size_t lds, const float *X, const float *T, float *theta, float *comp, int epochs,
+                             float *loss_hist, hipStream_t s) {
+  auto kern = k_small_hsplit<NW, KO>;
+  hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(n_nets), dim3(NW * 64), lds, s, items, one, n_in, n_out, X, T, theta, comp,
+                     epochs, loss_hist);
+  return hipGetLastError();
+}
+
+template <int NW>
+hipError_t launch_hsplit_nw(const mlp_batch_item *items, mlp_batch_item one, int n_nets, int n_in, int n_out,
+                            size_t lds, const float *X, const float *T, float *theta, float *comp, int epochs,
+                            float *loss_hist, hipStream_t s) {
+  if (n_out <= 3)
+    return launch_hsplit_one<NW, 3>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs, loss_hist, s);
+  return launch_hsplit_one<NW, 4>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs, loss_hist, s);
+}
+
 }  // namespace mlpk
 
 namespace mlph {
@@ -456,7 +759,7 @@ size_t small_lds_bytes(int n_rows, int n_hidden, int n_in, int threads, bool mom
 }
 
 int small_threads(int n_nets, int hint) {
-  if (hint == 128 || hint == 256 || hint == 512) return hint;
+  if (hint == kHiddenSplit || hint == 128 || hint == 256 || hint == 512) return hint;
   return n_nets <= 64 ? 512 : 128;
 }
 
@@ -471,6 +774,23 @@ hipError_t launch_small_train(const mlp_batch_item *items, mlp_batch_item one, i
                               float *loss_hist, int act, float mu, float *vel, int threads, hipStream_t s) {
   const mlpk::SmallVariant var{act, mu, vel};
   const bool mom = vel != nullptr;
+  if (threads == kHiddenSplit) {
+    if (act == 0 && !mom) {
+      // one wave per 16 hidden units of the launch's widest net
+      const int tiles = (max_hidden + 15) / 16;
+      const int nw = tiles <= 1 ? 1 : (tiles <= 2 ? 2 : 4);
+      const size_t lds = sizeof(float) * (size_t)mlpk::HSplitLayout(max_rows, max_hidden, n_in, nw).total();
+      if (nw == 1)
+        return mlpk::launch_hsplit_nw<1>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs,
+                                         loss_hist, s);
+      if (nw == 2)
+        return mlpk::launch_hsplit_nw<2>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs,
+                                         loss_hist, s);
+      return mlpk::launch_hsplit_nw<4>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs,
+                                       loss_hist, s);
+    }
+    threads = 128;   // the variants run on the row-split form
+  }
   // fewer waves when the per-wave partial buffers would not fit in LDS
   while (threads > 128 && small_launch_lds_bytes(max_rows, max_hidden, n_in, threads, mom) > 160 * 1024)
     threads /= 2;

@@ -32,7 +32,7 @@ from . import mlp
 from ._lib import MLPError
 
 CACHE_ENV = "MLP_TUNE_CACHE"
-SMALL_CHOICES = (128, 256, 512)
+SMALL_CHOICES = (64, 128, 256, 512)   # 64: the hidden-split form
 
 
 def cache_path() -> str:

@@ -401,3 +401,70 @@ def test_size_grouped_plan_replays_from_a_graph(M, batched_full):
         graph.replay()
         torch.cuda.synchronize()
         assert torch.equal(a, b) and torch.equal(ca, cb) and torch.equal(ha, hb), rep
+
+
+@pytest.mark.parametrize("n,d,h,k,epochs,lr", [
+    (1, 1, 1, 1, 300, 0.5),          # degenerate: one row, one feature, one unit (one wave)
+    (128, 48, 64, 4, 150, 0.1),      # every limit at once (four waves)
+    (77, 20, 37, 3, 400, 0.3),       # ragged everything: three tiles on four waves, one idle
+    (5, 33, 64, 2, 300, 1.0),        # fewer rows than hidden units
+    (120, 33, 20, 3, 500, 0.1),      # two tiles, the second partly padding
+])
+def test_hidden_split_edge_shapes_match_oracle(M, n, d, h, k, epochs, lr):
+    """The hidden-split form of the small trainer (launch hint 64: one wave
+    per 16 hidden units, the waves splitting the hidden layer, one barrier per
+    epoch) trains a single net as the oracle does."""
+    g = np.random.default_rng(n * 1000 + h + 7)
+    X = g.standard_normal((n, d)).astype(np.float32)
+    T = np.eye(k, dtype=np.float32)[g.integers(0, k, n)]
+    th = synth.theta0(d, h, k, g)
+    say(f"hidden-split n={n} d={d} h={h} k={k}")
+    M.set_launch_hint(small_threads=64)
+    try:
+        _, flat, hist = gpu_train(M, X, T, th, epochs, lr=lr)
+        _, flat_p, _ = gpu_train(M, X, T, th, epochs, lr=lr, compensated=False)
+    finally:
+        M.reset_launch_hint()
+    q, ref_hist = oracle.train(X, T, Params.of(th), lr, epochs)
+    check_params(flat, q)
+    assert normwise(hist, ref_hist) <= TOL
+    check_params(flat_p, q, tol=1e-4)   # the plain update: float32 drift only
+
+
+def test_hidden_split_plan_every_net(M, batched_full):
+    """Every group of the size-grouped plan on the hidden-split form trains
+    every net as the oracle does, bitwise repeatably, and a net's result does
+    not depend on the nets launched with it."""
+    w = batched_full
+    epochs = 25
+    plan = M.BatchPlan(w["items"], buckets=True)
+    plan.threads[:] = [64] * len(plan.groups)
+    X = torch.from_numpy(w["X"]).cuda()
+    T = torch.from_numpy(w["T"]).cuda()
+    th0 = torch.from_numpy(w["theta"]).cuda()
+    outs = []
+    for rep in range(2):
+        th = th0.clone()
+        hist = torch.empty((len(w["items"]), epochs), device="cuda")
+        M.train_batched(plan, X, T, th, torch.zeros_like(th), epochs, 33, 3, loss_hist=hist)
+        torch.cuda.synchronize()
+        outs.append((th.cpu().numpy(), hist.cpu().numpy()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    got, h = outs[0][0], np.empty_like(outs[0][1])
+    h[plan.order] = outs[0][1]
+    ref, ref_hist = oracle.train_many(w["items"], w["X"], w["T"], w["theta"], 33, 3, epochs, threads=0)
+    worst = 0.0
+    for i, it in enumerate(w["items"]):
+        s = _net_slice(w, it)
+        check_params(got[s], Params.of(synth.Theta.unpack(ref[s], 33, it["n_hidden"], 3)))
+        worst = max(worst, normwise(h[i], ref_hist[i]))
+    assert worst <= TOL
+    # one net alone gives the same bits as in its group
+    one = w["items"][7]
+    M.set_launch_hint(small_threads=64)
+    try:
+        alone, _ = run_batched(M, w, epochs, order="given", items=[one])
+    finally:
+        M.reset_launch_hint()
+    s = _net_slice(w, one)
+    assert np.array_equal(alone[s], got[s])
