@@ -35,6 +35,7 @@
 //
 // Limits: N <= 128 rows, H <= 64, D <= 48, K <= 4.
 #include <algorithm>
+#include <type_traits>
 
 #include "mlp_device.hpp"
 
@@ -453,13 +454,15 @@ hipError_t launch_nw(int max_hidden, const mlp_batch_item *items, mlp_batch_item
 // instead of the rows.  Wave w owns hidden tile w (units 16 w .. 16 w + 15)
 // for every row of the net; waves past the net's last tile only pass the
 // barriers.  Per epoch:
-//   phase A (every 16-row tile): z1^T of the wave's tile on MFMA, a and the
-//     slope kept in registers for the epoch, and the tile's share of z2 (its
+//   phase A (every 16-row tile): z1^T of the wave's tile on MFMA, kept in
+//     registers for the epoch, and the tile's share of z2 (its
 //     16 hidden units, reduce-scattered over the lanes of a row) to LDS;
 //   one barrier;
 //   phase B (every row tile): z2 = the tiles' shares summed in tile order
 //     plus b2, y and delta2 (each wave forms them itself, so every wave holds
-//     the same values), then for the wave's own units gW2 += a^T delta2,
+//     the same values), then for the wave's own units a and the slope again
+//     from z1 (two sigmoids per element cost less than holding both),
+//     gW2 += a^T delta2,
 //     delta1 = (W2^T delta2) . slope with the pre-update W2, and
 //     gW1 += delta1^T [X 1], all on MFMA and accumulated in registers;
 //   the update: each wave applies its own W1 rows and W2 columns from the
@@ -469,35 +472,38 @@ hipError_t launch_nw(int max_hidden, const mlp_batch_item *items, mlp_batch_item
 // A wave reads only its own W1 rows and W2 columns, the shares of consecutive
 // epochs alternate between two buffers, and b2 is private to each wave, so
 // one barrier per epoch suffices and no per-wave partial gradients exist:
-// LDS holds X, T, the parameters and the shares only.
-// Limits: N <= 128 rows, H <= 16 NW <= 64, D <= 48, K <= 4.
+// LDS holds X, the parameters and the shares only (the targets of a lane's
+// rows stay in its registers for the run).  The row stride of X and W1 is
+// DK + 2, the z1 contraction's length: the gW1 operand of the feature block
+// past DK reads into the next row, which only feeds gradients of padding
+// features that are never applied; so three 120-row, 64-unit nets share a CU.
+// Limits: N <= 128 rows, H <= 16 NW <= 64, D <= 48, K <= KO <= 4.
 struct HSplitLayout {
-  int N, H, D, NW, NP, NPT, DA, DK, DN, FT, XS, HP;
-  __host__ __device__ HSplitLayout(int n, int h, int d, int nw) : N(n), H(h), D(d), NW(nw) {
+  int N, H, D, NW, KO, NP, NPT, DA, DK, DN, FT, XS, HP;
+  __host__ __device__ HSplitLayout(int n, int h, int d, int nw, int ko)
+      : N(n), H(h), D(d), NW(nw), KO(ko) {
     NP = (n + 15) / 16 * 16;
     NPT = NP / 16;
     DA = d + 1;
     DK = (DA + 3) / 4 * 4;
     DN = (DA + 15) / 16 * 16;
     FT = DN / 16;
-    XS = DN + 2;
+    XS = DK + 2;
     HP = (h + 15) / 16 * 16;
   }
   __host__ __device__ int xs() const { return 0; }                 // [NP][XS] rows, ones column
   __host__ __device__ int w1() const { return xs() + NP * XS; }    // [HP][XS] W1 | b1
   __host__ __device__ int w2() const { return w1() + HP * XS; }    // [4][HP]
-  __host__ __device__ int ts() const { return w2() + 4 * HP; }     // [NP][4] targets
-  __host__ __device__ int zs() const { return ts() + NP * 4; }     // [2][NW][NP][4] z2 shares
-  __host__ __device__ int dst() const { return zs() + 2 * NW * NP * 4; }   // [NW][16][16] staging
-  __host__ __device__ int dd() const { return dst() + NW * 256; }  // [NW][16][4] delta2 staging
-  __host__ __device__ int total() const { return dd() + NW * 64; }
+  __host__ __device__ int zs() const { return w2() + 4 * HP; }     // [2][NW][NP][KO] z2 shares
+  __host__ __device__ int dst() const { return zs() + 2 * NW * NP * KO; }   // [NW][2][16][16] staging
+  __host__ __device__ int dd() const { return dst() + NW * 512; }  // [NW][2][16][4] delta2 staging
+  __host__ __device__ int total() const { return dd() + NW * 128 + 64; }   // + the over-read of the last X row
 };
 
-// At most 256 registers per lane (two waves per SIMD): the LDS of a net
-// (up to ~63 KB) lets two to six nets, i.e. at most two waves per SIMD,
-// share a CU anyway.
+// At most 168 registers per lane (three waves per SIMD): three of the
+// largest nets (52 KB of LDS each) share a CU.
 template <int NW, int KO>
-__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2))) void k_small_hsplit(
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(3))) void k_small_hsplit(
     const mlp_batch_item *__restrict__ items, mlp_batch_item one, int D, int K,
     const float *__restrict__ X, const float *__restrict__ T, float *__restrict__ theta,
     float *__restrict__ comp, int epochs, float *__restrict__ loss_hist) {
@@ -505,7 +511,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2))) vo
   const mlp_batch_item it = items ? items[blockIdx.x] : one;
   const int N = it.n_rows, H = it.n_hidden;
   const float lr = it.lr;
-  const HSplitLayout L(N, H, D, NW);
+  const HSplitLayout L(N, H, D, NW, KO);
   const int XS = L.XS, HP = L.HP, FT = L.FT, DK = L.DK, NP = L.NP, NPT = L.NPT;
   const int HTn = HP / 16;   // hidden tiles of this net
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -517,10 +523,9 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2))) vo
   float *Xs = sm + L.xs();
   float *W1s = sm + L.w1();
   float *W2s = sm + L.w2();
-  float *Ts = sm + L.ts();
   float *Zs = sm + L.zs();
-  float *Dst = sm + L.dst() + wave * 256;
-  float *Dd = sm + L.dd() + wave * 64;
+  float *Dst = sm + L.dst() + wave * 512;   // two buffers: a pair of row tiles
+  float *Dd = sm + L.dd() + wave * 128;
 
   const float *Xg = X + it.x_off * D;
   const float *Tg = T + it.x_off * K;
@@ -535,13 +540,16 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2))) vo
     const int r = i / XS, c = i - r * XS;
     Xs[i] = (r < N && c < D) ? Xg[(int64_t)r * D + c] : ((r < N && c == D) ? 1.0f : 0.0f);
   }
-  for (int i = tid; i < NP * 4; i += NT) {
-    const int r = i >> 2, k = i & 3;
-    Ts[i] = (r < N && k < K) ? Tg[(int64_t)r * K + k] : 0.0f;
-  }
   for (int i = tid; i < HP * XS; i += NT) {
     const int h = i / XS, c = i - h * XS;
     W1s[i] = (h < H && c < D) ? P[h * D + c] : ((h < H && c == D) ? P[oB1 + h] : 0.0f);
+  }
+  // the target of lane (row l16, output lg) of every row tile
+  float tv[8];
+#pragma unroll
+  for (int rt = 0; rt < 8; ++rt) {
+    const int n = rt * 16 + l16;
+    tv[rt] = (n < N && lg < K) ? Tg[(int64_t)n * K + lg] : 0.0f;
   }
   for (int i = tid; i < 4 * HP; i += NT) {
     const int k = i / HP, h = i - k * HP;
@@ -573,90 +581,148 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2))) vo
   const float inv_nk = 1.0f / (float)(N * K);
 
   for (int e = 0; e < epochs; ++e) {
-    float *zs = Zs + (e & 1) * (NW * NP * 4);
+    float *zs = Zs + (e & 1) * (NW * NP * KO);
     // the lane coordinates, opaque to the compiler each epoch: the per-lane
     // LDS addresses are formed here instead of being hoisted out of the
     // epoch loop and held (or spilled) for the whole run
     int l16 = l16_0, lg = lg_0;
     asm volatile("" : "+v"(l16), "+v"(lg));
-    float av[8][4], sl[8][4];
+    float zz[8][4];   // z1 of this wave's units, every row tile (a and the slope are re-formed from it)
     // ======================= phase A: a of this wave's tile, its share of z2
+    // Row tiles go in pairs whose two z1 chains share the W1 operand and
+    // interleave on the matrix cores (a lone last tile runs its own chain).
     if (own) {
+      const float *wb = W1s + (h0 + l16) * XS + lg;
+      auto finish = [&](auto rt_c, const f32x4_s &z) {
+        constexpr int rt = decltype(rt_c)::value;
+        float a[4];
 #pragma unroll
-      for (int rt = 0; rt < 8; ++rt) {
-        if (rt < NPT) {
-          f32x4_s z = {0.f, 0.f, 0.f, 0.f};
-          const float *xa = Xs + (rt * 16 + l16) * XS + lg;
-          const float *wb = W1s + (h0 + l16) * XS + lg;
-          for (int k0 = 0; k0 < DK; k0 += 4) z = __builtin_amdgcn_mfma_f32_16x16x4f32(wb[k0], xa[k0], z, 0, 0, 0);
-#pragma unroll
-          for (int i = 0; i < 4; ++i) av[rt][i] = sigmoid_slope(z[i], sl[rt][i]);
-          float zp[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-          for (int k = 0; k < KO; ++k) {
-            const f32x4_s w = *reinterpret_cast<const f32x4_s *>(W2s + k * HP + h0 + 4 * lg);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) zp[k] = fmaf(av[rt][i], w[i], zp[k]);
-          }
-          // reduce-scatter over the row's four lane groups: lane (row, lg)
-          // ends with output lg of the row
-          const bool hi2 = (lg & 2) != 0, hi1 = (lg & 1) != 0;
-          float ka = hi2 ? zp[2] : zp[0], kb = hi2 ? zp[3] : zp[1];
-          const float sa = hi2 ? zp[0] : zp[2], sb = hi2 ? zp[1] : zp[3];
-          ka += __shfl_xor(sa, 32, kWave);
-          kb += __shfl_xor(sb, 32, kWave);
-          zs[(wave * NP + rt * 16 + l16) * 4 + lg] = (hi1 ? kb : ka) + __shfl_xor(hi1 ? ka : kb, 16, kWave);
+        for (int i = 0; i < 4; ++i) {
+          zz[rt][i] = z[i];
+          a[i] = sigmoid(z[i]);
         }
-      }
+        float zp[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < KO; ++k) {
+          const f32x4_s w = *reinterpret_cast<const f32x4_s *>(W2s + k * HP + h0 + 4 * lg);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) zp[k] = fmaf(a[i], w[i], zp[k]);
+        }
+        // reduce-scatter over the row's four lane groups: lane (row, lg)
+        // ends with output lg of the row
+        const bool hi2 = (lg & 2) != 0, hi1 = (lg & 1) != 0;
+        float ka = hi2 ? zp[2] : zp[0], kb = hi2 ? zp[3] : zp[1];
+        const float sa = hi2 ? zp[0] : zp[2], sb = hi2 ? zp[1] : zp[3];
+        ka += __shfl_xor(sa, 32, kWave);
+        kb += __shfl_xor(sb, 32, kWave);
+        const float share = (hi1 ? kb : ka) + __shfl_xor(hi1 ? ka : kb, 16, kWave);
+        if (lg < KO) zs[(wave * NP + rt * 16 + l16) * KO + lg] = share;
+      };
+      auto pair = [&](auto r0_c) {
+        constexpr int r0 = decltype(r0_c)::value;
+        const float *xa = Xs + (r0 * 16 + l16) * XS + lg;
+        if (r0 + 1 < NPT) {
+          const float *xb = xa + 16 * XS;
+          f32x4_s za = {0.f, 0.f, 0.f, 0.f}, zb = {0.f, 0.f, 0.f, 0.f};
+          for (int k0 = 0; k0 < DK; k0 += 4) {
+            const float w = wb[k0];
+            za = __builtin_amdgcn_mfma_f32_16x16x4f32(w, xa[k0], za, 0, 0, 0);
+            zb = __builtin_amdgcn_mfma_f32_16x16x4f32(w, xb[k0], zb, 0, 0, 0);
+          }
+          finish(std::integral_constant<int, r0>{}, za);
+          finish(std::integral_constant<int, r0 + 1>{}, zb);
+        } else if (r0 < NPT) {
+          f32x4_s za = {0.f, 0.f, 0.f, 0.f};
+          for (int k0 = 0; k0 < DK; k0 += 4) za = __builtin_amdgcn_mfma_f32_16x16x4f32(wb[k0], xa[k0], za, 0, 0, 0);
+          finish(std::integral_constant<int, r0>{}, za);
+        }
+      };
+      pair(std::integral_constant<int, 0>{});
+      pair(std::integral_constant<int, 2>{});
+      pair(std::integral_constant<int, 4>{});
+      pair(std::integral_constant<int, 6>{});
     }
     __syncthreads();
     if (!own) continue;
     // ======================= phase B: delta2, then this tile's gradients
+    // Row tiles again go in pairs (two staging buffers), every product in
+    // the order a tile-by-tile loop would issue it, so a pair gives the same
+    // bits as its two tiles one after the other.
     f32x4_s gacc[4], g2 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ft = 0; ft < 4; ++ft) gacc[ft] = f32x4_s{0.f, 0.f, 0.f, 0.f};
     float gb2 = 0.0f, sq = 0.0f;
+    // delta2 of row tile rt in lane (row l16, output lg)
+    auto delta2 = [&](auto rt_c) {
+      constexpr int rt = decltype(rt_c)::value;
+      const int n = rt * 16 + l16, k = lg;
+      float z2 = 0.0f;
+      if (k < KO)
+        for (int w = 0; w < HTn; ++w) z2 += zs[(w * NP + n) * KO + k];
+      const float y = sigmoid(z2 + b2v);
+      const bool on = k < K && n < N;
+      const float err = on ? y - tv[rt] : 0.0f;
+      sq = fmaf(err, err, sq);
+      const float d2 = dscale * err * y * (1.0f - y);
+      gb2 += d2;
+      return d2;
+    };
+    // the gradients of NR (1 or 2) consecutive row tiles from r0
+    auto tiles = [&](auto r0_c, auto nr_c) {
+      constexpr int r0 = decltype(r0_c)::value, NR = decltype(nr_c)::value;
+      float d2[NR];
+      d2[0] = delta2(std::integral_constant<int, r0>{});
+      if constexpr (NR == 2) d2[NR - 1] = delta2(std::integral_constant<int, r0 + 1>{});
+      float av[NR][4], sl[NR][4];
 #pragma unroll
-    for (int rt = 0; rt < 8; ++rt) {
-      if (rt < NPT) {
-        const int n = rt * 16 + l16, k = lg;
-        float z2 = 0.0f;
-        for (int w = 0; w < HTn; ++w) z2 += zs[(w * NP + n) * 4 + k];
-        const float y = sigmoid(z2 + b2v);
-        const bool on = k < K && n < N;
-        const float err = on ? y - Ts[n * 4 + k] : 0.0f;
-        sq = fmaf(err, err, sq);
-        const float d2 = dscale * err * y * (1.0f - y);
-        gb2 += d2;
-        Dd[l16 * 4 + k] = d2;
-        // gW2^T += a^T delta2 (M = hidden, N = outputs, K = the tile's rows)
-        *reinterpret_cast<f32x4_s *>(Dst + l16 * 16 + 4 * lg) =
-            f32x4_s{av[rt][0], av[rt][1], av[rt][2], av[rt][3]};
+      for (int j = 0; j < NR; ++j) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) av[j][i] = sigmoid_slope(zz[r0 + j][i], sl[j][i]);
+        Dd[j * 64 + l16 * 4 + lg] = d2[j];
+        *reinterpret_cast<f32x4_s *>(Dst + j * 256 + l16 * 16 + 4 * lg) = f32x4_s{av[j][0], av[j][1], av[j][2], av[j][3]};
+      }
+      // gW2^T += a^T delta2 (M = hidden, N = outputs, K = the tile's rows)
+#pragma unroll
+      for (int j = 0; j < NR; ++j)
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-          const float dv = Dd[(4 * s + lg) * 4 + (l16 & 3)];
-          g2 = __builtin_amdgcn_mfma_f32_16x16x4f32(Dst[(4 * s + lg) * 16 + l16], l16 < 4 ? dv : 0.0f, g2, 0, 0,
-                                                   0);
+          const float dv = Dd[j * 64 + (4 * s + lg) * 4 + (l16 & 3)];
+          g2 = __builtin_amdgcn_mfma_f32_16x16x4f32(Dst[j * 256 + (4 * s + lg) * 16 + l16], l16 < 4 ? dv : 0.0f,
+                                                   g2, 0, 0, 0);
         }
-        // delta1^T = W2^T delta2^T (the pre-update W2), times the slope
-        const f32x4_s bp = __builtin_amdgcn_mfma_f32_16x16x4f32(W2s[lg * HP + h0 + l16], d2,
-                                                               f32x4_s{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-        *reinterpret_cast<f32x4_s *>(Dst + l16 * 16 + 4 * lg) =
-            f32x4_s{bp[0] * sl[rt][0], bp[1] * sl[rt][1], bp[2] * sl[rt][2], bp[3] * sl[rt][3]};
-        // gW1 += delta1^T [X 1] (M = hidden, N = features, K = the tile's rows)
-        const float *da = Dst + lg * 16 + l16;
+      // delta1^T = W2^T delta2^T (the pre-update W2), times the slope
 #pragma unroll
-        for (int ft = 0; ft < 4; ++ft) {
-          if (ft < FT) {
-            const float *xb = Xs + (rt * 16 + lg) * XS + ft * 16 + l16;
-            f32x4_s g = gacc[ft];
+      for (int j = 0; j < NR; ++j) {
+        const f32x4_s bp = __builtin_amdgcn_mfma_f32_16x16x4f32(W2s[lg * HP + h0 + l16], d2[j],
+                                                               f32x4_s{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        *reinterpret_cast<f32x4_s *>(Dst + j * 256 + l16 * 16 + 4 * lg) =
+            f32x4_s{bp[0] * sl[j][0], bp[1] * sl[j][1], bp[2] * sl[j][2], bp[3] * sl[j][3]};
+      }
+      // gW1 += delta1^T [X 1] (M = hidden, N = features, K = the tile's rows)
+#pragma unroll
+      for (int ft = 0; ft < 4; ++ft) {
+        if (ft < FT) {
+          f32x4_s g = gacc[ft];
+#pragma unroll
+          for (int j = 0; j < NR; ++j) {
+            const float *da = Dst + j * 256 + lg * 16 + l16;
+            const float *xb = Xs + ((r0 + j) * 16 + lg) * XS + ft * 16 + l16;
 #pragma unroll
             for (int s = 0; s < 4; ++s) g = __builtin_amdgcn_mfma_f32_16x16x4f32(da[s * 64], xb[s * 4 * XS], g, 0, 0, 0);
-            gacc[ft] = g;
           }
+          gacc[ft] = g;
         }
       }
-    }
+    };
+    auto pair_b = [&](auto r0_c) {
+      constexpr int r0 = decltype(r0_c)::value;
+      if (r0 + 1 < NPT) tiles(r0_c, std::integral_constant<int, 2>{});
+      else if (r0 < NPT) tiles(r0_c, std::integral_constant<int, 1>{});
+    };
+    pair_b(std::integral_constant<int, 0>{});
+    pair_b(std::integral_constant<int, 2>{});
+    pair_b(std::integral_constant<int, 4>{});
+    pair_b(std::integral_constant<int, 6>{});
     if (wave == 0 && loss_hist) {
       const float sqw = wave_sum(sq);
       if (lane == 0) loss_hist[(int64_t)blockIdx.x * epochs + e] = sqw * inv_nk;
@@ -779,7 +845,8 @@ hipError_t launch_small_train(const mlp_batch_item *items, mlp_batch_item one, i
       // one wave per 16 hidden units of the launch's widest net
       const int tiles = (max_hidden + 15) / 16;
       const int nw = tiles <= 1 ? 1 : (tiles <= 2 ? 2 : 4);
-      const size_t lds = sizeof(float) * (size_t)mlpk::HSplitLayout(max_rows, max_hidden, n_in, nw).total();
+      const size_t lds =
+          sizeof(float) * (size_t)mlpk::HSplitLayout(max_rows, max_hidden, n_in, nw, n_out <= 3 ? 3 : 4).total();
       if (nw == 1)
         return mlpk::launch_hsplit_nw<1>(items, one, n_nets, n_in, n_out, lds, X, T, theta, comp, epochs,
                                          loss_hist, s);
