@@ -1,7 +1,8 @@
 """GPU parity at the workloads' stated sizes (marked slow as well as gpu).
 
   * batched: every one of the 4096 independent nets, 2000 full-batch epochs,
-    against the float64 oracle (oracle.train_many, one net per host thread);
+    against the float64 oracle (oracle.train_many, one net per host thread),
+    on both launch forms (waves splitting the rows, or the hidden layer);
   * large-N: all 1,048,576 rows of the 33-256-3 workload for 20 epochs of
     4096-row minibatches (5,120 steps), float32, against the float64
     oracle's result stored by tests/golden/make_fullsize.py;
@@ -51,21 +52,38 @@ def M():
     return mlp
 
 
-def test_every_batched_net_at_2000_epochs(M):
+@pytest.fixture(scope="module")
+def batched_ref():
+    """The 4096-net workload and the float64 oracle's result for it at 2000
+    epochs (computed once for both launch forms)."""
     w = synth.batched()
+    say(f"batched: the oracle on {oracle.max_threads()} threads, {len(w['items'])} nets x {w['epochs']} epochs")
+    ref, ref_hist = oracle.train_many(w["items"], w["X"], w["T"], w["theta"], 33, 3, w["epochs"], threads=0)
+    return w, ref, ref_hist
+
+
+@pytest.mark.parametrize("form", ["rows", "hidden"])
+def test_every_batched_net_at_2000_epochs(M, batched_ref, form):
+    """Every net at 2000 epochs, on the row-split form (the library's default
+    launch) and on the hidden-split form (launch hint 64, which the autotuner
+    picks for the wide groups)."""
+    w, ref, ref_hist = batched_ref
     items, epochs = w["items"], w["epochs"]
     plan = M.BatchPlan(items)
     X = torch.from_numpy(w["X"]).cuda()
     T = torch.from_numpy(w["T"]).cuda()
     th = torch.from_numpy(w["theta"]).cuda()
     hist = torch.empty((len(items), epochs), device="cuda")
-    M.train_batched(plan, X, T, th, torch.zeros_like(th), epochs, 33, 3, loss_hist=hist)
-    torch.cuda.synchronize()
+    if form == "hidden":
+        M.set_launch_hint(small_threads=64)
+    try:
+        M.train_batched(plan, X, T, th, torch.zeros_like(th), epochs, 33, 3, loss_hist=hist)
+        torch.cuda.synchronize()
+    finally:
+        M.reset_launch_hint()
     got = th.cpu().numpy()
     h = np.empty((len(items), epochs), dtype=np.float32)
     h[plan.order] = hist.cpu().numpy()
-    say(f"batched: {len(items)} nets x {epochs} epochs on the GPU; the oracle on {oracle.max_threads()} threads")
-    ref, ref_hist = oracle.train_many(items, w["X"], w["T"], w["theta"], 33, 3, epochs, threads=0)
     worst, worst_net = 0.0, -1
     for i, it in enumerate(items):
         s = slice(it["p_off"], it["p_off"] + synth.n_params(33, it["n_hidden"], 3))
@@ -73,7 +91,8 @@ def test_every_batched_net_at_2000_epochs(M):
         e = max(e, normwise(h[i], ref_hist[i]))
         if e > worst:
             worst, worst_net = e, i
-    say(f"  worst normwise error over every net and tensor and the loss histories: {worst:.2e} (net {worst_net})")
+    say(f"  {form}-split form: worst normwise error over every net and tensor and the loss histories: "
+        f"{worst:.2e} (net {worst_net})")
     assert worst <= TOL
 
 
