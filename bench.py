@@ -486,7 +486,9 @@ def bench_batched(args):
                  "heldout_accuracy": float(vcor.sum() / vrows)},
         roofline={"bound": "alu", "achieved": achieved, "peak": PEAK["fp32"], "unit": "TFLOP/s",
                   "frac": achieved / PEAK["fp32"], "traffic": measured_traffic(f"w3-fp32-steps{steps}", "small"),
-                  "traffic_unit": "bytes per launch", "kernel": "mlpk::k_small_train",
+                  "traffic_unit": "bytes per launch",
+                  "kernel": " + ".join(sorted({"mlpk::k_small_hsplit" if t == 64 else "mlpk::k_small_train"
+                                               for t in threads})) + " (one launch per size group)",
                   "kernel_ms": kern * 1e3, "flops_per_launch": flops}, repeats=reps, vs_plain=vs_plain,
         steps=steps, warmup=warmup)
     return res, dict(w=w)

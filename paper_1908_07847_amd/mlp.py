@@ -325,7 +325,7 @@ class BatchPlan:
             start += c
         self.threads = [0] * len(self.groups)
         if len(self.groups) > 1:
-            self.side_streams = [torch.cuda.Stream(device=device) for _ in range(min(len(self.groups), 3))]
+            self.side_streams = [torch.cuda.Stream(device=device) for _ in range(min(len(self.groups), 4))]
 
     def host_at(self, start: int):
         """Pointer to the host item table from position `start`."""

@@ -2,9 +2,11 @@
 
 Choices tuned through `mlp_set_launch_hint` (include/mlp.h):
 
-  * small / batched trainer: waves per net (128, 256 or 512 threads).  More
-    waves shorten one net's epoch (fewer row tiles per wave); fewer waves let
-    more nets share a CU.
+  * small / batched trainer, per size group: the waves of a net splitting
+    its rows (128, 256 or 512 threads: more waves shorten one net's epoch,
+    fewer let more nets share a CU) or its hidden layer (64: one wave per 16
+    hidden units, one barrier per epoch and no per-wave partial gradients;
+    best for the wide nets, which then fit three to a CU).
   * large-N trainer: the Gi x Gj grid (row blocks x hidden blocks) and the
     waves per workgroup (4 or 8).  More row blocks spread the minibatch wider
     but add partial gradients to sum; more hidden blocks shrink each
@@ -135,7 +137,46 @@ def tune_batched(plan: "mlp.BatchPlan", X, T, theta, n_in: int, n_out: int, epoc
         _store(key, {"threads": best, "ms": times, "epochs": epochs, "when": time.time()})
         chosen.append(best)
     plan.threads[:] = chosen
+    if len(plan.groups) > 1:
+        chosen = _tune_together(plan, X, T, theta, n_in, n_out, epochs, force)
     return chosen
+
+
+def plan_key(n_in: int, plan: "mlp.BatchPlan") -> str:
+    sig = ",".join(f"N{_bucket(r)}H{_bucket(h)}n{_bucket(c)}" for _, c, r, h in plan.groups)
+    return f"{_device()}|smallplan|D{n_in}|{sig}"
+
+
+def _tune_together(plan, X, T, theta, n_in, n_out, epochs, force):
+    """The groups of a plan run concurrently, so a group's best shape alone
+    need not be its best in company (a shape whose workgroups need a whole
+    CU's LDS waits for CUs that the other groups keep busy).  One pass of
+    coordinate descent over the groups, each trying every choice with the
+    others fixed, on the time of the whole plan."""
+    key = plan_key(n_in, plan)
+    cached = _load_cache().get(key)
+    if cached and not force and len(cached["threads"]) == len(plan.groups):
+        plan.threads[:] = [int(t) for t in cached["threads"]]
+        return list(plan.threads)
+
+    def whole():
+        th = theta.clone()
+        comp = torch.zeros_like(th)
+        return _time(lambda: mlp.train_batched(plan, X, T, th, comp, epochs, n_in, n_out))
+
+    best_t = whole()
+    for g in range(len(plan.groups)):
+        keep = plan.threads[g]
+        for t in SMALL_CHOICES:
+            if t == keep:
+                continue
+            plan.threads[g] = t
+            tt = whole()
+            if tt < best_t:
+                best_t, keep = tt, t
+        plan.threads[g] = keep
+    _store(key, {"threads": list(plan.threads), "ms": best_t, "epochs": epochs, "when": time.time()})
+    return list(plan.threads)
 
 
 def tune_large(n_in: int, n_hidden: int, n_out: int, batch: int, prec: str, X, T, theta,
