@@ -457,11 +457,13 @@ def bench_batched(args):
     mlp.eval_batched(vplan, Xv, Tv, th, 33, 3)
     _, eval_s = timed(lambda: mlp.eval_batched(vplan, Xv, Tv, th, 33, 3), stream)
     vloss, vcor = mlp.eval_batched(vplan, Xv, Tv, th, 33, 3)
-    vloss, vcor = vloss.cpu().numpy(), vcor.cpu().numpy()
+    # the group (hidden size, learning rate) with the lowest mean held-out
+    # loss over its folds, selected on the device
     groups = np.array([it["group"] for it in w["items_val"]])
     ng = int(groups.max()) + 1
-    gmean = np.bincount(groups, weights=vloss, minlength=ng) / np.bincount(groups, minlength=ng)
-    best = int(np.argmin(gmean))
+    gmean_d, best_d = mlp.cv_select(vloss, torch.from_numpy(groups.astype(np.int32)).cuda(), ng)
+    gmean, best = gmean_d.cpu().numpy(), int(best_d.item())
+    vloss, vcor = vloss.cpu().numpy(), vcor.cpu().numpy()
     vrows = int(sum(it["n_rows"] for it in w["items_val"]))
     rows = sum(it["n_rows"] for it in items)
     flops = 0
@@ -479,7 +481,7 @@ def bench_batched(args):
                 "threads_per_net": threads,
                 "groups": [{"nets": c, "max_rows": r, "max_hidden": h} for (_, c, r, h) in plan.groups],
                 "launch": "hipGraph replay of one trainer launch per size group"},
-        cv_eval={"kernel": "mlpk::k_eval_batched", "ms": eval_s * 1e3, "heldout_rows": vrows,
+        cv_eval={"kernel": "mlpk::k_eval_batched + mlpk::k_cv_select", "ms": eval_s * 1e3, "heldout_rows": vrows,
                  "rows_per_s": vrows / eval_s, "best_group": best, "best_group_hidden": int(
                      w["items_val"][int(np.nonzero(groups == best)[0][0])]["n_hidden"]),
                  "best_mean_heldout_loss": float(gmean[best]),

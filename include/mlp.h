@@ -252,6 +252,20 @@ mlp_status mlp_eval_batched(const mlp_batch_item *items_host, const mlp_batch_it
                             int64_t total_rows, const float *theta_packed, int64_t total_params, float *loss,
                             int32_t *correct, void *stream);
 
+/* Cross-validation model selection over the nets of a batched run (the
+ * under/overfitting question of section 1 answered on a hidden-size grid),
+ * on the device: group_mean[g] = the mean of loss[i] over the nets i with
+ * group[i] == g, summed in increasing i in float32 (+inf for a group with no
+ * net or a non-finite mean), and best[0] = the group with the lowest mean,
+ * the lowest index on ties (0 when every mean is +inf).  loss [n_nets] (for
+ * instance mlp_eval_batched's held-out losses), group [n_nets] (int32),
+ * group_mean [n_groups] and best [1] are device pointers, 4-byte aligned;
+ * 1 <= n_nets, 1 <= n_groups <= 65536.  A net whose group index lies outside
+ * [0, n_groups) belongs to no group (the kernel cannot report it).  One
+ * launch on the stream, no allocation. */
+mlp_status mlp_cv_select(const float *loss, const int32_t *group, int32_t n_nets, int32_t n_groups,
+                         float *group_mean, int32_t *best, void *stream);
+
 /* ---- networks sharing one dataset --------------------------------------- */
 
 #define MLP_MAX_SHARED_NETS 64

@@ -57,7 +57,8 @@ F_COMPENSATED, F_DETERMINISTIC, F_CHECK_FINITE, F_TANH_HIDDEN = 1, 2, 4, 8   # m
 BARRIER_PROBE_WS_BYTES = 2048   # MLP_BARRIER_PROBE_WS_BYTES
 
 SYMBOLS = ["mlp_workspace_size", "mlp_init", "mlp_destroy", "mlp_forward", "mlp_backward", "mlp_step",
-           "mlp_train", "mlp_predict", "mlp_train_batched", "mlp_eval_batched", "mlp_shared_workspace_size",
+           "mlp_train", "mlp_predict", "mlp_train_batched", "mlp_eval_batched", "mlp_cv_select",
+           "mlp_shared_workspace_size",
            "mlp_train_shared", "mlp_train_shared_static", "mlp_barrier_probe", "mlp_set_momentum", "mlp_dense_forward", "mlp_dense_backward",
            "mlp_update", "mlp_mse_grad", "mlp_deep_train", "mlp_query_status", "mlp_workspace_status",
            "mlp_set_wait_limit", "mlp_mfma_probe", "mlp_set_launch_hint", "mlp_large_plan", "mlp_status_string",
@@ -82,6 +83,7 @@ def _load():
                                       i64, i32, vp, vp]
     lib.mlp_eval_batched.argtypes = [ctypes.POINTER(BatchItem), vp, i32, i32, i32, vp, vp, i64, vp, i64, vp, vp,
                                      vp]
+    lib.mlp_cv_select.argtypes = [vp, vp, i32, i32, vp, vp, vp]
     lib.mlp_shared_workspace_size.argtypes = [ctypes.POINTER(Config), i32, ctypes.POINTER(ctypes.c_size_t)]
     lib.mlp_train_shared.argtypes = [ctypes.POINTER(Config), i32, ctypes.POINTER(f32), vp, vp, vp, vp, i32, vp,
                                      vp, ctypes.c_size_t, vp]

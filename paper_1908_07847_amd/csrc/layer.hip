@@ -345,6 +345,84 @@ hipError_t launch_forward(int64_t n, int D, int H, int K, const float *X, mlp_pa
   return hipGetLastError();
 }
 
+}  // namespace mlph
+
+namespace mlpk {
+
+// Cross-validation selection: one workgroup.  Thread t owns the groups t,
+// t + 1024, ...: for each it walks every net in increasing order (the
+// (loss, group) pairs staged through LDS in chunks, read as broadcasts), so a
+// mean is one fixed-order float32 sum.  Then a (mean, group) minimum over
+// the threads, ties to the lower group.
+constexpr int kSelThreads = 1024;
+constexpr int kSelChunk = 2048;
+__global__ __launch_bounds__(kSelThreads) void k_cv_select(const float *__restrict__ loss,
+                                                         const int32_t *__restrict__ group, int n, int ng,
+                                                         float *__restrict__ mean, int32_t *__restrict__ best) {
+  __shared__ float ls[kSelChunk];
+  __shared__ int32_t gs[kSelChunk];
+  __shared__ float bv[kSelThreads];
+  __shared__ int32_t bi[kSelThreads];
+  const int t = threadIdx.x;
+  float mv = __builtin_inff();
+  int mi = 0x7fffffff;
+  for (int r = 0; r * kSelThreads < ng; ++r) {
+    const int g = t + r * kSelThreads;
+    float sum = 0.0f;
+    int cnt = 0;
+    for (int c0 = 0; c0 < n; c0 += kSelChunk) {
+      const int m = min(kSelChunk, n - c0);
+      __syncthreads();   // the previous chunk is no longer read
+      for (int i = t; i < m; i += kSelThreads) {
+        ls[i] = loss[c0 + i];
+        gs[i] = group[c0 + i];
+      }
+      __syncthreads();
+      if (g < ng)
+        for (int i = 0; i < m; ++i)
+          if (gs[i] == g) {
+            sum += ls[i];
+            cnt += 1;
+          }
+    }
+    if (g < ng) {
+      float v = cnt ? sum / (float)cnt : __builtin_inff();
+      if (!(v < __builtin_inff())) v = __builtin_inff();   // NaN or +inf
+      mean[g] = v;
+      if (v < mv || (v == mv && g < mi)) {
+        mv = v;
+        mi = g;
+      }
+    }
+  }
+  bv[t] = mv;
+  bi[t] = mi;
+  __syncthreads();
+  for (int st = kSelThreads / 2; st > 0; st >>= 1) {
+    if (t < st) {
+      const float v = bv[t + st];
+      const int i = bi[t + st];
+      if (v < bv[t] || (v == bv[t] && i < bi[t])) {
+        bv[t] = v;
+        bi[t] = i;
+      }
+    }
+    __syncthreads();
+  }
+  if (t == 0) best[0] = bi[0] == 0x7fffffff ? 0 : bi[0];
+}
+
+}  // namespace mlpk
+
+namespace mlph {
+
+hipError_t launch_cv_select(const float *loss, const int32_t *group, int n_nets, int n_groups, float *group_mean,
+                            int32_t *best, hipStream_t s) {
+  hipLaunchKernelGGL(mlpk::k_cv_select, dim3(1), dim3(mlpk::kSelThreads), 0, s, loss, group, n_nets, n_groups,
+                     group_mean, best);
+  return hipGetLastError();
+}
+
 hipError_t launch_eval_batched(const mlp_batch_item *items_dev, int n_nets, int D, int K, const float *X,
                                const float *T, const float *theta, float *loss, int32_t *correct, hipStream_t s) {
   hipLaunchKernelGGL(mlpk::k_eval_batched, dim3(n_nets), dim3(256), 0, s, items_dev, D, K, X, T, theta, loss,

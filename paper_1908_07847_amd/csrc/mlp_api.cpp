@@ -389,6 +389,18 @@ mlp_status mlp_eval_batched(const mlp_batch_item *items_host, const mlp_batch_it
   return e == hipSuccess ? MLP_OK : hip_fail(e, "mlp_eval_batched launch");
 }
 
+mlp_status mlp_cv_select(const float *loss, const int32_t *group, int32_t n_nets, int32_t n_groups,
+                         float *group_mean, int32_t *best, void *stream) {
+  if (!loss || !group || !group_mean || !best) return fail(MLP_ERR_ARG, "loss, group, group_mean, best must not be NULL");
+  if (n_nets < 1) return fail(MLP_ERR_SHAPE, "n_nets must be positive");
+  if (n_groups < 1 || n_groups > 65536) return fail(MLP_ERR_SHAPE, "n_groups must be in [1, 65536]");
+  const void *ptrs[] = {loss, group, group_mean, best};
+  for (const void *p : ptrs)
+    if (!aligned4(p)) return fail(MLP_ERR_ALIGN, "loss, group, group_mean, best must be 4-byte aligned");
+  hipError_t e = mlph::launch_cv_select(loss, group, n_nets, n_groups, group_mean, best, (hipStream_t)stream);
+  return e == hipSuccess ? MLP_OK : hip_fail(e, "mlp_cv_select launch");
+}
+
 mlp_status mlp_shared_workspace_size(const mlp_config *cfg, int32_t n_nets, size_t *bytes) {
   mlp_status s = check_config(cfg);
   if (s != MLP_OK) return s;

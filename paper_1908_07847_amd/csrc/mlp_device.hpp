@@ -157,5 +157,7 @@ hipError_t launch_update(int64_t P, float *theta, const float *g, float *comp, f
 hipError_t launch_mse_grad(int64_t n, int k, const float *Y, const float *T, float *dY, float *loss, hipStream_t s);
 hipError_t launch_eval_batched(const mlp_batch_item *items_dev, int n_nets, int D, int K, const float *X,
                                const float *T, const float *theta, float *loss, int32_t *correct, hipStream_t s);
+hipError_t launch_cv_select(const float *loss, const int32_t *group, int n_nets, int n_groups, float *group_mean,
+                            int32_t *best, hipStream_t s);
 
 }  // namespace mlph

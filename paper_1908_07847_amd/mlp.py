@@ -403,6 +403,20 @@ def eval_batched(plan: BatchPlan, X: torch.Tensor, T: torch.Tensor, theta: torch
     return loss[inv], correct[inv]
 
 
+def cv_select(loss: torch.Tensor, group: torch.Tensor, n_groups: int, stream=None):
+    """mlp_cv_select: (group_mean [n_groups], best [1] int32), both on the
+    device -- the mean held-out loss of every group of nets and the group
+    with the lowest one (ties to the lower index)."""
+    if loss.dtype != torch.float32 or group.dtype != torch.int32 or not loss.is_contiguous() or \
+            not group.is_contiguous() or loss.numel() != group.numel():
+        raise ValueError("loss (float32) and group (int32) must be contiguous and of one length")
+    mean = torch.empty(max(int(n_groups), 4), dtype=torch.float32, device=loss.device)[:int(n_groups)]
+    best = torch.empty(4, dtype=torch.int32, device=loss.device)[:1]
+    check(lib.mlp_cv_select(_ptr(loss), _ptr(group), loss.numel(), int(n_groups), _ptr(mean), _ptr(best),
+                            _stream(stream)))
+    return mean, best
+
+
 # ---------------------------------------------------------------- nets sharing one dataset
 def shared_workspace_size(n_in: int, n_hidden: int, n_out: int, n_rows: int, batch: int, n_nets: int,
                           prec: str = "fp32") -> int:

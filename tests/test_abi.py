@@ -268,3 +268,13 @@ def test_large_plan_on_the_host():
     assert L.lib.mlp_large_plan(ctypes.byref(wide_in), 1, 256, out) == L.MLP_ERR_UNSUPPORTED
     odd_batch = L.Config(33, 256, 3, 0, 4096, 48, 0.1, 0)
     assert L.lib.mlp_large_plan(ctypes.byref(odd_batch), 1, 256, out) == L.MLP_ERR_UNSUPPORTED
+
+
+def test_cv_select_rejects_before_touching_the_device():
+    L = _lib()
+    f = L.lib.mlp_cv_select
+    assert f(None, 0x1000, 4, 2, 0x2000, 0x3000, None) == L.MLP_ERR_ARG
+    assert f(0x1000, 0x1000, 0, 2, 0x2000, 0x3000, None) == L.MLP_ERR_SHAPE
+    assert f(0x1000, 0x1000, 4, 0, 0x2000, 0x3000, None) == L.MLP_ERR_SHAPE
+    assert f(0x1000, 0x1000, 4, 65537, 0x2000, 0x3000, None) == L.MLP_ERR_SHAPE
+    assert f(0x1002, 0x1000, 4, 2, 0x2000, 0x3000, None) == L.MLP_ERR_ALIGN

@@ -80,12 +80,60 @@ def test_eval_after_training_and_model_selection(M, cv):
         f"(smallest top-2 gap there {gaps[diff].min() if len(diff) else 0:.1e})")
     assert rel <= 1e-5
     assert np.all(gaps[diff] <= 1e-4)
-    # model selection: mean held-out loss per hyperparameter group (5 folds)
+    # model selection on the device (mlp_cv_select): mean held-out loss per
+    # hyperparameter group (5 folds), the group with the lowest; the oracle's
+    # from its definition
     groups = np.array([it["group"] for it in cv["items_val"]])
-    ng = groups.max() + 1
-    mg = np.bincount(groups, weights=gl, minlength=ng) / np.bincount(groups, minlength=ng)
+    ng = int(groups.max()) + 1
+    mg_d, best_d = M.cv_select(torch.from_numpy(gl.astype(np.float32)).cuda(),
+                               torch.from_numpy(groups.astype(np.int32)).cuda(), ng)
+    mg, best_g = mg_d.cpu().numpy().astype(np.float64), int(best_d.item())
     mo = np.bincount(groups, weights=ol, minlength=ng) / np.bincount(groups, minlength=ng)
-    best_g, best_o = int(np.argmin(mg)), int(np.argmin(mo))
+    best_o = int(np.argmin(mo))
+    assert np.max(np.abs(mg - mo) / mo) <= 1e-5
     second = np.sort(mo)[1]
     say(f"  best group: GPU {best_g}, oracle {best_o} (mean held-out loss {mo[best_o]:.5f}, next {second:.5f})")
     assert best_g == best_o or abs(mo[best_g] - mo[best_o]) <= 1e-5 * mo[best_o]
+
+
+def test_cv_select_against_its_definition(M):
+    """mlp_cv_select on seeded cases: the group means equal the float64 mean
+    of each group's losses (1e-6 relative: one float32 sum), a group without
+    nets and a group holding a NaN loss get +inf, a net with a group index
+    outside the range belongs to none, and the selected group is the lowest
+    index among those with the smallest mean (exact ties built in)."""
+    g = np.random.default_rng(11)
+    for n, ng in [(4096, 820), (1, 1), (5000, 3000), (37, 5)]:
+        loss = g.uniform(0.05, 0.3, n).astype(np.float32)
+        grp = g.integers(0, ng, n).astype(np.int32)
+        if n > 10:
+            grp[3] = ng + 7                      # outside the range: no group
+            grp[4] = -2
+            loss[5] = np.nan                     # its group's mean is +inf
+            empty = (grp[0] + 1) % ng            # a group with no net
+            grp[grp == empty] = grp[0]
+            # an exact tie for the minimum between two groups
+            lo = np.float32(0.01)
+            a, b = sorted(set(range(ng)) - {empty, int(grp[5]), int(grp[0])})[-2:]
+            grp[6], grp[7], grp[8] = a, b, b
+            grp[grp == a] = a
+            keep = np.isin(np.arange(n), [6, 7, 8])
+            grp[(grp == a) & ~keep] = grp[0]
+            grp[(grp == b) & ~keep] = grp[0]
+            loss[6] = loss[7] = loss[8] = lo
+        ref = np.full(ng, np.inf)
+        for k in range(ng):
+            sel = grp == k
+            if sel.any():
+                m = float(np.mean(loss[sel].astype(np.float64)))
+                ref[k] = m if np.isfinite(m) else np.inf
+        mean_d, best_d = M.cv_select(torch.from_numpy(loss).cuda(), torch.from_numpy(grp).cuda(), ng)
+        mean = mean_d.cpu().numpy().astype(np.float64)
+        best = int(best_d.item())
+        fin = np.isfinite(ref)
+        assert np.array_equal(np.isfinite(mean), fin)
+        assert np.max(np.abs(mean[fin] - ref[fin]) / ref[fin]) <= 1e-6
+        assert best == int(np.flatnonzero(mean == mean.min())[0])
+        assert ref[best] == ref.min()
+        if n > 10:
+            assert best == min(a, b) and mean[a] == mean[b]
