@@ -521,6 +521,20 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
     const int rows_here = (int)max((int64_t)0, min((int64_t)RB, m - (int64_t)gi * RB));
     const float dscale = 2.0f / ((float)m * (float)K);
 
+    // ---- the first piece of this step's row block of X: its loads are
+    // issued first, so they are in flight with the W1 slice's (and the e4m3
+    // scale partials') and the staging costs one memory round trip, not two
+    // (33-256-3, same-box A/B: bf16 6.65 -> 6.43 ms per epoch, e4m3 7.39 ->
+    // 7.20, float32 within its noise; the wide e4m3 form 15.91 -> 15.19).
+    // The 8-wave float32 and bf16
+    // instances load it after the W1 slice instead: there the 32 values held
+    // across the slice's staging cost spills (wide bf16 13.55 -> 13.74 ms per
+    // epoch; float32 unchanged).  (Loading it during the previous step's
+    // update keeps them live across the partial sums, which every instance
+    // spills.)
+    constexpr bool kXFirst = NW == 4 || PREC == 2;
+    if (kXFirst) load_x(step, xpre);
+
     // ---- scales of this step (e4m3): W1 from the master, delta1 delayed
     int ew = 0, ed = 0;
     if (PREC == 2) {
@@ -585,11 +599,9 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
         else if (q < (1 + kMaxK) * HB) w2s[q - HB] = bw[u];
       }
     }
-    // ---- this step's row block of X (its first piece): every load of the
-    // piece issued before the first store.  (Loading it during the previous
-    // step's update instead keeps kPre values per thread live across the
-    // partial sums, which the register allocation spills.)
-    load_x(step, xpre);
+    // ---- this step's row block of X (its first piece), loaded at the start
+    // of the step (see there) and stored after the W1 slice.
+    if (!kXFirst) load_x(step, xpre);
     store_x(step, 0, &xpre);
     int cur_piece = 0;   // piece of the row block held in LDS
     auto stage_piece = [&](int pc) {
