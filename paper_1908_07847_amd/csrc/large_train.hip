@@ -533,6 +533,18 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
     // update keeps them live across the partial sums, which every instance
     // spills.)
     constexpr bool kXFirst = NW == 4 || PREC == 2;
+    // e4m3: the amax partials of the previous update (W1) and of the
+    // previous step (delta1), issued ahead of X so the scales' reduction
+    // waits for them alone (loaded at every step, without a branch that
+    // would make the compiler wait for them before X; used after the first).
+    // One workgroup per CU keeps G <= kLT, and a repeated index leaves a
+    // maximum unchanged.
+    float pw = 0.0f, pd = 0.0f;
+    if (PREC == 2) {
+      const int g = min(tid, G - 1), par = step & 1;
+      pw = a.amax[par * G + g];
+      pd = a.amax[2 * G + (par ^ 1) * G + g];
+    }
     if (kXFirst) load_x(step, xpre);
 
     // ---- scales of this step (e4m3): W1 from the master, delta1 delayed
@@ -554,15 +566,12 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
         bound = bound / (float)(8 * m * K);
         ed = e4m3_scale_exp(bound);
       } else {
-        float mw = 0.0f, md = 0.0f;
-        for (int g = tid; g < G; g += kLT) {
-          mw = fmaxf(mw, a.amax[par * G + g]);              // written by the previous update
-          md = fmaxf(md, a.amax[2 * G + (par ^ 1) * G + g]);  // previous step's delta1
+        for (int g = tid + kLT; g < G; g += kLT) {
+          pw = fmaxf(pw, a.amax[par * G + g]);
+          pd = fmaxf(pd, a.amax[2 * G + (par ^ 1) * G + g]);
         }
-        mw = wg_reduce_max(mw, 24);
-        md = wg_reduce_max(md, 32);
-        ew = e4m3_scale_exp(mw);
-        ed = e4m3_scale_exp(md);
+        ew = e4m3_scale_exp(wg_reduce_max(pw, 24));
+        ed = e4m3_scale_exp(wg_reduce_max(pd, 32));
       }
     }
     const float sw = ldexpf(1.0f, ew), isw = ldexpf(1.0f, -ew);
