@@ -418,7 +418,7 @@ def bench_batched(args):
     warmup = args.warmup if args.warmup is not None else 5
     # launch shape of each size group from the autotuner (timed on copies,
     # cached per device and group shape)
-    threads = tune.tune_batched(plan, X, T, th, 33, 3, epochs=20)
+    threads = tune.tune_batched(plan, X, T, th, 33, 3, epochs=100)
     if warmup:
         mlp.train_batched(plan, X, T, th.clone(), torch.zeros_like(th), warmup, 33, 3)
     hist = torch.empty((len(items), steps), device="cuda")
@@ -479,7 +479,8 @@ def bench_batched(args):
                             "(5-fold CV splits), lr~logU(0.01,1), full batch, one launch",
                 "nets": len(items), "total_rows": rows, "step": "one epoch of every net",
                 "threads_per_net": threads,
-                "groups": [{"nets": c, "max_rows": r, "max_hidden": h} for (_, c, r, h) in plan.groups],
+                "groups": [{"nets": c, "max_rows": r, "max_hidden": h, "stream": plan.stream_of[g]}
+                           for g, (_, c, r, h) in enumerate(plan.groups)],
                 "launch": "hipGraph replay of one trainer launch per size group"},
         cv_eval={"kernel": "mlpk::k_eval_batched + mlpk::k_cv_select", "ms": eval_s * 1e3, "heldout_rows": vrows,
                  "rows_per_s": vrows / eval_s, "best_group": best, "best_group_hidden": int(

@@ -278,7 +278,11 @@ class BatchPlan:
     net, so grouping lets the many smaller nets run more workgroups per CU.
     `groups` lists (start, count, max_rows, max_hidden) in plan order, and
     `threads[g]` (0: the library's choice) is the launch shape of group g,
-    set by the autotuner (tune.tune_batched).
+    set by the autotuner (tune.tune_batched).  `stream_of[g]` is the side
+    stream group g is launched on (groups on one stream run one after the
+    other): group g on stream g mod 4 unless the autotuner moved it, as it
+    does with the groups after the fourth, which wait for the group they
+    follow.
     """
 
     def __init__(self, items, device="cuda", order: str = "lpt", buckets: bool = False):
@@ -324,6 +328,7 @@ class BatchPlan:
                                 int(max(it["n_hidden"] for it in sel))))
             start += c
         self.threads = [0] * len(self.groups)
+        self.stream_of = [g % 4 for g in range(len(self.groups))]
         if len(self.groups) > 1:
             self.side_streams = [torch.cuda.Stream(device=device) for _ in range(min(len(self.groups), 4))]
 
@@ -350,7 +355,7 @@ def train_batched(plan: BatchPlan, X: torch.Tensor, T: torch.Tensor, theta: torc
     for j, g in enumerate(todo):
         start, count, _, _ = plan.groups[g]
         threads = plan.threads[g]
-        st = side[j % len(side)] if side else cur
+        st = side[plan.stream_of[g] % len(side)] if side else cur
         if threads:
             set_launch_hint(small_threads=threads)
         try:

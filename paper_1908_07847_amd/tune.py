@@ -6,7 +6,9 @@ Choices tuned through `mlp_set_launch_hint` (include/mlp.h):
     its rows (128, 256 or 512 threads: more waves shorten one net's epoch,
     fewer let more nets share a CU) or its hidden layer (64: one wave per 16
     hidden units, one barrier per epoch and no per-wave partial gradients;
-    best for the wide nets, which then fit three to a CU).
+    best for the wide nets, which then fit three to a CU); and, for a plan
+    of more than four groups, the side stream each group after the fourth
+    follows (the group it waits for).
   * large-N trainer: the Gi x Gj grid (row blocks x hidden blocks) and the
     waves per workgroup (4 or 8).  More row blocks spread the minibatch wider
     but add partial gradients to sum; more hidden blocks shrink each
@@ -150,13 +152,17 @@ def plan_key(n_in: int, plan: "mlp.BatchPlan") -> str:
 def _tune_together(plan, X, T, theta, n_in, n_out, epochs, force):
     """The groups of a plan run concurrently, so a group's best shape alone
     need not be its best in company (a shape whose workgroups need a whole
-    CU's LDS waits for CUs that the other groups keep busy).  One pass of
-    coordinate descent over the groups, each trying every choice with the
-    others fixed, on the time of the whole plan."""
+    CU's LDS waits for CUs that the other groups keep busy).  Coordinate
+    descent on the time of the whole plan: one pass over the groups' shapes
+    (each trying every choice with the others fixed), one over the streams
+    of the groups after the fourth, and, if a group moved, the shapes
+    again."""
     key = plan_key(n_in, plan)
     cached = _load_cache().get(key)
     if cached and not force and len(cached["threads"]) == len(plan.groups):
         plan.threads[:] = [int(t) for t in cached["threads"]]
+        if len(cached.get("streams", [])) == len(plan.groups):
+            plan.stream_of[:] = [int(v) for v in cached["streams"]]
         return list(plan.threads)
 
     def whole():
@@ -165,17 +171,39 @@ def _tune_together(plan, X, T, theta, n_in, n_out, epochs, force):
         return _time(lambda: mlp.train_batched(plan, X, T, th, comp, epochs, n_in, n_out))
 
     best_t = whole()
-    for g in range(len(plan.groups)):
-        keep = plan.threads[g]
-        for t in SMALL_CHOICES:
-            if t == keep:
+
+    def threads_pass():
+        nonlocal best_t
+        for g in range(len(plan.groups)):
+            keep = plan.threads[g]
+            for t in SMALL_CHOICES:
+                if t == keep:
+                    continue
+                plan.threads[g] = t
+                tt = whole()
+                if tt < best_t:
+                    best_t, keep = tt, t
+            plan.threads[g] = keep
+
+    threads_pass()
+    # a group after the fourth waits on its stream for the one before it
+    # there: it should follow one that ends early, which the groups' costs
+    # alone do not tell (a group of large workgroups is starved in company)
+    moved = False
+    for g in range(4, len(plan.groups)):
+        keep = plan.stream_of[g]
+        for v in range(4):
+            if v == keep:
                 continue
-            plan.threads[g] = t
+            plan.stream_of[g] = v
             tt = whole()
             if tt < best_t:
-                best_t, keep = tt, t
-        plan.threads[g] = keep
-    _store(key, {"threads": list(plan.threads), "ms": best_t, "epochs": epochs, "when": time.time()})
+                best_t, keep, moved = tt, v, True
+        plan.stream_of[g] = keep
+    if moved:
+        threads_pass()   # a group's best shape depends on its company
+    _store(key, {"threads": list(plan.threads), "streams": list(plan.stream_of), "ms": best_t, "epochs": epochs,
+                 "when": time.time()})
     return list(plan.threads)
 
 

@@ -352,7 +352,8 @@ def test_epochs_as_library_calls_and_their_graph(M):
 def test_size_grouped_batched_plan_every_net(M, batched_full):
     """A plan grouped by size (one launch per group, each sized for its
     largest net and tuned to its own threads per net) trains every net as
-    the oracle does, and its results do not depend on the run (bitwise)."""
+    the oracle does, and its results depend neither on the run nor on the
+    side stream each group is launched on (bitwise)."""
     from paper_1908_07847_amd import tune
     w = batched_full
     epochs = 25
@@ -364,6 +365,9 @@ def test_size_grouped_batched_plan_every_net(M, batched_full):
     plan.threads[:] = [512, 256, 128, 512, 256, 128][:len(plan.groups)]
     outs = []
     for rep in range(2):
+        # the second run moves every group to another stream (and the groups
+        # after the fourth behind other groups)
+        plan.stream_of[:] = [(g if rep == 0 else 3 - g) % 4 for g in range(len(plan.groups))]
         th = th0.clone()
         hist = torch.empty((len(w["items"]), epochs), device="cuda")
         M.train_batched(plan, X, T, th, torch.zeros_like(th), epochs, 33, 3, loss_hist=hist)

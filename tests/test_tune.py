@@ -32,3 +32,42 @@ def test_cache_round_trip(tune):
     tune._store("k2", {"threads": 256})
     c = tune._load_cache()
     assert c["k"]["grid"] == [64, 4] and c["k2"]["threads"] == 256
+
+
+def test_whole_plan_search_moves_late_groups_and_caches_the_choice(tune, monkeypatch):
+    """The whole-plan pass of the batched autotuner: coordinate descent over
+    each group's launch shape, then over the stream of every group after the
+    fourth, then the shapes again; the choice is cached and re-applied.  The
+    plan's time here is a synthetic function of the choices (no device)."""
+    import torch
+
+    class Plan:
+        groups = [(0, 10, 120, 64), (10, 8, 64, 64), (18, 6, 120, 32), (24, 5, 119, 16), (29, 4, 64, 32),
+                  (33, 3, 64, 16)]
+
+        def __init__(self):
+            self.threads = [64, 64, 64, 512, 512, 256]
+            self.stream_of = [g % 4 for g in range(6)]
+
+    plan = Plan()
+    calls = []
+
+    def fake_time(fn, reps=2):
+        # the plan is fastest with group 4 behind group 2, group 5 behind
+        # group 3, and group 4 at 128 threads once it sits behind group 2
+        t = 100.0 + (0.0 if plan.stream_of[4] == 2 else 7.0) + (0.0 if plan.stream_of[5] == 3 else 3.0)
+        t += 0.0 if (plan.threads[4] == 128) == (plan.stream_of[4] == 2) else 2.0
+        calls.append(t)
+        return t
+
+    monkeypatch.setattr(tune, "_time", fake_time)
+    th = torch.zeros(8)
+    threads = tune._tune_together(plan, None, None, th, 33, 3, 20, force=True)
+    assert plan.stream_of == [0, 1, 2, 3, 2, 3]
+    assert threads == [64, 64, 64, 512, 128, 256] and plan.threads == threads
+    assert min(calls) == 100.0
+    # the cached choice is applied to a fresh plan without timing anything
+    fresh = Plan()
+    calls.clear()
+    assert tune._tune_together(fresh, None, None, th, 33, 3, 20, force=False) == threads
+    assert fresh.stream_of == [0, 1, 2, 3, 2, 3] and not calls
