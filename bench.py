@@ -338,13 +338,11 @@ def bench_large(args):
     for q in forms:
         r = large_form(mlp, torch, w, X, T, q, steps, warmup if q == prec else min(warmup, 1))
         ach = flops_epoch / r["kernel_s"] / 1e12
-        pi = {"fp32": 0, "bf16": 1, "e4m3": 2}[q]
         res_forms[q] = dict(value=N * steps / r["wall"], ms_per_step=r["wall"] * 1e3 / steps,
                             kernel_ms_per_launch=r["kernel_s"] * 1e3,
                             median_ms_per_launch=float(np.median(r["durs"])) * 1e3,
                             min_ms_per_launch=float(min(r["durs"])) * 1e3,
-                            kernel=f"mlpk::k_large_train<{pi}, {3 if K <= 3 else 4}, "
-                                   f"{mlp.large_plan(D, H, K, N, batch=batch, prec=q)['waves']}>",
+                            kernel=mlp.large_plan(D, H, K, N, batch=batch, prec=q)["kernel"],
                             achieved_tflops=ach, peak_tflops=PEAK[q], frac=ach / PEAK[q],
                             final_loss=r["final_loss"], dtype={"fp32": "f32", "bf16": "bf16", "e4m3": "e4m3"}[q])
     head = res_forms[prec]
@@ -551,7 +549,6 @@ def bench_shared(args):
     P = D * H + H + H * K + K
     flops = (flops_per_sample_epoch(D, H, K) * N + 2 * P * (-(-N // batch))) * M * steps
     achieved = flops / kern / 1e12
-    pi = {"fp32": 0, "bf16": 1}[prec]
     res = dict(
         metric="training samples*epochs/s", value=M * N * steps / wall, unit="samples*epochs/s",
         ms_per_step=wall * 1e3 / steps, dtype={"fp32": "f32", "bf16": "bf16"}[prec],
@@ -562,8 +559,7 @@ def bench_shared(args):
         roofline={"bound": "mfma", "achieved": achieved, "peak": PEAK[prec], "unit": "TFLOP/s",
                   "frac": achieved / PEAK[prec], "traffic": measured_traffic(f"w6-{prec}-steps{steps}", "large"),
                   "traffic_unit": "bytes per launch",
-                  "kernel": f"mlpk::k_large_train<{pi}, 3, "
-                            f"{mlp.large_plan(D, H, K, N, batch=batch, prec=prec, n_nets=M)['waves']}>",
+                  "kernel": mlp.large_plan(D, H, K, N, batch=batch, prec=prec, n_nets=M)["kernel"],
                   "kernel_ms": kern * 1e3, "flops_per_launch": flops},
         final_loss_mean=final_loss_mean, repeats={"runs": 1, "median_ms_per_step": wall * 1e3 / steps,
                                                   "min_ms_per_step": wall * 1e3 / steps},

@@ -445,13 +445,15 @@ mlp_status mlp_set_launch_hint(const mlp_launch_hint *hint /*host; NULL resets*/
  * device with n_cu compute units, under the current launch hint: shape[0]
  * the row blocks Gi, shape[1] the hidden blocks Gj (the grid has Gi x n_nets
  * x Gj workgroups, one per CU), shape[2] the waves per workgroup (4 or 8),
- * shape[3] the rows of a block staged in LDS at a time.  The default grid
+ * shape[3] the rows of a block staged in LDS at a time, shape[4] the hidden
+ * tiles of 16 units a wave owns at most (the kernel instance: 1 when a
+ * 4-wave block has at most one tile per wave, else 16 / waves).  The default grid
  * gives one net row blocks of at least 64 rows (32 for nets sharing X) and
  * hidden blocks of 64..256 units, filling the CUs.  Host-only arithmetic (no
  * device call): *cfg and shape are host pointers.  MLP_ERR_ARG for a NULL
  * pointer, n_cu < 1 or n_nets outside 1..64; MLP_ERR_UNSUPPORTED when no
  * grid covers the shape (mlp_last_error says why). */
-mlp_status mlp_large_plan(const mlp_config *cfg, int32_t n_nets, int32_t n_cu, int32_t shape[4]);
+mlp_status mlp_large_plan(const mlp_config *cfg, int32_t n_nets, int32_t n_cu, int32_t shape[5]);
 
 const char *mlp_status_string(mlp_status s);
 const char *mlp_last_error(void);

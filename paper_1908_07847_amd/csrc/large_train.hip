@@ -301,11 +301,15 @@ struct LLayout {
 
 // KO: outputs the loops run over (K <= KO <= kMaxK; 3 for the usual K = 3).
 // NW: waves per workgroup, 4 (one per SIMD) or 8 (two per SIMD, so one
-// wave's matrix-core work overlaps the other's vector work); a wave owns at
-// most NHM = 16 / NW hidden tiles (hidden blocks of at most 256 units).
-template <int PREC, int KO, int NW>
+// wave's matrix-core work overlaps the other's vector work).  NHM: hidden
+// tiles a wave owns at most, 16 / NW for hidden blocks of up to 256 units,
+// or 1 for blocks of at most NW tiles (the loops over a wave's tiles then
+// hold one tile: a step's code is far smaller, and fits the instruction
+// cache that two CUs share, which the general instance's does not).
+template <int PREC, int KO, int NW, int NHM>
 __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
-  constexpr int kNW = NW, kLT = 64 * NW, NHM = 16 / NW;
+  static_assert(NHM >= 1 && NHM <= 16 / NW, "tiles per wave");
+  constexpr int kNW = NW, kLT = 64 * NW;
   using O = Ops<PREC>;
   using E = typename O::elem;
   constexpr int XROW = O::XROW;
@@ -1551,7 +1555,9 @@ void set_large_grid_hint(int row_blocks, int hidden_blocks, int waves) {
 
 void set_wait_limit_us(int64_t us) { g_wait_us = us < 0 ? kDefaultWaitUs : us; }
 
-mlp_status large_plan(const mlp_config &c, int n_nets, int n_cu, int shape[4], std::string *err) {
+static int tiles_per_wave(const Plan &pl);
+
+mlp_status large_plan(const mlp_config &c, int n_nets, int n_cu, int shape[5], std::string *err) {
   if (c.n_in > mlpk::kMaxD || c.n_out > mlpk::kMaxK) {
     *err = "large-N training covers n_in <= 64 and n_out <= 4";
     return MLP_ERR_UNSUPPORTED;
@@ -1570,19 +1576,30 @@ mlp_status large_plan(const mlp_config &c, int n_nets, int n_cu, int shape[4], s
   shape[1] = pl.Gj;
   shape[2] = pl.nw;
   shape[3] = pl.RBP;
+  shape[4] = tiles_per_wave(pl);
   return MLP_OK;
 }
 
-// The kernel instance: operand type, output count (3 or 4), waves.
-template <int NW>
+// The kernel instance: operand type, output count (3 or 4), waves, tiles
+// per wave.
+template <int NW, int NHM>
 static const void *kernel_nw(int prec, bool k3) {
   using namespace mlpk;
-  if (prec == MLP_FP32) return k3 ? (const void *)k_large_train<0, 3, NW> : (const void *)k_large_train<0, 4, NW>;
-  if (prec == MLP_BF16) return k3 ? (const void *)k_large_train<1, 3, NW> : (const void *)k_large_train<1, 4, NW>;
-  return k3 ? (const void *)k_large_train<2, 3, NW> : (const void *)k_large_train<2, 4, NW>;
+  if (prec == MLP_FP32)
+    return k3 ? (const void *)k_large_train<0, 3, NW, NHM> : (const void *)k_large_train<0, 4, NW, NHM>;
+  if (prec == MLP_BF16)
+    return k3 ? (const void *)k_large_train<1, 3, NW, NHM> : (const void *)k_large_train<1, 4, NW, NHM>;
+  return k3 ? (const void *)k_large_train<2, 3, NW, NHM> : (const void *)k_large_train<2, 4, NW, NHM>;
 }
-static const void *kernel_for(int prec, bool k3, int nw) {
-  return nw == 8 ? kernel_nw<8>(prec, k3) : kernel_nw<4>(prec, k3);
+// tiles per wave of a plan: one when the hidden block has at most one
+// 16-unit tile per wave (4 waves), else 16 / waves
+static int tiles_per_wave(const Plan &pl) {
+  const int nt = pl.Hp / pl.Gj / 16;
+  return (pl.nw == 4 && nt <= 4) ? 1 : 16 / pl.nw;
+}
+static const void *kernel_for(int prec, bool k3, const Plan &pl) {
+  if (pl.nw == 8) return kernel_nw<8, 2>(prec, k3);
+  return tiles_per_wave(pl) == 1 ? kernel_nw<4, 1>(prec, k3) : kernel_nw<4, 4>(prec, k3);
 }
 
 mlp_status large_workspace_bytes(const mlp_config &c, int n_nets, size_t *bytes) {
@@ -1674,7 +1691,7 @@ mlp_status large_train(const mlp_config &c, int n_nets, const float *lrs, const 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) { *err = hipGetErrorString(e); return MLP_ERR_HIP; }
 
-  const void *kern = kernel_for(c.prec, c.n_out <= 3, pl.nw);
+  const void *kern = kernel_for(c.prec, c.n_out <= 3, pl);
   e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.lds);
   if (e != hipSuccess) { *err = std::string("hipFuncSetAttribute: ") + hipGetErrorString(e); return MLP_ERR_HIP; }
   int per_cu = 0;

@@ -133,16 +133,16 @@ mlp_status mlp_set_launch_hint(const mlp_launch_hint *hint) {
   return MLP_OK;
 }
 
-mlp_status mlp_large_plan(const mlp_config *cfg, int32_t n_nets, int32_t n_cu, int32_t shape[4]) {
+mlp_status mlp_large_plan(const mlp_config *cfg, int32_t n_nets, int32_t n_cu, int32_t shape[5]) {
   mlp_status s = check_config(cfg);
   if (s != MLP_OK) return s;
   if (!shape) return fail(MLP_ERR_ARG, "shape is NULL");
   if (n_cu < 1) return fail(MLP_ERR_ARG, "n_cu must be >= 1");
   if (n_nets < 1 || n_nets > MLP_MAX_SHARED_NETS) return fail(MLP_ERR_ARG, "n_nets must be in 1..%d", MLP_MAX_SHARED_NETS);
-  int out[4] = {0, 0, 0, 0};
+  int out[5] = {0, 0, 0, 0, 0};
   s = mlph::large_plan(*cfg, n_nets, n_cu, out, &g_last_error);
   if (s != MLP_OK) return s;
-  for (int i = 0; i < 4; ++i) shape[i] = out[i];
+  for (int i = 0; i < 5; ++i) shape[i] = out[i];
   return MLP_OK;
 }
 

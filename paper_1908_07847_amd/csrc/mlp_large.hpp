@@ -14,7 +14,7 @@ mlp_status large_workspace_bytes(const mlp_config &cfg, int n_nets, size_t *byte
 
 // The plan the trainer would launch for n_nets nets of shape cfg on n_cu
 // CUs: {Gi, Gj, waves, rows staged per piece}.
-mlp_status large_plan(const mlp_config &cfg, int n_nets, int n_cu, int shape[4], std::string *err);
+mlp_status large_plan(const mlp_config &cfg, int n_nets, int n_cu, int shape[5], std::string *err);
 
 // Launch hint for the Gi x Gj grid (0, 0: automatic) and the waves per
 // workgroup (0: automatic, else 4 or 8).

@@ -458,13 +458,17 @@ def large_plan(n_in: int, n_hidden: int, n_out: int, n_rows: int, *, batch: int 
                n_nets: int = 1, n_cu: int | None = None) -> dict:
     """The launch shape of the large-N trainer for this shape (host-side
     query, no device call unless n_cu is None): row blocks, hidden blocks,
-    waves per workgroup and rows staged per piece."""
+    waves per workgroup, rows staged per piece, hidden tiles per wave, and
+    the name of the kernel instance it launches."""
     if n_cu is None:
         n_cu = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
     cfg = Config(int(n_in), int(n_hidden), int(n_out), _lib.PREC[prec], int(n_rows), int(batch), 0.1, 0)
-    out = (ctypes.c_int32 * 4)()
+    out = (ctypes.c_int32 * 5)()
     check(lib.mlp_large_plan(ctypes.byref(cfg), int(n_nets), int(n_cu), out))
-    return {"row_blocks": out[0], "hidden_blocks": out[1], "waves": out[2], "piece_rows": out[3]}
+    pi = {"fp32": 0, "bf16": 1, "e4m3": 2}[prec]
+    return {"row_blocks": out[0], "hidden_blocks": out[1], "waves": out[2], "piece_rows": out[3],
+            "tiles_per_wave": out[4],
+            "kernel": f"mlpk::k_large_train<{pi}, {3 if n_out <= 3 else 4}, {out[2]}, {out[4]}>"}
 
 
 def set_launch_hint(small_threads: int = 0, large_grid: tuple[int, int] | None = None, large_waves: int = 0) -> None:

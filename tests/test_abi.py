@@ -247,9 +247,19 @@ def test_large_plan_on_the_host():
     from paper_1908_07847_amd import mlp
     L = _lib()
     assert mlp.large_plan(64, 1024, 3, 4194304, batch=16384, n_cu=256) == \
-        {"row_blocks": 64, "hidden_blocks": 4, "waves": 8, "piece_rows": 256}
+        {"row_blocks": 64, "hidden_blocks": 4, "waves": 8, "piece_rows": 256, "tiles_per_wave": 2,
+         "kernel": "mlpk::k_large_train<0, 3, 8, 2>"}
     p = mlp.large_plan(33, 256, 3, 1048576, batch=4096, prec="bf16", n_cu=256)
-    assert (p["row_blocks"], p["hidden_blocks"], p["waves"]) == (64, 4, 4)
+    assert (p["row_blocks"], p["hidden_blocks"], p["waves"], p["tiles_per_wave"]) == (64, 4, 4, 1)
+    assert p["kernel"] == "mlpk::k_large_train<1, 3, 4, 1>"
+    # a 4-wave block of more than four tiles (here by a launch hint) takes the
+    # general instance
+    mlp.set_launch_hint(large_grid=(64, 2), large_waves=4)
+    try:
+        big = mlp.large_plan(33, 256, 4, 1048576, batch=4096, n_cu=256)
+        assert (big["waves"], big["tiles_per_wave"], big["kernel"]) == (4, 4, "mlpk::k_large_train<0, 4, 4, 4>")
+    finally:
+        mlp.reset_launch_hint()
     q = mlp.large_plan(64, 1024, 3, 4194304, batch=16384, n_nets=64, n_cu=256)
     assert q["row_blocks"] * 64 * q["hidden_blocks"] <= 256
     mlp.set_launch_hint(large_grid=(128, 2), large_waves=8)
@@ -258,7 +268,7 @@ def test_large_plan_on_the_host():
         assert (r["row_blocks"], r["hidden_blocks"], r["waves"]) == (128, 2, 8)
     finally:
         mlp.reset_launch_hint()
-    out = (ctypes.c_int32 * 4)()
+    out = (ctypes.c_int32 * 5)()
     c = L.Config(64, 1024, 3, 0, 4194304, 16384, 0.1, 0)
     assert L.lib.mlp_large_plan(None, 1, 256, out) == L.MLP_ERR_ARG
     assert L.lib.mlp_large_plan(ctypes.byref(c), 1, 256, None) == L.MLP_ERR_ARG
