@@ -416,7 +416,7 @@ def bench_batched(args):
     warmup = args.warmup if args.warmup is not None else 5
     # launch shape of each size group from the autotuner (timed on copies,
     # cached per device and group shape)
-    threads = tune.tune_batched(plan, X, T, th, 33, 3, epochs=100)
+    threads = tune.tune_batched(plan, X, T, th, 33, 3, epochs=100, plan_epochs=500)
     if warmup:
         mlp.train_batched(plan, X, T, th.clone(), torch.zeros_like(th), warmup, 33, 3)
     hist = torch.empty((len(items), steps), device="cuda")

@@ -116,10 +116,12 @@ def _time(fn, reps: int = 2) -> float:
 
 
 def tune_batched(plan: "mlp.BatchPlan", X, T, theta, n_in: int, n_out: int, epochs: int = 20,
-                 force: bool = False) -> list:
+                 force: bool = False, plan_epochs: int | None = None) -> list:
     """Pick threads per net for each group of the plan (mlp_train_batched
     launches; theta is not modified: candidates train copies), store them in
-    plan.threads and return them."""
+    plan.threads and return them.  Each group alone is timed for `epochs`
+    epochs, the whole plan for `plan_epochs` (default `epochs`): plans that
+    differ by a percent or two need the longer run to be told apart."""
     chosen = []
     for g, (start, count, max_rows, max_hidden) in enumerate(plan.groups):
         key = small_key(n_in, max_rows, max_hidden, count)
@@ -140,7 +142,7 @@ def tune_batched(plan: "mlp.BatchPlan", X, T, theta, n_in: int, n_out: int, epoc
         chosen.append(best)
     plan.threads[:] = chosen
     if len(plan.groups) > 1:
-        chosen = _tune_together(plan, X, T, theta, n_in, n_out, epochs, force)
+        chosen = _tune_together(plan, X, T, theta, n_in, n_out, plan_epochs or epochs, force)
     return chosen
 
 
