@@ -59,6 +59,7 @@ struct LargeArgs {
   float *lossp;      // [Gi][M] partial squared errors
   float *amax;       // [2][G] W1 amax partials, [2][G] delta1 amax partials, [G] |X|
   float *acc;        // [M]: epoch loss accumulators
+  unsigned short *w1h;  // [P] bf16 copy of theta written by each update (bf16 operands, one net), else null
   unsigned *bar;     // grid-barrier counters and status words (see GridSync)
   uint64_t wait_limit;  // wall-clock ticks a grid-barrier wait may take
   int64_t N, b;
@@ -529,14 +530,14 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
     // issued first, so they are in flight with the W1 slice's (and the e4m3
     // scale partials') and the staging costs one memory round trip, not two
     // (33-256-3, same-box A/B: bf16 6.65 -> 6.43 ms per epoch, e4m3 7.39 ->
-    // 7.20, float32 within its noise; the wide e4m3 form 15.91 -> 15.19).
-    // The 8-wave float32 and bf16
-    // instances load it after the W1 slice instead: there the 32 values held
-    // across the slice's staging cost spills (wide bf16 13.55 -> 13.74 ms per
-    // epoch; float32 unchanged).  (Loading it during the previous step's
+    // 7.20, float32 within its noise; the wide e4m3 form 15.91 -> 15.19; the
+    // wide bf16 form, once its W1 slice comes from the bf16 copy, 12.84 ->
+    // 12.77).  The 8-wave float32 instance loads it after the W1 slice
+    // instead: there the 32 values held across the slice's two batches of
+    // float loads cost spills.  (Loading it during the previous step's
     // update keeps them live across the partial sums, which every instance
     // spills.)
-    constexpr bool kXFirst = NW == 4 || PREC == 2;
+    constexpr bool kXFirst = NW == 4 || PREC != 0;
     // e4m3: the amax partials of the previous update (W1) and of the
     // previous step (delta1), issued ahead of X so the scales' reduction
     // waits for them alone (loaded at every step, without a branch that
@@ -597,14 +598,62 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
         bw[u] = load_if(th + (k < 0 ? oB1 + h : oW2 + (int64_t)k * H + h), th, ok);
       }
       const int hv = max(0, min(HB, H - gj * HB));          // real hidden units here
-      const float *w1src = th + (int64_t)gj * HB * D;
-      stage_flat<kStageU, kLT>(w1src, hv * D, tid, [&](int q, float v) {
-        const int hl = div_by(q, mdD), c = q - hl * D;
-        const int o = hl * XROW + c;
-        if (PREC == 0) reinterpret_cast<float *>(w1s)[o] = v;
-        if (PREC == 1) reinterpret_cast<__bf16 *>(w1s)[o] = (__bf16)v;
-        if (PREC == 2) reinterpret_cast<uint8_t *>(w1s)[o] = e4m3_byte(v * sw);
-      });
+      if (PREC == 1 && a.w1h != nullptr && step > 0) {
+        // bf16, one net, after the first step of the launch: the slice of
+        // the bf16 copy of W1 that the previous update wrote (the rounding
+        // below, done once per parameter instead of once per workgroup):
+        // half the bytes, and with D a multiple of 8 eight values per
+        // 16-byte load, so the whole slice is one batch of loads
+        const unsigned short *hsrc = a.w1h + (int64_t)gj * HB * D;
+        const int n = hv * D;
+        int tid_o = tid;
+        asm volatile("" : "+v"(tid_o));   // addresses formed per step (see the X staging)
+        if ((D & 7) == 0) {
+          constexpr int kV = 4;   // a 256 x 64 slice on 8 waves, a 128 x 64 one on 4
+          for (int base = 0; base < n; base += 8 * kV * kLT) {
+            uint4 v[kV];
+#pragma unroll
+            for (int u = 0; u < kV; ++u) {
+              const int q = base + 8 * (u * kLT + tid_o);
+              v[u] = *reinterpret_cast<const uint4 *>(hsrc + (q < n ? q : 0));
+            }
+#pragma unroll
+            for (int u = 0; u < kV; ++u) {
+              const int q = base + 8 * (u * kLT + tid_o);
+              if (q < n) {
+                const int hl = div_by(q, mdD), c = q - hl * D;   // the 8 values share row hl
+                *reinterpret_cast<uint4 *>(reinterpret_cast<unsigned short *>(w1s) + hl * XROW + c) = v[u];
+              }
+            }
+          }
+        } else {
+          for (int base = 0; base < n; base += kStageU * kLT) {
+            unsigned short v[kStageU];
+#pragma unroll
+            for (int u = 0; u < kStageU; ++u) {
+              const int q = base + u * kLT + tid_o;
+              v[u] = hsrc[q < n ? q : 0];
+            }
+#pragma unroll
+            for (int u = 0; u < kStageU; ++u) {
+              const int q = base + u * kLT + tid_o;
+              if (q < n) {
+                const int hl = div_by(q, mdD), c = q - hl * D;
+                reinterpret_cast<unsigned short *>(w1s)[hl * XROW + c] = v[u];
+              }
+            }
+          }
+        }
+      } else {
+        const float *w1src = th + (int64_t)gj * HB * D;
+        stage_flat<kStageU, kLT>(w1src, hv * D, tid, [&](int q, float v) {
+          const int hl = div_by(q, mdD), c = q - hl * D;
+          const int o = hl * XROW + c;
+          if (PREC == 0) reinterpret_cast<float *>(w1s)[o] = v;
+          if (PREC == 1) reinterpret_cast<__bf16 *>(w1s)[o] = (__bf16)v;
+          if (PREC == 2) reinterpret_cast<uint8_t *>(w1s)[o] = e4m3_byte(v * sw);
+        });
+      }
 #pragma unroll
       for (int u = 0; u < kBW; ++u) {
         const int q = tid + u * kLT;
@@ -1215,6 +1264,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
         const float lr = a.M == 1 ? a.lr[0] : a.lr[(int)(p / P)];
         gd_update(w, c, lr, gsum, a.comp != nullptr);
         a.theta[p] = w;
+        if (PREC == 1 && a.w1h != nullptr) reinterpret_cast<__bf16 *>(a.w1h)[p] = (__bf16)w;
         if (a.comp) a.comp[p] = c;
         if (p < oB1) wmax = fmaxf(wmax, fabsf(w));
       };
@@ -1476,7 +1526,7 @@ int min_hidden_blocks(int H) {
 // status words come first, so the status of the last launch sits at a fixed
 // place (mlp_workspace_status reads it).
 struct WsLayout {
-  size_t bar, z2p, gp, lossp, amax, acc, total;
+  size_t bar, z2p, gp, lossp, amax, acc, w1h, total;
 };
 
 WsLayout ws_layout(const mlp_config &c, int M, int Gi, int Gj) {
@@ -1493,6 +1543,9 @@ WsLayout ws_layout(const mlp_config &c, int M, int Gi, int Gj) {
   w.lossp = o; o += up(sizeof(float) * (size_t)Gi * M);
   w.amax = o; o += up(sizeof(float) * (size_t)5 * Gi * M * Gj);
   w.acc = o; o += up(sizeof(float) * (size_t)(M + 4));
+  // bf16 operands, one net: the bf16 copy of the parameters the update writes
+  w.w1h = 0;
+  if (c.prec == MLP_BF16 && M == 1) { w.w1h = o; o += up(sizeof(unsigned short) * (size_t)P); }
   w.total = o;
   return w;
 }
@@ -1669,6 +1722,7 @@ mlp_status large_train(const mlp_config &c, int n_nets, const float *lrs, const 
   a.lossp = reinterpret_cast<float *>(w + wl.lossp);
   a.amax = reinterpret_cast<float *>(w + wl.amax);
   a.acc = reinterpret_cast<float *>(w + wl.acc);
+  a.w1h = wl.w1h ? reinterpret_cast<unsigned short *>(w + wl.w1h) : nullptr;
   a.bar = reinterpret_cast<unsigned *>(w + wl.bar);
   a.N = c.n_rows;
   a.b = b;

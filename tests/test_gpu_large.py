@@ -103,6 +103,28 @@ def test_large_runs_are_bitwise_repeatable_and_resumable(M):
     assert np.array_equal(np.concatenate([h1, h2]), ha)
 
 
+@pytest.mark.parametrize("d,h,batch", [(64, 1024, 16384), (33, 256, 4096)])
+def test_bf16_w1_copy_equals_staging_from_theta(M, d, h, batch):
+    """bf16 operands, one net: after a launch's first step the W1 slice is
+    staged from the bf16 copy the update wrote, not from theta.  One launch of
+    three one-step epochs (steps 1 and 2 read the copy) equals three one-epoch
+    launches (every step the first of its launch, staged from theta), bitwise;
+    64 features take the 16-byte path, 33 the per-value one."""
+    g = np.random.default_rng(d * 7 + h)
+    X = g.standard_normal((batch, d)).astype(np.float32)
+    T = np.eye(3, dtype=np.float32)[g.integers(0, 3, batch)]
+    th = synth.theta0(d, h, 3, g)
+    Xd, Td = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+    say(f"bf16 W1 copy d={d} h={h} batch={batch}")
+    one = M.Net(d, h, 3, batch, batch=batch, prec="bf16", theta=th)
+    h_one = one.train(Xd, Td, 3).cpu().numpy()
+    many = M.Net(d, h, 3, batch, batch=batch, prec="bf16", theta=th)
+    h_many = np.concatenate([many.train(Xd, Td, 1).cpu().numpy() for _ in range(3)])
+    assert np.array_equal(one.flat.cpu().numpy(), many.flat.cpu().numpy())
+    assert np.array_equal(h_one, h_many)
+    assert not np.array_equal(one.flat.cpu().numpy(), th.packed())
+
+
 def test_large_lr_zero_leaves_parameters_bitwise(M):
     w = synth.single(4, n_rows=2 * 4096)
     _, flat, _ = gpu_train(M, w["X"], w["T"], w["theta"], 2, 4096, lr=0.0)
