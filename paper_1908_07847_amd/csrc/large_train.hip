@@ -530,14 +530,12 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
     // issued first, so they are in flight with the W1 slice's (and the e4m3
     // scale partials') and the staging costs one memory round trip, not two
     // (33-256-3, same-box A/B: bf16 6.65 -> 6.43 ms per epoch, e4m3 7.39 ->
-    // 7.20, float32 within its noise; the wide e4m3 form 15.91 -> 15.19; the
-    // wide bf16 form, once its W1 slice comes from the bf16 copy, 12.84 ->
-    // 12.77).  The 8-wave float32 instance loads it after the W1 slice
-    // instead: there the 32 values held across the slice's two batches of
-    // float loads cost spills.  (Loading it during the previous step's
-    // update keeps them live across the partial sums, which every instance
-    // spills.)
-    constexpr bool kXFirst = NW == 4 || PREC != 0;
+    // 7.20; the wide e4m3 form 15.91 -> 15.19; the wide bf16 form, once its
+    // W1 slice comes from the bf16 copy, 12.84 -> 12.77; the wide float32
+    // form, once its slice is one batch of 16-byte loads, 25.03 -> 24.77).
+    // (Loading it during the previous step's update keeps the values live
+    // across the partial sums, which every instance spills.)
+    //
     // e4m3: the amax partials of the previous update (W1) and of the
     // previous step (delta1), issued ahead of X so the scales' reduction
     // waits for them alone (loaded at every step, without a branch that
@@ -550,7 +548,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
       pw = a.amax[par * G + g];
       pd = a.amax[2 * G + (par ^ 1) * G + g];
     }
-    if (kXFirst) load_x(step, xpre);
+    load_x(step, xpre);
 
     // ---- scales of this step (e4m3): W1 from the master, delta1 delayed
     int ew = 0, ed = 0;
@@ -644,6 +642,34 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
             }
           }
         }
+      } else if (PREC == 0 && (D & 3) == 0 && (reinterpret_cast<uintptr_t>(th) & 15) == 0) {
+        // float32 with D a multiple of 4 (and theta 16-byte aligned): four
+        // values (of one row) per 16-byte load, the whole slice in one batch
+        // of at most eight loads per thread (a 256 x 64 slice on 8 waves),
+        // and two 8-byte LDS stores
+        const float *w1src = th + (int64_t)gj * HB * D;
+        const int n = hv * D;
+        int tid_o = tid;
+        asm volatile("" : "+v"(tid_o));   // addresses formed per step (see the X staging)
+        constexpr int kV = 8;
+        for (int base = 0; base < n; base += 4 * kV * kLT) {
+          float4 v[kV];
+#pragma unroll
+          for (int u = 0; u < kV; ++u) {
+            const int q = base + 4 * (u * kLT + tid_o);
+            v[u] = *reinterpret_cast<const float4 *>(w1src + (q < n ? q : 0));
+          }
+#pragma unroll
+          for (int u = 0; u < kV; ++u) {
+            const int q = base + 4 * (u * kLT + tid_o);
+            if (q < n) {
+              const int hl = div_by(q, mdD), c = q - hl * D;
+              float2 *d = reinterpret_cast<float2 *>(reinterpret_cast<float *>(w1s) + hl * XROW + c);
+              d[0] = float2{v[u].x, v[u].y};
+              d[1] = float2{v[u].z, v[u].w};
+            }
+          }
+        }
       } else {
         const float *w1src = th + (int64_t)gj * HB * D;
         stage_flat<kStageU, kLT>(w1src, hv * D, tid, [&](int q, float v) {
@@ -663,7 +689,6 @@ __global__ __launch_bounds__(64 * NW, 1) void k_large_train(LargeArgs a) {
     }
     // ---- this step's row block of X (its first piece), loaded at the start
     // of the step (see there) and stored after the W1 slice.
-    if (!kXFirst) load_x(step, xpre);
     store_x(step, 0, &xpre);
     int cur_piece = 0;   // piece of the row block held in LDS
     auto stage_piece = [&](int pc) {
